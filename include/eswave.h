@@ -1,0 +1,174 @@
+/*
+ * eswave.h -- C ABI of the MI355X (gfx950) wavelet Sobolev-embedding / Matern-prior library.
+ *
+ * Paper: Kultima, Ramlau, Sahlstrom, Tarvainen, "Fast reconstruction approaches for
+ * photoacoustic tomography with smoothing Sobolev/Matern priors", arXiv 2507.02401.
+ *
+ * The library applies, on the GPU and in FP32, the wavelet realisation of the adjoint
+ * Sobolev embedding of Sec. 4 (Prop. 4.2, the per-level weight rule and the block
+ * diagonal D, and the closing formula E_s^* X = W^{-1}(D (W X))):
+ *
+ *   W      periodic orthonormal Daubechies (dbN, L = 2N taps, extremal phase) DWT of depth m,
+ *          separable over 1, 2 or 3 axes (Mallat's isotropic pyramid, Sec. 4 / Def. 4.1);
+ *   D_tau  diagonal, weight 1 on the approximation band and 2^{-tau s (m-i)} on every detail
+ *          band of level i (1 = finest, m = coarsest).
+ *
+ *   es_adjoint(x)        = D_s W x           E_s^* in orthonormal coordinates of H^s
+ *   es_apply(c)          = W^T D_s c         E_s, its Euclidean adjoint
+ *   matern_cov_apply(x)  = W^T D_{2s} W x    = E_s E_s^*: the paper's pixel-space E_s^*; with
+ *                                            s = nu + d/2 the Matern covariance of Prop. 3.2
+ *                                            up to its constant (dropped, Remark 3.3)
+ *   matern_sample(xi)    = W^T D_s W xi      symmetric square root of the covariance; applied to
+ *                                            white noise it draws a prior sample (Sec. 3, the
+ *                                            Gaussian prior of the MAP estimate)
+ *
+ * Data layout.  Every array is FP32, contiguous, row-major (last axis fastest).  A call
+ * processes `batch` independent instances of the same geometry stored back to back
+ * (instance b starts at element b * prod(shape)).  Coefficient arrays use the packed
+ * pyramid layout: same shape as the image; after m levels the approximation occupies
+ * [0, n_k/2^m) on every axis k and the detail band of level i with high-pass pattern
+ * eps in {0,1}^d \ {0} occupies [eps_k n_k/2^i, (eps_k+1) n_k/2^i) on axis k.
+ * The 1-D step is the periodic correlation a[k] = sum_t h[t] x[(2k+t) mod n],
+ * d[k] = sum_t g[t] x[(2k+t) mod n], g[t] = (-1)^t h[L-1-t].
+ *
+ * Arguments shared by the operator entry points:
+ *   ndim     1, 2 or 3.
+ *   shape    host array of ndim sides; every side must be divisible by 2^levels and
+ *            at least 2^levels (non-square grids allowed).
+ *   batch    number of instances (>= 0; 0 is a no-op).
+ *   order    Daubechies order N in 1..8 (1 = Haar).
+ *   levels   depth m >= 0 (0 gives the identity); at most 30.
+ *   s        smoothness, finite, any sign (s < 0 gives the inverse operators' weights).
+ *   in/out   device pointers, 16-byte aligned, batch*prod(shape) floats each, caller-owned,
+ *            must not overlap.
+ *   ws       device workspace of at least es_workspace_bytes(...) bytes, 256-byte aligned
+ *            (may be NULL when that size is 0); caller-owned, contents undefined on return.
+ *   stream   hipStream_t to launch on (NULL = default stream).  Launches are asynchronous.
+ *
+ * Errors.  Every entry point returns an es_status, never throws and never aborts.  All
+ * arguments are validated on the host before any device call; on a non-OK status no
+ * work was enqueued (except ES_EDEVICE, reported by the HIP runtime at launch).
+ * es_last_error() returns a thread-local message for the last non-OK status.
+ * Thread safety: entry points may be called concurrently from several threads.
+ */
+#ifndef ESWAVE_H
+#define ESWAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ES_OK = 0,
+  ES_EINVAL = 1,       /* bad argument: ndim, shape, order, levels, s, pointer, overlap, alignment */
+  ES_EWORKSPACE = 2,   /* workspace missing or smaller than es_workspace_bytes()                     */
+  ES_EUNSUPPORTED = 3, /* valid request this build cannot run (e.g. no gfx950 device)               */
+  ES_EDEVICE = 4,      /* HIP runtime error; message from hipGetErrorString in es_last_error()      */
+  ES_ENOMEM = 5        /* host or device allocation failed (plan API only)                          */
+} es_status;
+
+typedef enum { ES_OP_ADJOINT = 0, ES_OP_APPLY = 1, ES_OP_COV = 2, ES_OP_SAMPLE = 3 } es_op;
+
+/* ---- single-geometry entry points (uniform batch) ------------------------------------- */
+
+/* E_s^* in wavelet coordinates: coeff = D_s W x (Sec. 4, Prop. 4.2 and the weight rule). */
+es_status es_adjoint(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                     const float* x, float* coeff, void* ws, size_t ws_bytes, void* stream);
+
+/* E_s = (E_s^*)^T: x = W^T D_s coeff (exact transpose of es_adjoint). */
+es_status es_apply(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                   const float* coeff, float* x, void* ws, size_t ws_bytes, void* stream);
+
+/* y = W^T D_{2s} W x: the paper's pixel-space E_s^* (Sec. 4, closing formula). */
+es_status matern_cov_apply(int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                           double s, const float* x, float* y, void* ws, size_t ws_bytes, void* stream);
+
+/* x = W^T D_s W xi: symmetric square root of matern_cov_apply (prior sampling). */
+es_status matern_sample(int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                        double s, const float* xi, float* x, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes the four entry points above need for this geometry and op (es_op). */
+size_t es_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels, int op);
+
+/* Reference variant of the four operators: one launch per 1-D pass per level per instance
+ * (no fusion across axes or levels), for comparison against the fused path.  Same
+ * arguments and results; needs es_workspace_bytes_plain(...) bytes of workspace. */
+es_status es_plain_apply_op(int op, int ndim, const int64_t* shape, int64_t batch, int order,
+                            int levels, double s, const float* in, float* out, void* ws,
+                            size_t ws_bytes, void* stream);
+size_t es_workspace_bytes_plain(int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                                int op);
+
+/* ---- ragged batches: many geometries in one captured launch sequence ------------------ */
+
+typedef struct {
+  int32_t ndim;
+  int32_t order;
+  int64_t shape[3];
+  int32_t levels;
+  int32_t reserved;
+  double s;
+} es_desc;
+
+typedef struct es_plan es_plan;
+
+/* Builds a plan for `count` instances (descs is a host array) of one op.  The plan owns its
+ * device descriptor tables and a hipGraph of the whole launch sequence; the graph is
+ * instantiated on the first es_plan_execute.  Returns ES_ENOMEM if allocation fails. */
+es_status es_plan_create(const es_desc* descs, int32_t count, int op, void* stream, es_plan** out);
+
+/* Runs the plan: in[i] / out[i] (host arrays of device pointers) are instance i's input and
+ * output.  When the pointers equal those of the previous call the captured graph is
+ * replayed as is; otherwise the descriptor table is refreshed first. */
+es_status es_plan_execute(es_plan* plan, const float* const* in, float* const* out, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Same as es_plan_execute but launches kernel by kernel without the graph (for comparison). */
+es_status es_plan_execute_eager(es_plan* plan, const float* const* in, float* const* out, void* ws,
+                                size_t ws_bytes, void* stream);
+
+size_t es_plan_workspace_bytes(const es_plan* plan);
+/* Number of kernel launches one execution of the plan performs. */
+int32_t es_plan_num_launches(const es_plan* plan);
+void es_plan_destroy(es_plan* plan);
+
+/* ---- instrumentation: the launch sequence of one operator call ------------------------- */
+
+/* Number of kernel launches es_adjoint / es_apply / matern_cov_apply / matern_sample (op) run
+ * for this geometry (0 when the operator is the identity, -1 on invalid arguments). */
+int32_t es_schedule_length(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels);
+
+/* Names launch `index` of that sequence (kernel kind, dimensionality, taps, tile variant),
+ * its work-group count and the pyramid level it works on.  Host only. */
+es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                               int32_t index, char* name, size_t name_len, int64_t* work_groups, int32_t* level);
+
+/* Enqueues only launch `index` of the sequence, with the same arguments as the operator call;
+ * the launches before it must already have run on the same buffers.  Used to time one kernel. */
+es_status es_schedule_run_step(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                               double s, const float* in, float* out, void* ws, size_t ws_bytes, int32_t index,
+                               void* stream);
+
+/* ---- host-side helpers (no device call) ------------------------------------------------ */
+
+/* Daubechies extremal-phase low-pass filter dbN (2*order doubles) as this library derives
+ * it on the host; the kernels use it rounded to FP32.  ES_EINVAL for order outside 1..8. */
+es_status es_filter(int order, double* h_out);
+
+/* Weight of the detail bands of each level i = 1..levels (index i-1) and of the
+ * approximation (index levels), as FP32 values the kernels use; tau = 2 for the covariance,
+ * 1 for es_adjoint / es_apply / the sampler. */
+es_status es_level_weights(int levels, double s, double tau, float* w_out);
+
+const char* es_status_string(es_status status);
+const char* es_last_error(void);
+const char* es_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESWAVE_H */

@@ -1,0 +1,1127 @@
+// C ABI of the wavelet E_s^* / Matern-prior library: validation, level schedules, launches.
+//
+// Operators (Sec. 4: W the periodic orthonormal DWT, D the level-weight diagonal with detail
+// level i weighted 2^{-tau s (m-i)} and the approximation weighted 1):
+//   es_adjoint = D_s W,  es_apply = W^T D_s,  matern_cov_apply = W^T D_2s W,
+//   matern_sample = W^T D_s W.
+//
+// es_adjoint / es_apply run the full filter bank level by level (FB_DOWN / FB_UP tile
+// kernels) and finish the coarse levels in one LDS-resident tail kernel per instance.
+//
+// matern_cov_apply / matern_sample use the projection form of W^T D W.  With P_i the
+// orthogonal projection onto the level-i approximation space, P_i = (A^T)^i A^i for the
+// one-level low-pass analysis A, and w_i the weight of detail level i (w_m = 1 = weight of
+// the approximation):
+//   W^T D W = sum_{i=1}^{m} w_i (P_{i-1} - P_i) + P_m = w_1 I + sum_{i=1}^{m-1} c_i P_i,
+//   c_i = w_{i+1} - w_i,
+// evaluated by the Horner recurrence
+//   a_i = A a_{i-1} (a_0 = x),  z_{m-1} = c_{m-1} a_{m-1},
+//   z_i = c_i a_i + A^T z_{i+1},  y = w_1 x + A^T z_1.
+// Only the all-low band of every level is ever formed and level m is never visited, so the
+// high-pass half of every filter pass disappears.  This is exactly the same linear operator
+// as the filter-bank evaluation (a re-association of the same sum), not an approximation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/eswave.h"
+#include "internal.h"
+
+using namespace es;
+
+// ------------------------------------------------------------------------------------------
+// Errors.
+
+namespace {
+
+thread_local std::string g_last_error;
+
+es_status fail(es_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+es_status fail(es_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+es_status dev_fail(hipError_t e, const char* where) {
+  return fail(ES_EDEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define ES_HIP(call, where)                        \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return dev_fail(e_, where); \
+  } while (0)
+
+// ------------------------------------------------------------------------------------------
+// Geometry and validation.
+
+constexpr int kMaxLevels = 30;
+
+struct Geo {
+  int D;
+  int n[3];  // padded: 1-D (1,1,n), 2-D (1,n0,n1), 3-D (n0,n1,n2)
+  int L;
+  int m;
+  double s;
+  int64_t N() const { return (int64_t)n[0] * n[1] * n[2]; }
+  int64_t level_size(int i) const { return (int64_t)(n[0] >> (D >= 3 ? i : 0)) * (n[1] >> (D >= 2 ? i : 0)) * (n[2] >> i); }
+  void level_dims(int i, int out[3]) const {
+    out[0] = D >= 3 ? n[0] >> i : 1;
+    out[1] = D >= 2 ? n[1] >> i : 1;
+    out[2] = n[2] >> i;
+  }
+};
+
+es_status make_geo(int ndim, const int64_t* shape, int order, int levels, double s, Geo* g) {
+  if (ndim < 1 || ndim > 3) return fail(ES_EINVAL, "ndim must be 1, 2 or 3 (got %d)", ndim);
+  if (!shape) return fail(ES_EINVAL, "shape is NULL");
+  if (order < 1 || order > 8) return fail(ES_EINVAL, "order must be in 1..8 (got %d)", order);
+  if (levels < 0 || levels > kMaxLevels) return fail(ES_EINVAL, "levels must be in 0..%d (got %d)", kMaxLevels, levels);
+  if (!std::isfinite(s)) return fail(ES_EINVAL, "s must be finite");
+  g->D = ndim;
+  g->L = 2 * order;
+  g->m = levels;
+  g->s = s;
+  g->n[0] = g->n[1] = 1;
+  int64_t prod = 1;
+  for (int k = 0; k < ndim; ++k) {
+    const int64_t v = shape[k];
+    if (v < 1) return fail(ES_EINVAL, "shape[%d] must be positive (got %lld)", k, (long long)v);
+    if (v > (1ll << 30)) return fail(ES_EINVAL, "shape[%d] too large", k);
+    if (v % (1ll << levels)) return fail(ES_EINVAL, "shape[%d] = %lld is not divisible by 2^levels = %lld", k, (long long)v, 1ll << levels);
+    prod *= v;
+    if (prod > 0x7fffffffll) return fail(ES_EINVAL, "an instance may hold at most 2^31-1 elements");
+    g->n[3 - ndim + k] = (int)v;
+  }
+  return ES_OK;
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return na && nb && pa < pb + nb && pb < pa + na;
+}
+
+es_status check_io(const void* in, const void* out, int64_t batch, int64_t N, const void* ws, size_t ws_bytes,
+                   size_t need) {
+  if (batch < 0) return fail(ES_EINVAL, "batch must be >= 0");
+  if (batch > 0 && N > INT64_MAX / batch / 4) return fail(ES_EINVAL, "batch * size overflows");
+  const size_t bytes = (size_t)(batch * N) * sizeof(float);
+  if (batch == 0) return ES_OK;
+  if (!in || !out) return fail(ES_EINVAL, "input and output pointers must be non-NULL");
+  if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return fail(ES_EINVAL, "input and output must be 16-byte aligned");
+  if (overlap(in, bytes, out, bytes)) return fail(ES_EINVAL, "input and output overlap");
+  if (need) {
+    if (!ws) return fail(ES_EWORKSPACE, "workspace of %zu bytes required, got NULL", need);
+    if (ws_bytes < need) return fail(ES_EWORKSPACE, "workspace of %zu bytes required, got %zu", need, ws_bytes);
+    if ((uintptr_t)ws & 15) return fail(ES_EINVAL, "workspace must be 16-byte aligned");
+    if (overlap(ws, need, in, bytes) || overlap(ws, need, out, bytes)) return fail(ES_EINVAL, "workspace overlaps input or output");
+  }
+  return ES_OK;
+}
+
+// gfx950 check, once per device.
+es_status check_device() {
+  static std::mutex mu;
+  static int ok[64] = {0};  // 0 unknown, 1 ok, -1 unsupported
+  int dev = 0;
+  ES_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= 64) return fail(ES_EUNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lk(mu);
+  if (ok[dev] == 0) {
+    hipDeviceProp_t prop;
+    ES_HIP(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    ok[dev] = strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+    if (ok[dev] < 0) return fail(ES_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  }
+  if (ok[dev] < 0) return fail(ES_EUNSUPPORTED, "device %d is not gfx950", dev);
+  return ES_OK;
+}
+
+bool get_filter(int L, Filter* f) {
+  double h[kMaxTaps];
+  if (!daubechies_filter(L / 2, h)) return false;
+  for (int t = 0; t < kMaxTaps; ++t) f->h[t] = f->g[t] = 0.f;
+  for (int t = 0; t < L; ++t) {
+    f->h[t] = (float)h[t];
+    f->g[t] = (float)((t & 1 ? -1.0 : 1.0) * h[L - 1 - t]);
+  }
+  return true;
+}
+
+// Detail weight of level i (1..m), FP64.
+double wdet(const Geo& g, double tau, int i) { return std::exp2(-tau * g.s * (double)(g.m - i)); }
+
+int64_t align64(int64_t v) { return (v + 63) & ~(int64_t)63; }
+
+// Workspace: level arrays a_1 .. a_m of one instance, each 256-byte aligned.
+int64_t ws_floats_per_instance(const Geo& g) {
+  int64_t tot = 0;
+  for (int i = 1; i <= g.m; ++i) tot += align64(g.level_size(i));
+  return tot;
+}
+int64_t ws_level_offset(const Geo& g, int i) {  // offset of a_i (i >= 1)
+  int64_t off = 0;
+  for (int j = 1; j < i; ++j) off += align64(g.level_size(j));
+  return off;
+}
+
+// ------------------------------------------------------------------------------------------
+// Schedules.  A schedule is a list of launches for one geometry; each launch has one Task
+// (level kernels) or one TailTask (tail kernels) whose pointers already include the
+// per-instance strides of a uniform batch.
+
+// Largest block (elements) the tail kernels keep in LDS, per dimensionality.
+constexpr int64_t kTailMax[4] = {0, 4096, 8192, 8192};
+
+// Test and tuning knobs read at every call: ESWAVE_TAIL_MAX overrides the tail threshold
+// (0 disables the tail kernels), ESWAVE_FORCE_VARIANT=0/1 forces the wide/narrow tiles.
+int64_t tail_max(int D) {
+  const char* e = getenv("ESWAVE_TAIL_MAX");
+  if (e && *e) return atoll(e);
+  return kTailMax[D];
+}
+int forced_variant() {
+  const char* e = getenv("ESWAVE_FORCE_VARIANT");
+  if (e && (*e == '0' || *e == '1')) return *e - '0';
+  return -1;
+}
+
+struct Launch {
+  int is_tail;
+  int kind;     // KernelKind, or tail kind (0 LP, 1 FB analysis, 2 FB synthesis)
+  int variant;
+  int vec;
+  int D, L;
+  Task task;
+  TailTask tail;
+  size_t lds;
+};
+
+struct Schedule {
+  std::vector<Launch> launches;
+  bool identity = false;  // plain copy
+  Filter f;
+};
+
+void set_tiles(Task& t, int kind, const Geo& g, int level, int variant, int64_t batch) {
+  int b[3];
+  g.level_dims(level - 1, b);  // full-res block of the level
+  const TileShape ts = tile_shape(kind, g.D, variant, g.L);
+  const bool analysis = (kind == K_LP_DOWN || kind == K_FB_DOWN);
+  for (int k = 0; k < 3; ++k) {
+    t.b[k] = b[k];
+    const bool real = k >= 3 - g.D;
+    const int extent = real ? (analysis ? b[k] / 2 : b[k]) : 1;
+    t.ntile[k] = real ? (extent + ts.t[k] - 1) / ts.t[k] : 1;
+  }
+  t.tiles_per_inst = t.ntile[0] * t.ntile[1] * t.ntile[2];
+  t.batch = (int32_t)batch;
+  t.tile_begin = 0;
+}
+
+double tile_waste(int kind, const Geo& g, int level, int variant) {
+  int b[3];
+  g.level_dims(level - 1, b);
+  const TileShape ts = tile_shape(kind, g.D, variant, g.L);
+  const bool analysis = (kind == K_LP_DOWN || kind == K_FB_DOWN);
+  double covered = 1, needed = 1;
+  for (int k = 3 - g.D; k < 3; ++k) {
+    const int extent = analysis ? b[k] / 2 : b[k];
+    covered *= (double)((extent + ts.t[k] - 1) / ts.t[k]) * ts.t[k];
+    needed *= extent;
+  }
+  return covered / needed;
+}
+
+int pick_variant(int kind, const Geo& g, int level, int64_t batch) {
+  const int fv = forced_variant();
+  if (fv >= 0) return fv;
+  const double w0 = tile_waste(kind, g, level, 0), w1 = tile_waste(kind, g, level, 1);
+  Task t{};
+  set_tiles(t, kind, g, level, 0, batch);
+  const int64_t wg0 = (int64_t)t.tiles_per_inst * batch;
+  if (w0 <= 1.25 && wg0 >= 1024) return 0;
+  if (w0 <= w1 && wg0 >= 2048) return 0;
+  return 1;
+}
+
+// Row-alignment condition of the vector staging path for one launch.
+bool vec_ok(const Task& t, int kind, const Geo& g) {
+  auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+  auto m4 = [](int64_t v) { return (v & 3) == 0; };
+  const bool analysis = (kind == K_LP_DOWN || kind == K_FB_DOWN);
+  const int row = analysis ? t.b[2] : t.b[2] / 2;  // staged rows are the input rows
+  if (!m4(row)) return false;
+  if (!a16(t.in0) || !m4(t.bs_in0) || !m4(t.st_in0[0]) || !m4(t.st_in0[1])) return false;
+  if (kind == K_FB_UP && (!a16(t.in1) || !m4(t.bs_in1) || !m4(t.st_in1[0]) || !m4(t.st_in1[1]))) return false;
+  (void)g;
+  return true;
+}
+
+void strides_of(const int dims[3], int32_t st[2]) {
+  st[0] = dims[1] * dims[2];
+  st[1] = dims[2];
+}
+
+Launch level_launch(int kind, const Geo& g, int level, int64_t batch) {
+  Launch l{};
+  l.is_tail = 0;
+  l.kind = kind;
+  l.D = g.D;
+  l.L = g.L;
+  l.variant = pick_variant(kind, g, level, batch);
+  set_tiles(l.task, kind, g, level, l.variant, batch);
+  return l;
+}
+
+void finish_level(Launch& l, const Geo& g) { l.vec = vec_ok(l.task, l.kind, g) ? 1 : 0; }
+
+es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, float* out, float* ws,
+                         Schedule* sc) {
+  sc->launches.clear();
+  sc->identity = false;
+  if (!get_filter(g.L, &sc->f)) return fail(ES_EUNSUPPORTED, "filter derivation failed for order %d", g.L / 2);
+  const int64_t N = g.N();
+  const int64_t wsi = ws_floats_per_instance(g);
+  const int D = g.D, m = g.m;
+  int full[3];
+  g.level_dims(0, full);
+  int32_t st_full[2];
+  strides_of(full, st_full);
+  auto lvl_ptr = [&](int i) -> float* { return ws + ws_level_offset(g, i); };
+  auto lvl_dims = [&](int i, int d[3]) { g.level_dims(i, d); };
+
+  if (op == ES_OP_COV || op == ES_OP_SAMPLE) {
+    if (m <= 1) {  // all weights are 1: identity
+      sc->identity = true;
+      return ES_OK;
+    }
+    const double tau = op == ES_OP_COV ? 2.0 : 1.0;
+    std::vector<double> w(m + 2), c(m + 1);
+    for (int i = 1; i <= m; ++i) w[i] = wdet(g, tau, i);
+    for (int i = 1; i <= m - 1; ++i) c[i] = w[i + 1] - w[i];
+    int T = -1;
+    for (int i = 0; i <= m - 2; ++i)
+      if (g.level_size(i) <= tail_max(D)) { T = i; break; }
+    const bool tail = T >= 0;
+    const int down_to = tail ? T : m - 1;
+    for (int i = 1; i <= down_to; ++i) {
+      Launch l = level_launch(K_LP_DOWN, g, i, batch);
+      int d_in[3], d_out[3];
+      lvl_dims(i - 1, d_in);
+      lvl_dims(i, d_out);
+      l.task.in0 = i == 1 ? in : lvl_ptr(i - 1);
+      l.task.bs_in0 = i == 1 ? N : wsi;
+      strides_of(d_in, l.task.st_in0);
+      l.task.out0 = lvl_ptr(i);
+      l.task.bs_out0 = wsi;
+      strides_of(d_out, l.task.st_out0);
+      finish_level(l, g);
+      sc->launches.push_back(l);
+    }
+    if (tail) {
+      Launch l{};
+      l.is_tail = 1;
+      l.kind = 0;
+      l.D = D;
+      l.L = g.L;
+      TailTask& t = l.tail;
+      const int K = m - 1 - T;
+      t.in = T == 0 ? in : lvl_ptr(T);
+      t.bs_in = T == 0 ? N : wsi;
+      t.out = T == 0 ? out : lvl_ptr(T);
+      t.bs_out = T == 0 ? N : wsi;
+      lvl_dims(T, t.b);
+      t.nlev = K;
+      t.batch = (int32_t)batch;
+      t.coef[0] = (float)(T == 0 ? w[1] : c[T]);
+      for (int j = 1; j <= K; ++j) t.coef[j] = (float)c[T + j];
+      l.lds = tail_lds_bytes(0, D, t.b, K);
+      sc->launches.push_back(l);
+    }
+    const int up_from = tail ? T - 1 : m - 2;
+    for (int i = up_from; i >= 0; --i) {
+      // produce level i (full-res block of level i = dims of a_i)
+      Launch l = level_launch(K_LP_UP, g, i + 1, batch);
+      int d_z[3], d_o[3];
+      lvl_dims(i + 1, d_z);
+      lvl_dims(i, d_o);
+      l.task.in0 = lvl_ptr(i + 1);
+      l.task.bs_in0 = wsi;
+      strides_of(d_z, l.task.st_in0);
+      l.task.in1 = i == 0 ? in : lvl_ptr(i);
+      l.task.bs_in1 = i == 0 ? N : wsi;
+      l.task.out0 = i == 0 ? out : lvl_ptr(i);
+      l.task.bs_out0 = i == 0 ? N : wsi;
+      strides_of(d_o, l.task.st_in1);
+      strides_of(d_o, l.task.st_out0);
+      l.task.alpha = (float)(i == 0 ? w[1] : c[i]);
+      l.task.beta = (!tail && i == m - 2) ? (float)c[m - 1] : 1.f;
+      finish_level(l, g);
+      sc->launches.push_back(l);
+    }
+    return ES_OK;
+  }
+
+  // full filter bank
+  if (m == 0) {
+    sc->identity = true;
+    return ES_OK;
+  }
+  std::vector<double> w(m + 1);
+  for (int i = 1; i <= m; ++i) w[i] = wdet(g, 1.0, i);
+  int T = m;  // tail handles levels T+1..m from a_T
+  for (int i = 0; i <= m - 1; ++i)
+    if (g.level_size(i) <= tail_max(D)) { T = i; break; }
+  const bool tail = T < m;
+  auto approx_region = [&](int32_t st[2]) { st[0] = st_full[0]; st[1] = st_full[1]; };
+
+  if (op == ES_OP_ADJOINT) {
+    for (int i = 1; i <= T; ++i) {
+      Launch l = level_launch(K_FB_DOWN, g, i, batch);
+      int d_in[3], d_ll[3];
+      lvl_dims(i - 1, d_in);
+      lvl_dims(i, d_ll);
+      l.task.in0 = i == 1 ? in : lvl_ptr(i - 1);
+      l.task.bs_in0 = i == 1 ? N : wsi;
+      strides_of(d_in, l.task.st_in0);
+      l.task.out0 = out;
+      l.task.bs_out0 = N;
+      l.task.st_out0[0] = st_full[0];
+      l.task.st_out0[1] = st_full[1];
+      if (i == m) {  // last level without tail: approximation into the coefficient array
+        l.task.out1 = out;
+        l.task.bs_out1 = N;
+        approx_region(l.task.st_out1);
+      } else {
+        l.task.out1 = lvl_ptr(i);
+        l.task.bs_out1 = wsi;
+        strides_of(d_ll, l.task.st_out1);
+      }
+      l.task.alpha = (float)w[i];
+      l.task.beta = 1.f;
+      finish_level(l, g);
+      sc->launches.push_back(l);
+    }
+    if (tail) {
+      Launch l{};
+      l.is_tail = 1;
+      l.kind = 1;
+      l.D = D;
+      l.L = g.L;
+      TailTask& t = l.tail;
+      t.in = T == 0 ? in : lvl_ptr(T);
+      t.bs_in = T == 0 ? N : wsi;
+      t.out = out;
+      t.bs_out = N;
+      t.st_out[0] = st_full[0];
+      t.st_out[1] = st_full[1];
+      lvl_dims(T, t.b);
+      int db[3];
+      lvl_dims(T, db);
+      strides_of(db, t.st_in);
+      t.nlev = m - T;
+      t.batch = (int32_t)batch;
+      for (int j = 0; j < m - T; ++j) t.coef[j] = (float)w[T + 1 + j];
+      t.coef[m - T] = 1.f;
+      l.lds = tail_lds_bytes(1, D, t.b, t.nlev);
+      sc->launches.push_back(l);
+    }
+    return ES_OK;
+  }
+
+  // ES_OP_APPLY
+  if (tail) {
+    Launch l{};
+    l.is_tail = 1;
+    l.kind = 2;
+    l.D = D;
+    l.L = g.L;
+    TailTask& t = l.tail;
+    t.in = in;
+    t.bs_in = N;
+    t.st_in[0] = st_full[0];
+    t.st_in[1] = st_full[1];
+    t.out = T == 0 ? out : lvl_ptr(T);
+    t.bs_out = T == 0 ? N : wsi;
+    lvl_dims(T, t.b);
+    int db[3];
+    lvl_dims(T, db);
+    if (T == 0) {
+      t.st_out[0] = st_full[0];
+      t.st_out[1] = st_full[1];
+    } else {
+      strides_of(db, t.st_out);
+    }
+    t.nlev = m - T;
+    t.batch = (int32_t)batch;
+    for (int j = 0; j < m - T; ++j) t.coef[j] = (float)w[T + 1 + j];
+    t.coef[m - T] = 1.f;
+    l.lds = tail_lds_bytes(2, D, t.b, t.nlev);
+    sc->launches.push_back(l);
+  }
+  for (int i = T; i >= 1; --i) {
+    Launch l = level_launch(K_FB_UP, g, i, batch);
+    int d_ll[3], d_out[3];
+    lvl_dims(i, d_ll);
+    lvl_dims(i - 1, d_out);
+    if (i == m) {  // no tail: approximation read from the coefficient array
+      l.task.in0 = in;
+      l.task.bs_in0 = N;
+      approx_region(l.task.st_in0);
+    } else {
+      l.task.in0 = lvl_ptr(i);
+      l.task.bs_in0 = wsi;
+      strides_of(d_ll, l.task.st_in0);
+    }
+    l.task.in1 = in;
+    l.task.bs_in1 = N;
+    l.task.st_in1[0] = st_full[0];
+    l.task.st_in1[1] = st_full[1];
+    l.task.out0 = i == 1 ? out : lvl_ptr(i - 1);
+    l.task.bs_out0 = i == 1 ? N : wsi;
+    strides_of(d_out, l.task.st_out0);
+    l.task.alpha = (float)w[i];
+    l.task.beta = 1.f;
+    finish_level(l, g);
+    sc->launches.push_back(l);
+  }
+  return ES_OK;
+}
+
+int64_t round8(int64_t v) { return (v + 7) & ~(int64_t)7; }
+
+es_status run_launch(const Launch& l, const Filter& f, hipStream_t stream, const Task* table, int count,
+                     int total_wg, const TailTask* ttable) {
+  if (total_wg <= 0) return ES_OK;
+  const int grid = (int)round8(total_wg);
+  if (!l.is_tail) {
+    TaskArgs a{};
+    a.table = table;
+    a.count = count;
+    a.total_wg = total_wg;
+    a.vec = l.vec;
+    a.t0 = l.task;
+    ES_HIP(launch_level(l.kind, l.D, l.L, l.variant, a, grid, f, stream), "level kernel launch");
+  } else {
+    TailArgs a{};
+    a.table = ttable;
+    a.count = count;
+    a.total_wg = total_wg;
+    a.t0 = l.tail;
+    ES_HIP(launch_tail(l.kind, l.D, l.L, a, grid, l.lds, f, stream), "tail kernel launch");
+  }
+  return ES_OK;
+}
+
+es_status run_schedule(const Schedule& sc, const Geo& g, int64_t batch, const float* in, float* out,
+                       hipStream_t stream) {
+  if (batch == 0) return ES_OK;
+  if (sc.identity) {
+    const int64_t n = batch * g.N();
+    if (n % 4 == 0) {
+      ES_HIP(launch_copy(in, out, n, stream), "copy kernel launch");
+    } else {
+      ES_HIP(hipMemcpyAsync(out, in, n * sizeof(float), hipMemcpyDeviceToDevice, stream), "hipMemcpyAsync");
+    }
+    return ES_OK;
+  }
+  for (const Launch& l : sc.launches) {
+    const int64_t per = l.is_tail ? 1 : l.task.tiles_per_inst;
+    const int64_t total = per * batch;
+    if (total > 0x7fffffffll) return fail(ES_EINVAL, "too many work-groups in one launch");
+    es_status st = run_launch(l, sc.f, stream, nullptr, 1, (int)total, nullptr);
+    if (st != ES_OK) return st;
+  }
+  return ES_OK;
+}
+
+es_status run_op(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                 const float* in, float* out, void* ws, size_t ws_bytes, void* stream) {
+  Geo g;
+  es_status st = make_geo(ndim, shape, order, levels, s, &g);
+  if (st != ES_OK) return st;
+  const size_t need = (size_t)(batch > 0 ? batch : 0) * (size_t)ws_floats_per_instance(g) * sizeof(float);
+  const bool identity = (op >= ES_OP_COV) ? levels <= 1 : levels == 0;
+  st = check_io(in, out, batch, g.N(), ws, ws_bytes, identity ? 0 : need);
+  if (st != ES_OK) return st;
+  if (batch == 0) return ES_OK;
+  if (batch > 0x7fffffffll) return fail(ES_EINVAL, "batch too large");
+  st = check_device();
+  if (st != ES_OK) return st;
+  Schedule sc;
+  st = build_schedule(op, g, batch, in, out, (float*)ws, &sc);
+  if (st != ES_OK) return st;
+  return run_schedule(sc, g, batch, in, out, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------------------------------
+// Plain reference path: per instance, per level, per axis, one launch each.
+
+int64_t plain_ws_floats(const Geo& g, int op) {
+  const int64_t N = align64(g.N());
+  if (op == ES_OP_COV || op == ES_OP_SAMPLE) return 3 * N;  // coefficients + two temporaries
+  return 2 * N;
+}
+
+es_status plain_instance(int op, const Geo& g, const Filter& f, const float* in, float* out, float* ws,
+                         hipStream_t s) {
+  const int64_t N = align64(g.N());
+  float* T1 = ws;
+  float* T2 = ws + N;
+  float* C = ws + 2 * N;  // coefficient buffer (cov / sample)
+  int full[3];
+  g.level_dims(0, full);
+  int32_t stf[2];
+  strides_of(full, stf);
+  const int D = g.D, m = g.m;
+  auto pass = [&](const float* src, float* dst, int i, int ax, int synth, int scale, float w) -> es_status {
+    PlainPass p{};
+    p.src = src;
+    p.dst = dst;
+    g.level_dims(i - 1, p.b);
+    p.st_src[0] = p.st_dst[0] = stf[0];
+    p.st_src[1] = p.st_dst[1] = stf[1];
+    p.axis = ax;
+    p.synth = synth;
+    p.scale_mode = scale;
+    p.ndim = D;
+    p.w = w;
+    ES_HIP(launch_plain_pass(p, g.L, f, s), "plain pass launch");
+    return ES_OK;
+  };
+  auto blk_copy = [&](const float* src, float* dst, int i) -> es_status {
+    int b[3];
+    g.level_dims(i - 1, b);
+    int st[2] = {stf[0], stf[1]};
+    ES_HIP(launch_block_copy(src, dst, b, st, st, s), "block copy launch");
+    return ES_OK;
+  };
+  // analysis of `src` into packed coefficients `dst` (dst may equal the level-2+ source)
+  auto analysis = [&](const float* src, float* dst, double tau) -> es_status {
+    for (int i = 1; i <= m; ++i) {
+      const float w = (float)wdet(g, tau, i);
+      const float* a = i == 1 ? src : dst;
+      // axes last to first, ping-pong T1/T2, the level's last pass scales and writes dst
+      int axes[3], na = 0;
+      for (int ax = 2; ax >= 3 - D; --ax) axes[na++] = ax;
+      const float* cur = a;
+      for (int k = 0; k < na; ++k) {
+        const bool last = k == na - 1;
+        float* nxt = last ? dst : (k % 2 == 0 ? T1 : T2);
+        if (last && cur == dst) nxt = (k % 2 == 0 ? T1 : T2);  // avoid in-place pass
+        es_status st = pass(cur, nxt, i, axes[k], 0, last ? 1 : 0, w);
+        if (st != ES_OK) return st;
+        if (last && nxt != dst) {
+          st = blk_copy(nxt, dst, i);
+          if (st != ES_OK) return st;
+        }
+        cur = nxt;
+      }
+    }
+    return ES_OK;
+  };
+  // synthesis of packed coefficients `src` into `dst` (src is copied to dst first)
+  auto synthesis = [&](const float* src, float* dst, double tau) -> es_status {
+    ES_HIP(launch_copy(src, dst, g.N(), s), "copy kernel launch");
+    for (int i = m; i >= 1; --i) {
+      const float w = (float)wdet(g, tau, i);
+      int axes[3], na = 0;
+      for (int ax = 3 - D; ax <= 2; ++ax) axes[na++] = ax;
+      const float* cur = dst;
+      for (int k = 0; k < na; ++k) {
+        const bool last = k == na - 1;
+        float* nxt = last ? dst : (k % 2 == 0 ? T1 : T2);
+        if (last && cur == dst) nxt = (k % 2 == 0 ? T1 : T2);
+        es_status st = pass(cur, nxt, i, axes[k], 1, k == 0 ? 2 : 0, w);
+        if (st != ES_OK) return st;
+        if (last && nxt != dst) {
+          st = blk_copy(nxt, dst, i);
+          if (st != ES_OK) return st;
+        }
+        cur = nxt;
+      }
+    }
+    return ES_OK;
+  };
+  switch (op) {
+    case ES_OP_ADJOINT: return analysis(in, out, 1.0);
+    case ES_OP_APPLY: return synthesis(in, out, 1.0);
+    default: {
+      // D_tau = D_{tau/2} D_{tau/2}: half of the weight on each side
+      const double half_tau = op == ES_OP_COV ? 1.0 : 0.5;
+      es_status st = analysis(in, C, half_tau);
+      if (st != ES_OK) return st;
+      return synthesis(C, out, half_tau);
+    }
+  }
+}
+
+
+
+// ------------------------------------------------------------------------------------------
+// Ragged plans.  Every instance gets the schedule a single call would run; launches of the
+// same phase (down level i, tail, up level i) and the same kernel instantiation are merged
+// into one launch whose work-groups look their instance up in a device task table.  Phases
+// run in dependency order: down levels ascending, tails, up levels descending, so each
+// instance's steps keep their order.  The whole sequence is captured once into a hipGraph.
+
+struct PlanGroup {
+  int phase;
+  Launch proto;           // kernel instantiation (kind, D, L, variant, vec, lds)
+  std::vector<int> inst;  // instances, in table order
+  std::vector<int> step;  // index of the step in the instance's schedule
+  int64_t table_off;      // first entry in the task (or tail) table
+  int total_wg;
+};
+
+}  // namespace
+
+struct es_plan {
+  int op = 0;
+  int device = 0;
+  std::vector<Geo> geos;
+  std::vector<int64_t> ws_off;
+  int64_t ws_total = 0;
+  std::vector<std::vector<int>> phase_of;  // per instance: phase of each schedule step
+  std::vector<PlanGroup> groups;
+  std::vector<Task> h_tasks;
+  std::vector<TailTask> h_tails;
+  Task* d_tasks = nullptr;
+  TailTask* d_tails = nullptr;
+  Filter filt[17];
+  std::vector<const float*> last_in;
+  std::vector<float*> last_out;
+  void* last_ws = nullptr;
+  bool tables_valid = false;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  std::vector<int> identity_inst;  // instances whose op is the identity (plain copy)
+};
+
+namespace {
+
+// Schedule of instance `k` with the plan's current pointers.
+es_status instance_schedule(const es_plan* p, int k, const float* in, float* out, void* ws, Schedule* sc) {
+  const Geo& g = p->geos[k];
+  float* wsk = ws ? (float*)ws + p->ws_off[k] : (float*)(uintptr_t)256;
+  return build_schedule(p->op, g, 1, in ? in : (const float*)(uintptr_t)256, out ? out : (float*)(uintptr_t)512, wsk,
+                        sc);
+}
+
+// Phase of step j of an instance schedule: down steps get their level index, the tail 1000,
+// up steps 2000 - (level they produce).
+void step_phases(int op, const Geo& g, const Schedule& sc, std::vector<int>* ph) {
+  ph->clear();
+  int down = 0;
+  for (const Launch& l : sc.launches) {
+    if (l.is_tail) {
+      ph->push_back(op == ES_OP_APPLY ? 0 : 1000);
+    } else if (l.kind == K_LP_DOWN || l.kind == K_FB_DOWN) {
+      ph->push_back(++down);
+    } else {
+      // LP_UP / FB_UP: task.b is the full-res output block; its level index follows from size
+      int lev = 0;
+      while (lev < 31 && (g.n[2] >> lev) != l.task.b[2]) ++lev;
+      ph->push_back(2000 - lev);
+    }
+  }
+}
+
+es_status plan_fill_tables(es_plan* p, const float* const* in, float* const* out, void* ws) {
+  const int n = (int)p->geos.size();
+  std::vector<Schedule> scs(n);
+  for (int k = 0; k < n; ++k) {
+    es_status st = instance_schedule(p, k, in ? in[k] : nullptr, out ? out[k] : nullptr, ws, &scs[k]);
+    if (st != ES_OK) return st;
+  }
+  for (PlanGroup& gr : p->groups) {
+    int64_t wg = 0;
+    for (size_t q = 0; q < gr.inst.size(); ++q) {
+      const Launch& l = scs[gr.inst[q]].launches[gr.step[q]];
+      if (gr.proto.is_tail) {
+        TailTask t = l.tail;
+        t.tile_begin = (int32_t)wg;
+        t.batch = 1;
+        p->h_tails[gr.table_off + q] = t;
+        wg += 1;
+      } else {
+        Task t = l.task;
+        t.tile_begin = (int32_t)wg;
+        t.batch = 1;
+        p->h_tasks[gr.table_off + q] = t;
+        wg += t.tiles_per_inst;
+      }
+    }
+    gr.total_wg = (int)wg;
+  }
+  return ES_OK;
+}
+
+es_status plan_launch_all(es_plan* p, hipStream_t s) {
+  for (const PlanGroup& gr : p->groups) {
+    const Filter& f = p->filt[gr.proto.L];
+    es_status st = run_launch(gr.proto, f, s, gr.proto.is_tail ? nullptr : p->d_tasks + gr.table_off,
+                              (int)gr.inst.size(), gr.total_wg, gr.proto.is_tail ? p->d_tails + gr.table_off : nullptr);
+    if (st != ES_OK) return st;
+  }
+  return ES_OK;
+}
+
+es_status plan_identity_copies(es_plan* p, const float* const* in, float* const* out, hipStream_t s) {
+  for (int k : p->identity_inst) {
+    const int64_t N = p->geos[k].N();
+    if (N % 4 == 0) {
+      ES_HIP(launch_copy(in[k], out[k], N, s), "copy kernel launch");
+    } else {
+      ES_HIP(hipMemcpyAsync(out[k], in[k], N * sizeof(float), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync");
+    }
+  }
+  return ES_OK;
+}
+
+es_status plan_prepare(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
+                       hipStream_t s, bool* changed) {
+  if (!in || !out) return fail(ES_EINVAL, "in and out must be non-NULL host arrays");
+  const int n = (int)p->geos.size();
+  if (p->ws_total > 0) {
+    if (!ws) return fail(ES_EWORKSPACE, "workspace of %zu bytes required", (size_t)p->ws_total * sizeof(float));
+    if (ws_bytes < (size_t)p->ws_total * sizeof(float)) return fail(ES_EWORKSPACE, "workspace too small");
+    if ((uintptr_t)ws & 15) return fail(ES_EINVAL, "workspace must be 16-byte aligned");
+  }
+  for (int k = 0; k < n; ++k) {
+    const size_t bytes = (size_t)p->geos[k].N() * sizeof(float);
+    es_status st = check_io(in[k], out[k], 1, p->geos[k].N(), nullptr, 0, 0);
+    if (st != ES_OK) return fail(st, "instance %d: %s", k, g_last_error.c_str());
+    if (ws && p->ws_total && (overlap(ws, p->ws_total * sizeof(float), in[k], bytes) ||
+                              overlap(ws, p->ws_total * sizeof(float), out[k], bytes)))
+      return fail(ES_EINVAL, "instance %d overlaps the workspace", k);
+  }
+  int dev = 0;
+  ES_HIP(hipGetDevice(&dev), "hipGetDevice");
+  if (dev != p->device) return fail(ES_EINVAL, "plan was created on device %d, current device is %d", p->device, dev);
+  bool same = p->tables_valid && ws == p->last_ws;
+  for (int k = 0; same && k < n; ++k) same = in[k] == p->last_in[k] && out[k] == p->last_out[k];
+  *changed = !same;
+  if (!same) {
+    es_status st = plan_fill_tables(p, in, out, ws);
+    if (st != ES_OK) return st;
+    if (!p->h_tasks.empty())
+      ES_HIP(hipMemcpyAsync(p->d_tasks, p->h_tasks.data(), p->h_tasks.size() * sizeof(Task), hipMemcpyHostToDevice, s),
+             "task table upload");
+    if (!p->h_tails.empty())
+      ES_HIP(hipMemcpyAsync(p->d_tails, p->h_tails.data(), p->h_tails.size() * sizeof(TailTask),
+                            hipMemcpyHostToDevice, s),
+             "tail table upload");
+    p->last_in.assign(in, in + n);
+    p->last_out.assign(out, out + n);
+    p->last_ws = ws;
+    p->tables_valid = true;
+  }
+  return ES_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Exports.
+
+extern "C" {
+
+es_status es_adjoint(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s, const float* x,
+                     float* coeff, void* ws, size_t ws_bytes, void* stream) {
+  return run_op(ES_OP_ADJOINT, ndim, shape, batch, order, levels, s, x, coeff, ws, ws_bytes, stream);
+}
+
+es_status es_apply(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s, const float* coeff,
+                   float* x, void* ws, size_t ws_bytes, void* stream) {
+  return run_op(ES_OP_APPLY, ndim, shape, batch, order, levels, s, coeff, x, ws, ws_bytes, stream);
+}
+
+es_status matern_cov_apply(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                           const float* x, float* y, void* ws, size_t ws_bytes, void* stream) {
+  return run_op(ES_OP_COV, ndim, shape, batch, order, levels, s, x, y, ws, ws_bytes, stream);
+}
+
+es_status matern_sample(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                        const float* xi, float* x, void* ws, size_t ws_bytes, void* stream) {
+  return run_op(ES_OP_SAMPLE, ndim, shape, batch, order, levels, s, xi, x, ws, ws_bytes, stream);
+}
+
+size_t es_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels, int op) {
+  Geo g;
+  if (make_geo(ndim, shape, order, levels, 0.0, &g) != ES_OK || batch < 0 || op < 0 || op > 3) return 0;
+  const bool identity = (op >= ES_OP_COV) ? levels <= 1 : levels == 0;
+  if (identity) return 0;
+  return (size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float);
+}
+
+size_t es_workspace_bytes_plain(int ndim, const int64_t* shape, int64_t batch, int order, int levels, int op) {
+  Geo g;
+  (void)batch;
+  if (make_geo(ndim, shape, order, levels, 0.0, &g) != ES_OK || op < 0 || op > 3) return 0;
+  return (size_t)plain_ws_floats(g, op) * sizeof(float);
+}
+
+es_status es_plain_apply_op(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                            const float* in, float* out, void* ws, size_t ws_bytes, void* stream) {
+  if (op < 0 || op > 3) return fail(ES_EINVAL, "unknown op %d", op);
+  Geo g;
+  es_status st = make_geo(ndim, shape, order, levels, s, &g);
+  if (st != ES_OK) return st;
+  if (g.N() % 4) return fail(ES_EUNSUPPORTED, "the plain path needs instance sizes divisible by 4");
+  const size_t need = (size_t)plain_ws_floats(g, op) * sizeof(float);
+  st = check_io(in, out, batch, g.N(), ws, ws_bytes, need);
+  if (st != ES_OK) return st;
+  if (batch == 0) return ES_OK;
+  st = check_device();
+  if (st != ES_OK) return st;
+  Filter f;
+  if (!get_filter(g.L, &f)) return fail(ES_EUNSUPPORTED, "filter derivation failed");
+  const hipStream_t hs = (hipStream_t)stream;
+  for (int64_t b = 0; b < batch; ++b) {
+    const float* ib = in + b * g.N();
+    float* ob = out + b * g.N();
+    if (g.m == 0) {
+      ES_HIP(launch_copy(ib, ob, g.N(), hs), "copy kernel launch");
+      continue;
+    }
+    st = plain_instance(op, g, f, ib, ob, (float*)ws, hs);
+    if (st != ES_OK) return st;
+  }
+  return ES_OK;
+}
+
+es_status es_plan_create(const es_desc* descs, int32_t count, int op, void* stream, es_plan** out) {
+  if (!out) return fail(ES_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 0 || (count > 0 && !descs)) return fail(ES_EINVAL, "descs must hold count >= 0 entries");
+  if (op < 0 || op > 3) return fail(ES_EINVAL, "unknown op %d", op);
+  es_status st = check_device();
+  if (st != ES_OK) return st;
+  (void)stream;
+  es_plan* p = new (std::nothrow) es_plan();
+  if (!p) return fail(ES_ENOMEM, "plan allocation failed");
+  p->op = op;
+  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(ES_EDEVICE, "hipGetDevice failed"); }
+  for (int o = 1; o <= 8; ++o)
+    if (!get_filter(2 * o, &p->filt[2 * o])) { delete p; return fail(ES_EUNSUPPORTED, "filter derivation failed"); }
+  p->geos.resize(count);
+  p->ws_off.resize(count);
+  for (int k = 0; k < count; ++k) {
+    const es_desc& d = descs[k];
+    st = make_geo(d.ndim, d.shape, d.order, d.levels, d.s, &p->geos[k]);
+    if (st != ES_OK) { delete p; return fail(st, "desc %d: %s", k, g_last_error.c_str()); }
+    p->ws_off[k] = p->ws_total;
+    p->ws_total += ws_floats_per_instance(p->geos[k]);
+  }
+  // group steps
+  std::vector<Schedule> scs(count);
+  for (int k = 0; k < count; ++k) {
+    st = instance_schedule(p, k, nullptr, nullptr, nullptr, &scs[k]);
+    if (st != ES_OK) { delete p; return st; }
+    if (scs[k].identity) { p->identity_inst.push_back(k); continue; }
+    std::vector<int> ph;
+    step_phases(op, p->geos[k], scs[k], &ph);
+    for (size_t j = 0; j < scs[k].launches.size(); ++j) {
+      const Launch& l = scs[k].launches[j];
+      PlanGroup* gr = nullptr;
+      for (PlanGroup& c : p->groups)
+        if (c.phase == ph[j] && c.proto.is_tail == l.is_tail && c.proto.kind == l.kind && c.proto.D == l.D &&
+            c.proto.L == l.L && c.proto.variant == l.variant && c.proto.vec == l.vec) { gr = &c; break; }
+      if (!gr) {
+        p->groups.push_back(PlanGroup{});
+        gr = &p->groups.back();
+        gr->phase = ph[j];
+        gr->proto = l;
+        gr->proto.lds = 0;
+      }
+      gr->inst.push_back(k);
+      gr->step.push_back((int)j);
+      if (l.is_tail) gr->proto.lds = std::max(gr->proto.lds, l.lds);
+    }
+  }
+  std::stable_sort(p->groups.begin(), p->groups.end(), [](const PlanGroup& a, const PlanGroup& b) { return a.phase < b.phase; });
+  int64_t nt = 0, ntail = 0;
+  for (PlanGroup& gr : p->groups) {
+    if (gr.proto.is_tail) { gr.table_off = ntail; ntail += gr.inst.size(); }
+    else { gr.table_off = nt; nt += gr.inst.size(); }
+  }
+  p->h_tasks.resize(nt);
+  p->h_tails.resize(ntail);
+  if (nt && hipMalloc(&p->d_tasks, nt * sizeof(Task)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "task table allocation failed"); }
+  if (ntail && hipMalloc(&p->d_tails, ntail * sizeof(TailTask)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "tail table allocation failed"); }
+  *out = p;
+  return ES_OK;
+}
+
+es_status es_plan_execute_eager(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
+                                void* stream) {
+  if (!p) return fail(ES_EINVAL, "plan is NULL");
+  if (p->geos.empty()) return ES_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  bool changed = false;
+  es_status st = plan_prepare(p, in, out, ws, ws_bytes, s, &changed);
+  if (st != ES_OK) return st;
+  st = plan_identity_copies(p, in, out, s);
+  if (st != ES_OK) return st;
+  return plan_launch_all(p, s);
+}
+
+es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!p) return fail(ES_EINVAL, "plan is NULL");
+  if (p->geos.empty()) return ES_OK;
+  const hipStream_t s = (hipStream_t)stream;
+  bool changed = false;
+  es_status st = plan_prepare(p, in, out, ws, ws_bytes, s, &changed);
+  if (st != ES_OK) return st;
+  // identity instances are plain copies of caller pointers: launched eagerly
+  st = plan_identity_copies(p, in, out, s);
+  if (st != ES_OK) return st;
+  if (p->groups.empty()) return ES_OK;
+  if (!p->exec) {
+    // kernels read everything through the device tables, so the captured graph stays valid
+    // when the caller's pointers change (only the tables are refreshed, above)
+    hipStream_t cap = nullptr;
+    ES_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { (void)hipStreamDestroy(cap); return dev_fail(e, "hipStreamBeginCapture"); }
+    st = plan_launch_all(p, cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap, &graph);
+    (void)hipStreamDestroy(cap);
+    if (st != ES_OK) { if (graph) (void)hipGraphDestroy(graph); return st; }
+    if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(graph); return dev_fail(e, "hipGraphInstantiate"); }
+    p->graph = graph;
+    p->exec = exec;
+  }
+  ES_HIP(hipGraphLaunch(p->exec, s), "hipGraphLaunch");
+  return ES_OK;
+}
+
+size_t es_plan_workspace_bytes(const es_plan* p) { return p ? (size_t)p->ws_total * sizeof(float) : 0; }
+
+int32_t es_plan_num_launches(const es_plan* p) {
+  return p ? (int32_t)(p->groups.size() + p->identity_inst.size()) : 0;
+}
+
+void es_plan_destroy(es_plan* p) {
+  if (!p) return;
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->d_tasks) (void)hipFree(p->d_tasks);
+  if (p->d_tails) (void)hipFree(p->d_tails);
+  delete p;
+}
+
+int32_t es_schedule_length(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels) {
+  Geo g;
+  if (op < 0 || op > 3 || batch < 1 || make_geo(ndim, shape, order, levels, 0.0, &g) != ES_OK) return -1;
+  Schedule sc;
+  if (build_schedule(op, g, batch, (const float*)(uintptr_t)256, (float*)(uintptr_t)512, (float*)(uintptr_t)1024, &sc) !=
+      ES_OK)
+    return -1;
+  return sc.identity ? 0 : (int32_t)sc.launches.size();
+}
+
+es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                               int32_t index, char* name, size_t name_len, int64_t* work_groups, int32_t* level) {
+  Geo g;
+  if (op < 0 || op > 3) return fail(ES_EINVAL, "unknown op %d", op);
+  if (batch < 1) return fail(ES_EINVAL, "batch must be >= 1");
+  es_status st = make_geo(ndim, shape, order, levels, 0.0, &g);
+  if (st != ES_OK) return st;
+  Schedule sc;
+  st = build_schedule(op, g, batch, (const float*)(uintptr_t)256, (float*)(uintptr_t)512, (float*)(uintptr_t)1024, &sc);
+  if (st != ES_OK) return st;
+  if (index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
+  const Launch& l = sc.launches[index];
+  static const char* kinds[4] = {"lp_down", "lp_up", "fb_down", "fb_up"};
+  static const char* tails[3] = {"tail_lp", "tail_fb_analysis", "tail_fb_synthesis"};
+  char buf[128];
+  int lev = 0;
+  while (lev < 31 && (g.n[2] >> lev) != (l.is_tail ? l.tail.b[2] : l.task.b[2])) ++lev;
+  snprintf(buf, sizeof buf, "%s_%dd_L%d_v%d%s", l.is_tail ? tails[l.kind] : kinds[l.kind], l.D, l.L, l.variant,
+           l.vec ? "" : "_scalar");
+  if (name && name_len) {
+    strncpy(name, buf, name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (work_groups) *work_groups = (l.is_tail ? 1 : (int64_t)l.task.tiles_per_inst) * batch;
+  if (level) *level = lev;
+  return ES_OK;
+}
+
+es_status es_schedule_run_step(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                               const float* in, float* out, void* ws, size_t ws_bytes, int32_t index, void* stream) {
+  if (op < 0 || op > 3) return fail(ES_EINVAL, "unknown op %d", op);
+  Geo g;
+  es_status st = make_geo(ndim, shape, order, levels, s, &g);
+  if (st != ES_OK) return st;
+  const size_t need = (size_t)(batch > 0 ? batch : 0) * (size_t)ws_floats_per_instance(g) * sizeof(float);
+  st = check_io(in, out, batch, g.N(), ws, ws_bytes, need);
+  if (st != ES_OK) return st;
+  if (batch < 1) return fail(ES_EINVAL, "batch must be >= 1");
+  st = check_device();
+  if (st != ES_OK) return st;
+  Schedule sc;
+  st = build_schedule(op, g, batch, in, out, (float*)ws, &sc);
+  if (st != ES_OK) return st;
+  if (sc.identity || index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
+  const Launch& l = sc.launches[index];
+  const int64_t total = (l.is_tail ? 1 : l.task.tiles_per_inst) * batch;
+  return run_launch(l, sc.f, (hipStream_t)stream, nullptr, 1, (int)total, nullptr);
+}
+
+es_status es_filter(int order, double* h_out) {
+  if (!h_out) return fail(ES_EINVAL, "h_out is NULL");
+  if (order < 1 || order > 8) return fail(ES_EINVAL, "order must be in 1..8 (got %d)", order);
+  if (!daubechies_filter(order, h_out)) return fail(ES_EUNSUPPORTED, "filter derivation failed for order %d", order);
+  return ES_OK;
+}
+
+es_status es_level_weights(int levels, double s, double tau, float* w_out) {
+  if (!w_out) return fail(ES_EINVAL, "w_out is NULL");
+  if (levels < 0 || levels > kMaxLevels) return fail(ES_EINVAL, "levels out of range");
+  if (!std::isfinite(s) || !std::isfinite(tau)) return fail(ES_EINVAL, "s and tau must be finite");
+  for (int i = 1; i <= levels; ++i) w_out[i - 1] = (float)std::exp2(-tau * s * (double)(levels - i));
+  w_out[levels] = 1.f;
+  return ES_OK;
+}
+
+const char* es_status_string(es_status st) {
+  switch (st) {
+    case ES_OK: return "ES_OK";
+    case ES_EINVAL: return "ES_EINVAL: invalid argument";
+    case ES_EWORKSPACE: return "ES_EWORKSPACE: workspace missing or too small";
+    case ES_EUNSUPPORTED: return "ES_EUNSUPPORTED: unsupported request";
+    case ES_EDEVICE: return "ES_EDEVICE: HIP runtime error";
+    case ES_ENOMEM: return "ES_ENOMEM: allocation failed";
+  }
+  return "unknown es_status";
+}
+
+const char* es_last_error(void) { return g_last_error.c_str(); }
+
+const char* es_version(void) { return "eswave 0.1 (gfx950)"; }
+
+}  // extern "C"
+

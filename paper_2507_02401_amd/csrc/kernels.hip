@@ -1,0 +1,1218 @@
+// gfx950 kernels of the wavelet E_s^* / Matern-prior path.
+//
+// Notation: L taps, h low-pass, g[t] = (-1)^t h[L-1-t] high-pass.  One periodic analysis step
+// along an axis of even length n is a[k] = sum_t h[t] x[(2k+t) mod n],
+// d[k] = sum_t g[t] x[(2k+t) mod n]; synthesis is its transpose.  (Sec. 4: the discrete
+// wavelet transform W and E_s^* X = W^{-1}(D (W X)).)
+//
+// Level kernels (one launch per level, every instance of a batch in the same launch):
+//   LP_DOWN  a_i = A a_{i-1}                    low-pass only, every axis in one kernel
+//   LP_UP    out = alpha*same + beta*A^T z      low-pass-only synthesis fused with the
+//                                               projection-form recurrence (see api.cpp)
+//   FB_DOWN  one full analysis level: 2^d bands, detail bands scaled, LL to the next level
+//   FB_UP    one full synthesis level: LL + scaled detail bands -> finer approximation
+// A work-group owns one output tile.  It stages the periodic input region (tile plus filter
+// halo) in LDS with 16-byte loads, filters the contiguous axis first and the strided axes
+// after, keeping each thread's filter window in registers, and writes the last pass straight
+// to global memory with lanes along the contiguous axis (coalesced).
+//
+// Tail kernels: once a level's block fits in LDS, one work-group per instance runs every
+// remaining level (down, scale and up) without leaving LDS.
+//
+// Plain kernels: one launch per 1-D pass over the whole level block, for comparison.
+#include "internal.h"
+
+namespace es {
+
+#define DEVI __device__ __forceinline__
+
+DEVI int pmod(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// ---------------------------------------------------------------------------------------
+// Work-group -> task/tile mapping.
+//
+// The hardware hands work-group i to XCD i mod 8.  Remapping gives each XCD a contiguous run
+// of logical tiles, so tiles that share filter halos share an L2.
+DEVI int logical_wg(int total_wg) {
+  const int grid = gridDim.x;  // padded to a multiple of 8 by the host
+  const int per = grid >> 3;
+  const int i = blockIdx.x;
+  const int l = (i & 7) * per + (i >> 3);
+  return l < total_wg ? l : -1;
+}
+
+template <class T, class A>
+DEVI T pick_task(const A& args, int wg) {
+  if (args.table == nullptr) return args.t0;
+  int lo = 0, hi = args.count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (args.table[mid].tile_begin <= wg) lo = mid;
+    else hi = mid - 1;
+  }
+  return args.table[lo];
+}
+
+struct Tile {
+  int inst, c0, c1, c2;
+};
+
+DEVI Tile decode_tile(const Task& t, int wg) {
+  const int local = wg - t.tile_begin;
+  Tile r;
+  r.inst = local / t.tiles_per_inst;
+  int rem = local - r.inst * t.tiles_per_inst;
+  r.c2 = rem % t.ntile[2];
+  rem /= t.ntile[2];
+  r.c1 = rem % t.ntile[1];
+  r.c0 = rem / t.ntile[1];
+  return r;
+}
+
+// ---------------------------------------------------------------------------------------
+// Register-window filter passes over lines of an LDS array.
+//
+// analysis_pass: line l, chunk ch: window samples s[j] = In(l, 2*P*ch + j), j < 2P+L-2;
+// outputs k = P*ch + q:  lo = sum_t h[t] s[2q+t],  hi = sum_t g[t] s[2q+t].
+// synthesis_pass: window samples lo/hi In(l, P*ch + j), j < P+L/2-1; outputs p = 2(P*ch+q)+e:
+//   x = sum_{j<L/2} h[2j+e] lo[q+L/2-1-j] + g[2j+e] hi[q+L/2-1-j].
+// LINES_FAST puts consecutive lanes on consecutive lines (strided passes: lines are columns
+// and LDS accesses are conflict-free); otherwise consecutive lanes take consecutive chunks
+// of one line (contiguous pass).
+
+template <int L, int P, bool FB, bool LINES_FAST, int NT, class In, class Out>
+DEVI void analysis_pass(int nlines, int nch, const Filter& f, In in, Out out) {
+  constexpr int W = 2 * P + L - 2;
+  const int ntask = nlines * nch;
+  for (int task = threadIdx.x; task < ntask; task += NT) {
+    int l, ch;
+    if (LINES_FAST) { l = task % nlines; ch = task / nlines; }
+    else { ch = task % nch; l = task / nch; }
+    float win[W + 3];
+    in(l, 2 * P * ch, win);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      float lo = 0.f, hi = 0.f;
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        lo = fmaf(f.h[t], win[2 * q + t], lo);
+        if (FB) hi = fmaf(f.g[t], win[2 * q + t], hi);
+      }
+      out(l, P * ch + q, lo, hi);
+    }
+  }
+}
+
+template <int L, int P, bool FB, bool LINES_FAST, int NT, class In, class Out>
+DEVI void synthesis_pass(int nlines, int nch, const Filter& f, In in, Out out) {
+  constexpr int H = L / 2;
+  constexpr int W = P + H - 1;
+  const int ntask = nlines * nch;
+  for (int task = threadIdx.x; task < ntask; task += NT) {
+    int l, ch;
+    if (LINES_FAST) { l = task % nlines; ch = task / nlines; }
+    else { ch = task % nch; l = task / nch; }
+    float lo[W], hi[FB ? W : 1];
+    in(l, P * ch, lo, hi);
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      float e0 = 0.f, e1 = 0.f;
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        const float a = lo[q + H - 1 - j];
+        e0 = fmaf(f.h[2 * j], a, e0);
+        e1 = fmaf(f.h[2 * j + 1], a, e1);
+        if (FB) {
+          const float d = hi[q + H - 1 - j];
+          e0 = fmaf(f.g[2 * j], d, e0);
+          e1 = fmaf(f.g[2 * j + 1], d, e1);
+        }
+      }
+      out(l, 2 * (P * ch + q), e0, e1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Geometry of a level kernel instantiation.
+//
+// Analysis kinds tile the half-resolution output: T_k outputs per dim, input region
+// I_k = 2 T_k + L - 2 starting at 2 T_k c_k.  Synthesis kinds tile the full-resolution output:
+// U_k outputs (even), half-resolution input region J_k = U_k/2 + L/2 - 1 starting at
+// c_k U_k/2 - (L/2 - 1).  Dims below 3-D are padded with extent 1 and skipped.
+
+template <int D, int L, int T0, int T1, int T2>
+struct DownGeom {
+  static constexpr int I0 = D >= 3 ? 2 * T0 + L - 2 : 1;
+  static constexpr int I1 = D >= 2 ? 2 * T1 + L - 2 : 1;
+  static constexpr int I2 = 2 * T2 + L - 2;
+  static constexpr int I2P = (I2 + 3) & ~3;
+  static constexpr int NV = I2P / 4;
+  static constexpr int NROW = I0 * I1;
+};
+
+template <int D, int L, int U0, int U1, int U2>
+struct UpGeom {
+  static constexpr int H = L / 2;
+  static constexpr int J0 = D >= 3 ? U0 / 2 + H - 1 : 1;
+  static constexpr int J1 = D >= 2 ? U1 / 2 + H - 1 : 1;
+  static constexpr int J2 = U2 / 2 + H - 1;
+  // the contiguous dim is loaded from a 4-aligned start, OFF samples before the region
+  static constexpr int OFF = (4 - ((H - 1) & 3)) & 3;
+  static constexpr int J2P = (J2 + OFF + 3) & ~3;
+  static constexpr int NV = J2P / 4;
+  static constexpr int NROW = J0 * J1;
+};
+
+// Stage a periodic region into LDS: rows given by a row-offset table, 16-byte columns by a
+// column table (element offsets), both already reduced modulo the block.
+template <int NT, bool VEC>
+DEVI void stage_rows(const float* __restrict__ src, const int* s_row, const int* s_col, int nrows, int nv,
+                     float* lds, int lds_row, int b2, float scale) {
+  if (VEC) {
+    float4* d4 = reinterpret_cast<float4*>(lds);
+    const int n = nrows * nv;
+    for (int q = threadIdx.x; q < n; q += NT) {
+      const int v = q % nv, r = q / nv;
+      float4 x = *reinterpret_cast<const float4*>(src + s_row[r] + s_col[v]);
+      if (scale != 1.f) { x.x *= scale; x.y *= scale; x.z *= scale; x.w *= scale; }
+      d4[r * (lds_row >> 2) + v] = x;
+    }
+  } else {
+    const int n = nrows * nv * 4;
+    for (int q = threadIdx.x; q < n; q += NT) {
+      const int e = q & 3, v = (q >> 2) % nv, r = (q >> 2) / nv;
+      const int col = pmod(s_col[v] + e, b2);  // s_col holds the unreduced aligned start here
+      lds[r * lds_row + 4 * v + e] = src[s_row[r] + col] * scale;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// LP_DOWN: a_out = A a_in on a (T0,T1,T2) tile of the half-resolution output.
+
+template <int D, int L, int T0, int T1, int T2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
+  using G = DownGeom<D, L, T0, T1, T2>;
+  constexpr int P2 = 4, P1 = 4, P0 = 2;
+  __shared__ __attribute__((aligned(16))) float s_in[G::NROW * G::I2P];
+  __shared__ float s_a[G::NROW * T2];
+  __shared__ float s_b[D >= 3 ? T0 * G::I1 * T2 : 1];
+  __shared__ int s_row[G::NROW];
+  __shared__ int s_col[G::NV];
+
+  const int wg = logical_wg(args.total_wg);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ src = t.in0 + tl.inst * t.bs_in0;
+  float* __restrict__ dst = t.out0 + tl.inst * t.bs_out0;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int o0 = 2 * T0 * tl.c0, o1 = 2 * T1 * tl.c1, o2 = 2 * T2 * tl.c2;
+
+  for (int i = threadIdx.x; i < G::NROW; i += NT) {
+    const int i1 = i % G::I1, i0 = i / G::I1;
+    s_row[i] = (D >= 3 ? pmod(o0 + i0, b0) * t.st_in0[0] : 0) + (D >= 2 ? pmod(o1 + i1, b1) * t.st_in0[1] : 0);
+  }
+  for (int i = threadIdx.x; i < G::NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
+  __syncthreads();
+  stage_rows<NT, VEC>(src, s_row, s_col, G::NROW, G::NV, s_in, G::I2P, b2, 1.f);
+  __syncthreads();
+
+  // contiguous dim: (NROW, I2) -> (NROW, T2)
+  analysis_pass<L, P2, false, false, NT>(
+      G::NROW, T2 / P2, f,
+      [&](int l, int j0, float* w) {
+        const float4* p = reinterpret_cast<const float4*>(s_in + l * G::I2P + j0);
+#pragma unroll
+        for (int v = 0; v < (2 * P2 + L - 2 + 3) / 4; ++v) {
+          const float4 x = p[v];
+          w[4 * v] = x.x; w[4 * v + 1] = x.y; w[4 * v + 2] = x.z; w[4 * v + 3] = x.w;
+        }
+      },
+      [&](int l, int k, float lo, float) { s_a[l * T2 + k] = lo; });
+  __syncthreads();
+
+  const int n1o = b1 >> 1, n2o = b2 >> 1, n0o = b0 >> 1;
+  if constexpr (D == 1) {
+    // already the output: (1, T2)
+    for (int k = threadIdx.x; k < T2; k += NT) {
+      const int g2 = T2 * tl.c2 + k;
+      if (g2 < n2o) dst[g2] = s_a[k];
+    }
+  } else if constexpr (D == 2) {
+    analysis_pass<L, P1, false, true, NT>(
+        T2, T1 / P1, f,
+        [&](int c, int j0, float* w) {
+#pragma unroll
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_a[(j0 + j) * T2 + c];
+        },
+        [&](int c, int k, float lo, float) {
+          const int g1 = T1 * tl.c1 + k, g2 = T2 * tl.c2 + c;
+          if (g1 < n1o && g2 < n2o) dst[g1 * n2o + g2] = lo;
+        });
+  } else {
+    // dim 0: (I0, I1, T2) -> (T0, I1, T2), lines are (i1, c)
+    analysis_pass<L, P0, false, true, NT>(
+        G::I1 * T2, T0 / P0, f,
+        [&](int l, int j0, float* w) {
+#pragma unroll
+          for (int j = 0; j < 2 * P0 + L - 2; ++j) w[j] = s_a[(j0 + j) * G::I1 * T2 + l];
+        },
+        [&](int l, int k, float lo, float) { s_b[k * G::I1 * T2 + l] = lo; });
+    __syncthreads();
+    // dim 1: (T0, I1, T2) -> (T0, T1, T2), lines are (k0, c)
+    analysis_pass<L, P1, false, true, NT>(
+        T0 * T2, T1 / P1, f,
+        [&](int l, int j0, float* w) {
+          const int c = l % T2, k0 = l / T2;
+#pragma unroll
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_b[(k0 * G::I1 + j0 + j) * T2 + c];
+        },
+        [&](int l, int k, float lo, float) {
+          const int c = l % T2, k0 = l / T2;
+          const int g0 = T0 * tl.c0 + k0, g1 = T1 * tl.c1 + k, g2 = T2 * tl.c2 + c;
+          if (g0 < n0o && g1 < n1o && g2 < n2o) dst[(g0 * n1o + g1) * n2o + g2] = lo;
+        });
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// LP_UP: out = alpha*same + beta*(A^T z) on a (U0,U1,U2) full-resolution tile.
+
+template <int D, int L, int U0, int U1, int U2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
+  using G = UpGeom<D, L, U0, U1, U2>;
+  constexpr int H = G::H;
+  constexpr int P2 = 4, P1 = 4, P0 = 2;
+  __shared__ __attribute__((aligned(16))) float s_in[G::NROW * G::J2P];
+  __shared__ float s_a[G::NROW * U2];
+  __shared__ float s_b[D >= 3 ? U0 * G::J1 * U2 : 1];
+  __shared__ int s_row[G::NROW];
+  __shared__ int s_col[G::NV];
+
+  const int wg = logical_wg(args.total_wg);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ z = t.in0 + tl.inst * t.bs_in0;
+  const float* same = t.in1 + tl.inst * t.bs_in1;  // may alias out (in-place z over a)
+  float* out = t.out0 + tl.inst * t.bs_out0;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int h0 = b0 >> 1, h1 = b1 >> 1, h2 = b2 >> 1;  // z dims
+  const int r0 = tl.c0 * (U0 / 2) - (H - 1), r1 = tl.c1 * (U1 / 2) - (H - 1);
+  const int r2 = tl.c2 * (U2 / 2) - (H - 1) - G::OFF;
+
+  for (int i = threadIdx.x; i < G::NROW; i += NT) {
+    const int i1 = i % G::J1, i0 = i / G::J1;
+    s_row[i] = (D >= 3 ? pmod(r0 + i0, h0) * (h1 * h2) : 0) + (D >= 2 ? pmod(r1 + i1, h1) * h2 : 0);
+  }
+  for (int i = threadIdx.x; i < G::NV; i += NT) s_col[i] = VEC ? pmod(r2 + 4 * i, h2) : r2 + 4 * i;
+  __syncthreads();
+  stage_rows<NT, VEC>(z, s_row, s_col, G::NROW, G::NV, s_in, G::J2P, h2, 1.f);
+  __syncthreads();
+
+  // contiguous dim: (NROW, J2) -> (NROW, U2)
+  synthesis_pass<L, P2, false, false, NT>(
+      G::NROW, U2 / 2 / P2, f,
+      [&](int l, int j0, float* lo, float*) {
+        const float* p = s_in + l * G::J2P + G::OFF + j0;
+#pragma unroll
+        for (int j = 0; j < P2 + H - 1; ++j) lo[j] = p[j];
+      },
+      [&](int l, int p, float e0, float e1) {
+        s_a[l * U2 + p] = e0;
+        s_a[l * U2 + p + 1] = e1;
+      });
+  __syncthreads();
+
+  const float alpha = t.alpha, beta = t.beta;
+  if constexpr (D == 1) {
+    for (int p = threadIdx.x; p < U2; p += NT) {
+      const int g2 = tl.c2 * U2 + p;
+      if (g2 < b2) out[g2] = fmaf(alpha, same[g2], beta * s_a[p]);
+    }
+  } else if constexpr (D == 2) {
+    synthesis_pass<L, P1, false, true, NT>(
+        U2, U1 / 2 / P1, f,
+        [&](int c, int j0, float* lo, float*) {
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) lo[j] = s_a[(j0 + j) * U2 + c];
+        },
+        [&](int c, int p, float e0, float e1) {
+          const int g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
+          if (g1 < b1 && g2 < b2) {
+            const int o = g1 * b2 + g2;
+            const float s0 = same[o], s1 = same[o + b2];
+            out[o] = fmaf(alpha, s0, beta * e0);
+            out[o + b2] = fmaf(alpha, s1, beta * e1);
+          }
+        });
+  } else {
+    // dim 0: (J0, J1, U2) -> (U0, J1, U2)
+    synthesis_pass<L, P0, false, true, NT>(
+        G::J1 * U2, U0 / 2 / P0, f,
+        [&](int l, int j0, float* lo, float*) {
+#pragma unroll
+          for (int j = 0; j < P0 + H - 1; ++j) lo[j] = s_a[(j0 + j) * G::J1 * U2 + l];
+        },
+        [&](int l, int p, float e0, float e1) {
+          s_b[p * G::J1 * U2 + l] = e0;
+          s_b[(p + 1) * G::J1 * U2 + l] = e1;
+        });
+    __syncthreads();
+    synthesis_pass<L, P1, false, true, NT>(
+        U0 * U2, U1 / 2 / P1, f,
+        [&](int l, int j0, float* lo, float*) {
+          const int c = l % U2, p0 = l / U2;
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) lo[j] = s_b[(p0 * G::J1 + j0 + j) * U2 + c];
+        },
+        [&](int l, int p, float e0, float e1) {
+          const int c = l % U2, p0 = l / U2;
+          const int g0 = tl.c0 * U0 + p0, g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
+          if (g0 < b0 && g1 < b1 && g2 < b2) {
+            const int o = (g0 * b1 + g1) * b2 + g2;
+            const float s0 = same[o], s1 = same[o + b2];
+            out[o] = fmaf(alpha, s0, beta * e0);
+            out[o + b2] = fmaf(alpha, s1, beta * e1);
+          }
+        });
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// FB_DOWN: one full analysis level on a (T0,T1,T2) tile of every band.
+// Bands go to out0 (packed coefficient array, strides st_out0, detail bands x alpha) except
+// the all-low band, which goes to out1 (next level's approximation, strides st_out1, x beta).
+
+template <int D, int L, int T0, int T1, int T2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
+  using G = DownGeom<D, L, T0, T1, T2>;
+  constexpr int P2 = 4, P1 = 4, P0 = 2;
+  constexpr int T2x = 2 * T2;  // [lo | hi] along the contiguous dim
+  __shared__ __attribute__((aligned(16))) float s_in[G::NROW * G::I2P];
+  __shared__ float s_a[G::NROW * T2x];
+  __shared__ float s_b[D >= 3 ? 2 * T0 * G::I1 * T2x : 1];
+  __shared__ int s_row[G::NROW];
+  __shared__ int s_col[G::NV];
+
+  const int wg = logical_wg(args.total_wg);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ src = t.in0 + tl.inst * t.bs_in0;
+  float* __restrict__ coef = t.out0 + tl.inst * t.bs_out0;
+  float* __restrict__ ll = t.out1 + tl.inst * t.bs_out1;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int o0 = 2 * T0 * tl.c0, o1 = 2 * T1 * tl.c1, o2 = 2 * T2 * tl.c2;
+
+  for (int i = threadIdx.x; i < G::NROW; i += NT) {
+    const int i1 = i % G::I1, i0 = i / G::I1;
+    s_row[i] = (D >= 3 ? pmod(o0 + i0, b0) * t.st_in0[0] : 0) + (D >= 2 ? pmod(o1 + i1, b1) * t.st_in0[1] : 0);
+  }
+  for (int i = threadIdx.x; i < G::NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
+  __syncthreads();
+  stage_rows<NT, VEC>(src, s_row, s_col, G::NROW, G::NV, s_in, G::I2P, b2, 1.f);
+  __syncthreads();
+
+  analysis_pass<L, P2, true, false, NT>(
+      G::NROW, T2 / P2, f,
+      [&](int l, int j0, float* w) {
+        const float4* p = reinterpret_cast<const float4*>(s_in + l * G::I2P + j0);
+#pragma unroll
+        for (int v = 0; v < (2 * P2 + L - 2 + 3) / 4; ++v) {
+          const float4 x = p[v];
+          w[4 * v] = x.x; w[4 * v + 1] = x.y; w[4 * v + 2] = x.z; w[4 * v + 3] = x.w;
+        }
+      },
+      [&](int l, int k, float lo, float hi) {
+        s_a[l * T2x + k] = lo;
+        s_a[l * T2x + T2 + k] = hi;
+      });
+  __syncthreads();
+
+  const int n0h = b0 >> 1, n1h = b1 >> 1, n2h = b2 >> 1;
+  const float alpha = t.alpha, beta = t.beta;
+  // write one coefficient of band (e0,e1,e2) at half-res position (g0,g1,g2)
+  auto emit = [&](int e0, int e1, int e2, int g0, int g1, int g2, float v) {
+    if (g0 >= (D >= 3 ? n0h : 1) || g1 >= (D >= 2 ? n1h : 1) || g2 >= n2h) return;
+    if ((e0 | e1 | e2) == 0) {
+      ll[(D >= 3 ? g0 * t.st_out1[0] : 0) + (D >= 2 ? g1 * t.st_out1[1] : 0) + g2] = beta * v;
+    } else {
+      const int r0 = e0 * n0h + g0, r1 = e1 * n1h + g1, r2 = e2 * n2h + g2;
+      coef[(D >= 3 ? r0 * t.st_out0[0] : 0) + (D >= 2 ? r1 * t.st_out0[1] : 0) + r2] = alpha * v;
+    }
+  };
+
+  if constexpr (D == 1) {
+    for (int c = threadIdx.x; c < T2x; c += NT) {
+      const int e2 = c >= T2, k = c - e2 * T2;
+      emit(0, 0, e2, 0, 0, T2 * tl.c2 + k, s_a[c]);
+    }
+  } else if constexpr (D == 2) {
+    analysis_pass<L, P1, true, true, NT>(
+        T2x, T1 / P1, f,
+        [&](int c, int j0, float* w) {
+#pragma unroll
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_a[(j0 + j) * T2x + c];
+        },
+        [&](int c, int k, float lo, float hi) {
+          const int e2 = c >= T2, g2 = T2 * tl.c2 + c - e2 * T2, g1 = T1 * tl.c1 + k;
+          emit(0, 0, e2, 0, g1, g2, lo);
+          emit(0, 1, e2, 0, g1, g2, hi);
+        });
+  } else {
+    constexpr int T0x = 2 * T0;
+    analysis_pass<L, P0, true, true, NT>(
+        G::I1 * T2x, T0 / P0, f,
+        [&](int l, int j0, float* w) {
+#pragma unroll
+          for (int j = 0; j < 2 * P0 + L - 2; ++j) w[j] = s_a[(j0 + j) * G::I1 * T2x + l];
+        },
+        [&](int l, int k, float lo, float hi) {
+          s_b[k * G::I1 * T2x + l] = lo;
+          s_b[(T0 + k) * G::I1 * T2x + l] = hi;
+        });
+    __syncthreads();
+    analysis_pass<L, P1, true, true, NT>(
+        T0x * T2x, T1 / P1, f,
+        [&](int l, int j0, float* w) {
+          const int c = l % T2x, k0 = l / T2x;
+#pragma unroll
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_b[(k0 * G::I1 + j0 + j) * T2x + c];
+        },
+        [&](int l, int k, float lo, float hi) {
+          const int c = l % T2x, k0x = l / T2x;
+          const int e2 = c >= T2, e0 = k0x >= T0;
+          const int g2 = T2 * tl.c2 + c - e2 * T2, g0 = T0 * tl.c0 + k0x - e0 * T0, g1 = T1 * tl.c1 + k;
+          emit(e0, 0, e2, g0, g1, g2, lo);
+          emit(e0, 1, e2, g0, g1, g2, hi);
+        });
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// FB_UP: one full synthesis level on a (U0,U1,U2) full-resolution tile.
+// in0: approximation of the level (strides st_in0, x beta); in1: packed coefficient array
+// (strides st_in1; detail bands x alpha); out0: finer approximation (strides st_out0).
+
+template <int D, int L, int U0, int U1, int U2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
+  using G = UpGeom<D, L, U0, U1, U2>;
+  constexpr int H = G::H;
+  constexpr int P2 = 4, P1 = 4, P0 = 2;
+  constexpr int NB = 1 << D;           // bands
+  constexpr int NRB = G::NROW * NB / 2;  // staged rows: (e0, j0, e1, j1) for both e2
+  // LDS rows: index ((e0*J0 + j0)*2*J1 + e1*J1 + j1) * 2 + e2, each J2P long
+  __shared__ __attribute__((aligned(16))) float s_in[NRB * 2 * G::J2P];
+  __shared__ float s_a[NRB * U2];
+  __shared__ float s_b[D >= 3 ? U0 * 2 * G::J1 * U2 : 1];
+  __shared__ int s_rowc[NRB];  // offset into in1 of staged row r (band rows of e0,e1)
+  __shared__ int s_rowl[NRB];  // offset into in0 when e0 = e1 = 0, else -1
+  __shared__ int s_col[2 * G::NV];
+
+  const int wg = logical_wg(args.total_wg);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ ap = t.in0 + tl.inst * t.bs_in0;
+  const float* __restrict__ cp = t.in1 + tl.inst * t.bs_in1;
+  float* __restrict__ out = t.out0 + tl.inst * t.bs_out0;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int h0 = b0 >> 1, h1 = b1 >> 1, h2 = b2 >> 1;
+  const int r0 = tl.c0 * (U0 / 2) - (H - 1), r1 = tl.c1 * (U1 / 2) - (H - 1);
+  const int r2 = tl.c2 * (U2 / 2) - (H - 1) - G::OFF;
+  constexpr int E0 = D >= 3 ? 2 : 1, E1 = D >= 2 ? 2 : 1;
+
+  for (int i = threadIdx.x; i < NRB; i += NT) {
+    int rem = i;
+    const int j1 = rem % G::J1; rem /= G::J1;
+    const int e1 = rem % E1; rem /= E1;
+    const int j0 = rem % G::J0; rem /= G::J0;
+    const int e0 = rem;
+    const int q0 = pmod(r0 + j0, D >= 3 ? h0 : 1), q1 = pmod(r1 + j1, D >= 2 ? h1 : 1);
+    s_rowc[i] = (D >= 3 ? (e0 * h0 + q0) * t.st_in1[0] : 0) + (D >= 2 ? (e1 * h1 + q1) * t.st_in1[1] : 0);
+    s_rowl[i] = (e0 | e1) ? -1 : (D >= 3 ? q0 * t.st_in0[0] : 0) + (D >= 2 ? q1 * t.st_in0[1] : 0);
+  }
+  for (int i = threadIdx.x; i < 2 * G::NV; i += NT) {
+    const int e2 = i / G::NV, v = i % G::NV;
+    s_col[i] = VEC ? pmod(r2 + 4 * v, h2) + e2 * h2 : r2 + 4 * v;
+  }
+  __syncthreads();
+  {
+    const float alpha = t.alpha, beta = t.beta;
+    if (VEC) {
+      const int n = NRB * 2 * G::NV;
+      float4* d4 = reinterpret_cast<float4*>(s_in);
+      for (int q = threadIdx.x; q < n; q += NT) {
+        const int v = q % G::NV, re = q / G::NV;  // re = row*2 + e2
+        const int e2 = re & 1, row = re >> 1;
+        float4 x;
+        float sc;
+        if (e2 == 0 && s_rowl[row] >= 0) {
+          x = *reinterpret_cast<const float4*>(ap + s_rowl[row] + s_col[v]);
+          sc = beta;
+        } else {
+          x = *reinterpret_cast<const float4*>(cp + s_rowc[row] + s_col[e2 * G::NV + v]);
+          sc = alpha;
+        }
+        x.x *= sc; x.y *= sc; x.z *= sc; x.w *= sc;
+        d4[re * (G::J2P / 4) + v] = x;
+      }
+    } else {
+      const int n = NRB * 2 * G::J2P;
+      for (int q = threadIdx.x; q < n; q += NT) {
+        const int c = q % G::J2P, re = q / G::J2P;
+        const int e2 = re & 1, row = re >> 1;
+        const int col = pmod(r2 + c, h2);
+        float v;
+        if (e2 == 0 && s_rowl[row] >= 0) v = beta * ap[s_rowl[row] + col];
+        else v = alpha * cp[s_rowc[row] + e2 * h2 + col];
+        s_in[re * G::J2P + c] = v;
+      }
+    }
+  }
+  __syncthreads();
+
+  synthesis_pass<L, P2, true, false, NT>(
+      NRB, U2 / 2 / P2, f,
+      [&](int l, int j0, float* lo, float* hi) {
+        const float* p = s_in + (2 * l) * G::J2P + G::OFF + j0;
+#pragma unroll
+        for (int j = 0; j < P2 + H - 1; ++j) { lo[j] = p[j]; hi[j] = p[G::J2P + j]; }
+      },
+      [&](int l, int p, float e0, float e1) {
+        s_a[l * U2 + p] = e0;
+        s_a[l * U2 + p + 1] = e1;
+      });
+  __syncthreads();
+
+  if constexpr (D == 1) {
+    for (int p = threadIdx.x; p < U2; p += NT) {
+      const int g2 = tl.c2 * U2 + p;
+      if (g2 < b2) out[g2] = s_a[p];
+    }
+  } else if constexpr (D == 2) {
+    // rows of s_a: (e1, j1); lines are columns c
+    synthesis_pass<L, P1, true, true, NT>(
+        U2, U1 / 2 / P1, f,
+        [&](int c, int j0, float* lo, float* hi) {
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) {
+            lo[j] = s_a[(j0 + j) * U2 + c];
+            hi[j] = s_a[(G::J1 + j0 + j) * U2 + c];
+          }
+        },
+        [&](int c, int p, float e0, float e1) {
+          const int g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
+          if (g1 < b1 && g2 < b2) {
+            out[g1 * t.st_out0[1] + g2] = e0;
+            out[(g1 + 1) * t.st_out0[1] + g2] = e1;
+          }
+        });
+  } else {
+    // s_a rows: (e0, j0, e1, j1); dim 0 first -> s_b rows (p0, e1, j1)
+    constexpr int R1 = 2 * G::J1;  // (e1, j1)
+    synthesis_pass<L, P0, true, true, NT>(
+        R1 * U2, U0 / 2 / P0, f,
+        [&](int l, int j0, float* lo, float* hi) {
+#pragma unroll
+          for (int j = 0; j < P0 + H - 1; ++j) {
+            lo[j] = s_a[(j0 + j) * R1 * U2 + l];
+            hi[j] = s_a[(G::J0 + j0 + j) * R1 * U2 + l];
+          }
+        },
+        [&](int l, int p, float e0, float e1) {
+          s_b[p * R1 * U2 + l] = e0;
+          s_b[(p + 1) * R1 * U2 + l] = e1;
+        });
+    __syncthreads();
+    synthesis_pass<L, P1, true, true, NT>(
+        U0 * U2, U1 / 2 / P1, f,
+        [&](int l, int j0, float* lo, float* hi) {
+          const int c = l % U2, p0 = l / U2;
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) {
+            lo[j] = s_b[(p0 * R1 + j0 + j) * U2 + c];
+            hi[j] = s_b[(p0 * R1 + G::J1 + j0 + j) * U2 + c];
+          }
+        },
+        [&](int l, int p, float e0, float e1) {
+          const int c = l % U2, p0 = l / U2;
+          const int g0 = tl.c0 * U0 + p0, g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
+          if (g0 < b0 && g1 < b1 && g2 < b2) {
+            const int o = g0 * t.st_out0[0] + g1 * t.st_out0[1] + g2;
+            out[o] = e0;
+            out[o + t.st_out0[1]] = e1;
+          }
+        });
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Tail kernels: every remaining level of one instance inside one work-group's LDS.
+// Block sides may be shorter than the filter (periodic folding through the modulo).
+
+constexpr int kTailThreads = 512;
+
+struct Blk {
+  int n[3];
+  DEVI int size() const { return n[0] * n[1] * n[2]; }
+};
+
+// One 1-D pass along `ax` on a block laid out with strides (sr0, sr1, 1) in src and
+// (sd0, sd1, 1) in dst.  Analysis (FB=false: low-pass only, output extent n/2 along ax;
+// FB=true: [lo | hi]).  Synthesis reads [lo | hi] (or lo only) of half extent.
+template <int L, bool FB>
+DEVI void tail_analysis_axis(const float* src, int sr0, int sr1, float* dst, int sd0, int sd1, Blk b, int ax,
+                             const Filter& f) {
+  const int n = b.n[ax], half = n >> 1;
+  Blk o = b;
+  o.n[ax] = half;
+  const int total = o.size();
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c2 = e % o.n[2], r = e / o.n[2];
+    int c1 = r % o.n[1], c0 = r / o.n[1];
+    int c[3] = {c0, c1, c2};
+    const int k = c[ax];
+    const int step = ax == 0 ? sr0 : (ax == 1 ? sr1 : 1);
+    c[ax] = 0;
+    const float* base = src + c[0] * sr0 + c[1] * sr1 + c[2];
+    float lo = 0.f, hi = 0.f;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const float x = base[((2 * k + t) % n) * step];
+      lo = fmaf(f.h[t], x, lo);
+      if (FB) hi = fmaf(f.g[t], x, hi);
+    }
+    const int dstep = ax == 0 ? sd0 : (ax == 1 ? sd1 : 1);
+    float* d = dst + c[0] * sd0 + c[1] * sd1 + c[2];
+    d[k * dstep] = lo;
+    if (FB) d[(half + k) * dstep] = hi;
+  }
+}
+
+// Synthesis along `ax`: output block b (full extent n along ax); input has [lo | hi] (FB) or
+// lo only (extent n/2) along ax.  mode: 0 store, 1 dst = alpha*dst_same + beta*val where
+// dst_same is read from `same` with dst strides.
+template <int L, bool FB>
+DEVI void tail_synthesis_axis(const float* src, int sr0, int sr1, float* dst, int sd0, int sd1, Blk b, int ax,
+                              const Filter& f, const float* same, float alpha, float beta) {
+  const int n = b.n[ax], half = n >> 1;
+  const int total = b.size();
+  const int step = ax == 0 ? sr0 : (ax == 1 ? sr1 : 1);
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c2 = e % b.n[2], r = e / b.n[2];
+    int c1 = r % b.n[1], c0 = r / b.n[1];
+    int c[3] = {c0, c1, c2};
+    const int p = c[ax];
+    c[ax] = 0;
+    const float* base = src + c[0] * sr0 + c[1] * sr1 + c[2];
+    float acc = 0.f;
+    // x[p] = sum_k sum_t [ (2k+t) mod n == p ] (h[t] lo[k] + g[t] hi[k])
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      // k with 2k + t == p (mod n): 2k == p - t (mod n); solvable iff p - t even
+      const int dlt = p - t;
+      if (dlt & 1) continue;
+      const int k = pmod(dlt >> 1, half);
+      acc = fmaf(f.h[t], base[k * step], acc);
+      if (FB) acc = fmaf(f.g[t], base[(half + k) * step], acc);
+    }
+    // when n < L several taps land on the same k; each (t, k) pair is visited once above
+    const int o = c0 * sd0 + c1 * sd1 + c2;
+    if (same) dst[o] = fmaf(alpha, same[o], beta * acc);
+    else dst[o] = acc;
+  }
+}
+
+// Weight of the packed-pyramid element at (c0,c1,c2) of a tail block: tail level j detail
+// -> coef[j]; approximation (inside block >> nlev) -> coef[nlev].
+DEVI float tail_weight(const float* coef, int nlev, Blk b, int c0, int c1, int c2, int D) {
+  int j = 0;
+  while (j < nlev) {
+    const int s = j + 1;
+    const bool inside = (c2 < (b.n[2] >> s)) && (D < 2 || c1 < (b.n[1] >> s)) && (D < 3 || c0 < (b.n[0] >> s));
+    if (!inside) break;
+    ++j;
+  }
+  return coef[j];
+}
+
+template <int D>
+DEVI Blk half_blk(Blk b) {
+  Blk o = b;
+  o.n[2] >>= 1;
+  if (D >= 2) o.n[1] >>= 1;
+  if (D >= 3) o.n[0] >>= 1;
+  return o;
+}
+
+// Low-pass projection-form tail (cov / sample).
+template <int D, int L>
+__global__ void __launch_bounds__(kTailThreads) k_tail_lp(TailArgs args, Filter f) {
+  extern __shared__ float lds[];
+  const int wg = logical_wg(args.total_wg);
+  if (wg < 0) return;
+  const TailTask t = pick_task<TailTask>(args, wg);
+  const int inst = wg - t.tile_begin;
+  const float* in = t.in + inst * t.bs_in;
+  float* out = t.out + inst * t.bs_out;
+  const int K = t.nlev;
+  Blk lev[32];
+  lev[0] = Blk{{t.b[0], t.b[1], t.b[2]}};
+  for (int j = 1; j <= K; ++j) lev[j] = half_blk<D>(lev[j - 1]);
+  // LDS: A[0..K] back to back, then tmpA, tmpB (each half of A[0])
+  float* A[32];
+  int off = 0;
+  for (int j = 0; j <= K; ++j) { A[j] = lds + off; off += lev[j].size(); }
+  float* tmpA = lds + off;
+  float* tmpB = tmpA + (lev[0].size() >> 1);
+  const Blk b0 = lev[0];
+  // load a_T (contiguous)
+  for (int e = threadIdx.x; e < b0.size(); e += blockDim.x) A[0][e] = in[e];
+  __syncthreads();
+  // down
+  for (int j = 0; j < K; ++j) {
+    Blk cur = lev[j];
+    // dim 2
+    Blk o2 = cur; o2.n[2] >>= 1;
+    float* dst2 = (D == 1) ? A[j + 1] : tmpA;
+    tail_analysis_axis<L, false>(A[j], cur.n[1] * cur.n[2], cur.n[2], dst2, o2.n[1] * o2.n[2], o2.n[2], cur, 2, f);
+    __syncthreads();
+    if (D >= 2) {
+      Blk o1 = o2; o1.n[1] >>= 1;
+      float* dst1 = (D == 2) ? A[j + 1] : tmpB;
+      tail_analysis_axis<L, false>(tmpA, o2.n[1] * o2.n[2], o2.n[2], dst1, o1.n[1] * o1.n[2], o1.n[2], o2, 1, f);
+      __syncthreads();
+      if (D >= 3) {
+        Blk o0 = o1; o0.n[0] >>= 1;
+        tail_analysis_axis<L, false>(tmpB, o1.n[1] * o1.n[2], o1.n[2], A[j + 1], o0.n[1] * o0.n[2], o0.n[2], o1, 0,
+                                     f);
+        __syncthreads();
+      }
+    }
+  }
+  // z_{m-1} = c_{m-1} a_{m-1}
+  for (int e = threadIdx.x; e < lev[K].size(); e += blockDim.x) A[K][e] *= t.coef[K];
+  __syncthreads();
+  // up: A[j] = coef[j] A[j] + A^T A[j+1]; j = 0 goes to global
+  for (int j = K - 1; j >= 0; --j) {
+    const Blk cur = lev[j];   // output dims
+    const Blk hz = lev[j + 1];
+    const bool last = (j == 0);
+    float* dst = last ? out : A[j];
+    const float* same = A[j];
+    const float alpha = t.coef[j];
+    if (D == 1) {
+      tail_synthesis_axis<L, false>(A[j + 1], 0, 0, dst, 0, 0, cur, 2, f, same, alpha, 1.f);
+      __syncthreads();
+    } else if (D == 2) {
+      // dim 2 first: (h1, h2) -> (h1, 2 h2) in tmpA
+      Blk m1 = hz; m1.n[2] = cur.n[2];
+      tail_synthesis_axis<L, false>(A[j + 1], hz.n[1] * hz.n[2], hz.n[2], tmpA, m1.n[1] * m1.n[2], m1.n[2], m1, 2, f,
+                                    nullptr, 0.f, 1.f);
+      __syncthreads();
+      tail_synthesis_axis<L, false>(tmpA, m1.n[1] * m1.n[2], m1.n[2], dst, cur.n[1] * cur.n[2], cur.n[2], cur, 1, f,
+                                    same, alpha, 1.f);
+      __syncthreads();
+    } else {
+      Blk m1 = hz; m1.n[2] = cur.n[2];
+      tail_synthesis_axis<L, false>(A[j + 1], hz.n[1] * hz.n[2], hz.n[2], tmpA, m1.n[1] * m1.n[2], m1.n[2], m1, 2, f,
+                                    nullptr, 0.f, 1.f);
+      __syncthreads();
+      Blk m2 = m1; m2.n[1] = cur.n[1];
+      tail_synthesis_axis<L, false>(tmpA, m1.n[1] * m1.n[2], m1.n[2], tmpB, m2.n[1] * m2.n[2], m2.n[2], m2, 1, f,
+                                    nullptr, 0.f, 1.f);
+      __syncthreads();
+      tail_synthesis_axis<L, false>(tmpB, m2.n[1] * m2.n[2], m2.n[2], dst, cur.n[1] * cur.n[2], cur.n[2], cur, 0, f,
+                                    same, alpha, 1.f);
+      __syncthreads();
+    }
+  }
+}
+
+// Full-bank tail.  SYN = false: analysis of levels T+1..m from a_T (contiguous `in`) into the
+// packed coefficient block (strided `out`).  SYN = true: synthesis from the packed block
+// (strided `in`) down to a_T (contiguous `out`, or strided when st_out is set).
+template <int D, int L, bool SYN>
+__global__ void __launch_bounds__(kTailThreads) k_tail_fb(TailArgs args, Filter f) {
+  extern __shared__ float lds[];
+  const int wg = logical_wg(args.total_wg);
+  if (wg < 0) return;
+  const TailTask t = pick_task<TailTask>(args, wg);
+  const int inst = wg - t.tile_begin;
+  const float* in = t.in + inst * t.bs_in;
+  float* out = t.out + inst * t.bs_out;
+  const Blk B = Blk{{t.b[0], t.b[1], t.b[2]}};
+  const int S0 = B.n[1] * B.n[2], S1 = B.n[2];  // LDS strides of the packed block
+  float* cur = lds;
+  float* tmp = lds + B.size();
+  const int nl = t.nlev;
+
+  if (!SYN) {
+    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) cur[e] = in[e];
+    __syncthreads();
+    Blk sb = B;
+    for (int j = 0; j < nl; ++j) {
+      // passes dim 2 (cur->tmp), dim 1 (tmp->cur), dim 0 (cur->tmp); copy back if needed
+      tail_analysis_axis<L, true>(cur, S0, S1, tmp, S0, S1, sb, 2, f);
+      __syncthreads();
+      float* res = tmp;
+      if (D >= 2) {
+        tail_analysis_axis<L, true>(tmp, S0, S1, cur, S0, S1, sb, 1, f);
+        __syncthreads();
+        res = cur;
+        if (D >= 3) {
+          tail_analysis_axis<L, true>(cur, S0, S1, tmp, S0, S1, sb, 0, f);
+          __syncthreads();
+          res = tmp;
+        }
+      }
+      if (res != cur) {
+        for (int e = threadIdx.x; e < sb.size(); e += blockDim.x) {
+          const int c2 = e % sb.n[2], r = e / sb.n[2], c1 = r % sb.n[1], c0 = r / sb.n[1];
+          const int o = c0 * S0 + c1 * S1 + c2;
+          cur[o] = tmp[o];
+        }
+        __syncthreads();
+      }
+      sb = half_blk<D>(sb);
+    }
+    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) {
+      const int c2 = e % B.n[2], r = e / B.n[2], c1 = r % B.n[1], c0 = r / B.n[1];
+      const float w = tail_weight(t.coef, nl, B, c0, c1, c2, D);
+      out[(D >= 3 ? c0 * t.st_out[0] : 0) + (D >= 2 ? c1 * t.st_out[1] : 0) + c2] = w * cur[e];
+    }
+  } else {
+    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) {
+      const int c2 = e % B.n[2], r = e / B.n[2], c1 = r % B.n[1], c0 = r / B.n[1];
+      const float w = tail_weight(t.coef, nl, B, c0, c1, c2, D);
+      cur[e] = w * in[(D >= 3 ? c0 * t.st_in[0] : 0) + (D >= 2 ? c1 * t.st_in[1] : 0) + c2];
+    }
+    __syncthreads();
+    for (int j = nl - 1; j >= 0; --j) {
+      Blk sb = B;
+      for (int q = 0; q < j; ++q) sb = half_blk<D>(sb);
+      // passes in reverse: dim 0 (3-D), dim 1, dim 2; ping-pong cur/tmp
+      float* a = cur;
+      float* bb = tmp;
+      if (D >= 3) {
+        tail_synthesis_axis<L, true>(a, S0, S1, bb, S0, S1, sb, 0, f, nullptr, 0.f, 1.f);
+        __syncthreads();
+        float* s = a; a = bb; bb = s;
+      }
+      if (D >= 2) {
+        tail_synthesis_axis<L, true>(a, S0, S1, bb, S0, S1, sb, 1, f, nullptr, 0.f, 1.f);
+        __syncthreads();
+        float* s = a; a = bb; bb = s;
+      }
+      tail_synthesis_axis<L, true>(a, S0, S1, bb, S0, S1, sb, 2, f, nullptr, 0.f, 1.f);
+      __syncthreads();
+      if (bb != cur) {
+        for (int e = threadIdx.x; e < sb.size(); e += blockDim.x) {
+          const int c2 = e % sb.n[2], r = e / sb.n[2], c1 = r % sb.n[1], c0 = r / sb.n[1];
+          const int o = c0 * S0 + c1 * S1 + c2;
+          cur[o] = bb[o];
+        }
+        __syncthreads();
+      }
+    }
+    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) {
+      const int c2 = e % B.n[2], r = e / B.n[2], c1 = r % B.n[1], c0 = r / B.n[1];
+      out[(D >= 3 ? c0 * t.st_out[0] : 0) + (D >= 2 ? c1 * t.st_out[1] : 0) + c2] = cur[e];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Plain reference kernels: one thread per output pair of one 1-D pass over the level block.
+
+template <int L>
+__global__ void __launch_bounds__(256) k_plain_pass(PlainPass p, Filter f) {
+  const int ax = p.axis;
+  const int n = p.b[ax], half = n >> 1;
+  int hb[3] = {p.b[0], p.b[1], p.b[2]};
+  hb[ax] = half;
+  const int64_t total = (int64_t)hb[0] * hb[1] * hb[2];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int c2 = (int)(e % hb[2]);
+  int64_t r = e / hb[2];
+  int c1 = (int)(r % hb[1]);
+  int c0 = (int)(r / hb[1]);
+  int c[3] = {c0, c1, c2};
+  const int k = c[ax];
+  c[ax] = 0;
+  const int ss = ax == 0 ? p.st_src[0] : (ax == 1 ? p.st_src[1] : 1);
+  const int ds = ax == 0 ? p.st_dst[0] : (ax == 1 ? p.st_dst[1] : 1);
+  const float* src = p.src + (int64_t)c[0] * p.st_src[0] + (int64_t)c[1] * p.st_src[1] + c[2];
+  float* dst = p.dst + (int64_t)c[0] * p.st_dst[0] + (int64_t)c[1] * p.st_dst[1] + c[2];
+  // an element is "low" when it lies in the all-low sub-block of the level block
+  auto low_other = [&]() {
+    for (int a = 0; a < 3; ++a) {
+      if (a == ax) continue;
+      if (a < 3 - p.ndim) continue;
+      const int ca = a == 0 ? c0 : (a == 1 ? c1 : c2);
+      if (ca >= (p.b[a] >> 1)) return false;
+    }
+    return true;
+  };
+  if (!p.synth) {
+    float lo = 0.f, hi = 0.f;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      const float x = src[(int64_t)((2 * k + t) % n) * ss];
+      lo = fmaf(f.h[t], x, lo);
+      hi = fmaf(f.g[t], x, hi);
+    }
+    if (p.scale_mode == 1) {
+      if (!low_other()) lo *= p.w;
+      hi *= p.w;
+    }
+    dst[(int64_t)k * ds] = lo;
+    dst[(int64_t)(half + k) * ds] = hi;
+  } else {
+    const bool lo_scaled = (p.scale_mode == 2) && !low_other();
+    const float wl = lo_scaled ? p.w : 1.f, wh = (p.scale_mode == 2) ? p.w : 1.f;
+    float x0 = 0.f, x1 = 0.f;  // outputs 2k and 2k+1
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      // output q = 2k + e receives h[t] lo[j] + g[t] hi[j] for 2j + t == q (mod n)
+      const int e0 = 2 * k - t, e1 = 2 * k + 1 - t;
+      if ((e0 & 1) == 0) {
+        const int j = pmod(e0 >> 1, half);
+        x0 = fmaf(f.h[t], wl * src[(int64_t)j * ss], x0);
+        x0 = fmaf(f.g[t], wh * src[(int64_t)(half + j) * ss], x0);
+      } else {
+        const int j = pmod((e1) >> 1, half);
+        x1 = fmaf(f.h[t], wl * src[(int64_t)j * ss], x1);
+        x1 = fmaf(f.g[t], wh * src[(int64_t)(half + j) * ss], x1);
+      }
+    }
+    dst[(int64_t)(2 * k) * ds] = x0;
+    dst[(int64_t)(2 * k + 1) * ds] = x1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_block_copy(const float* src, float* dst, int b0, int b1, int b2, int s0,
+                                                     int s1, int d0, int d1) {
+  const int64_t total = (int64_t)b0 * b1 * b2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int c2 = (int)(e % b2);
+  const int64_t r = e / b2;
+  const int c1 = (int)(r % b1), c0 = (int)(r / b1);
+  dst[(int64_t)c0 * d0 + (int64_t)c1 * d1 + c2] = src[(int64_t)c0 * s0 + (int64_t)c1 * s1 + c2];
+}
+
+__global__ void __launch_bounds__(256) k_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// Tile shapes and launch dispatch.
+
+namespace {
+
+// (kind, ndim, variant, taps) -> tile.  Variant 0 = wide, 1 = narrow (thin or small blocks).
+// Analysis kinds: half-res output tile per band; synthesis kinds: full-res output tile.
+struct Shape3 {
+  int a, b, c;
+};
+constexpr Shape3 shape_of(int K, int D, int V, int L) {
+  if (D == 1) return (K == K_LP_DOWN || K == K_FB_DOWN) ? (V == 0 ? Shape3{1, 1, 256} : Shape3{1, 1, 64})
+                                                          : (V == 0 ? Shape3{1, 1, 512} : Shape3{1, 1, 128});
+  if (D == 2) {
+    switch (K) {
+      case K_LP_DOWN: return V == 0 ? Shape3{1, 32, 64} : Shape3{1, 8, 16};
+      case K_LP_UP: return V == 0 ? Shape3{1, 64, 128} : Shape3{1, 16, 32};
+      case K_FB_DOWN: return V == 0 ? Shape3{1, 16, 32} : Shape3{1, 8, 16};
+      default: return V == 0 ? Shape3{1, 32, 64} : Shape3{1, 16, 32};
+    }
+  }
+  switch (K) {
+    case K_LP_DOWN: return V == 0 ? (L <= 8 ? Shape3{4, 8, 16} : Shape3{2, 4, 16}) : Shape3{2, 4, 8};
+    case K_LP_UP: return V == 0 ? Shape3{4, 16, 32} : Shape3{4, 8, 16};
+    case K_FB_DOWN: return V == 0 ? (L <= 8 ? Shape3{2, 8, 16} : Shape3{2, 4, 8}) : Shape3{2, 4, 8};
+    default: return V == 0 ? (L <= 8 ? Shape3{4, 16, 16} : Shape3{4, 8, 16}) : Shape3{4, 8, 16};
+  }
+}
+constexpr int kThreads = 256;
+
+#define ES_TILE(K, D, V, L) shape_of(K, D, V, L).a, shape_of(K, D, V, L).b, shape_of(K, D, V, L).c
+
+template <int K, int D, int L, int V, bool VEC>
+hipError_t launch_kind(const TaskArgs& a, int grid, const Filter& f, hipStream_t s) {
+  if constexpr (K == K_LP_DOWN)
+    hipLaunchKernelGGL((k_lp_down<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_LP_UP)
+    hipLaunchKernelGGL((k_lp_up<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_FB_DOWN)
+    hipLaunchKernelGGL((k_fb_down<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else
+    hipLaunchKernelGGL((k_fb_up<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  return hipGetLastError();
+}
+
+template <int K, int D, int L>
+hipError_t launch_kdl(int variant, bool vec, const TaskArgs& a, int grid, const Filter& f, hipStream_t s) {
+  if (variant == 0) return vec ? launch_kind<K, D, L, 0, true>(a, grid, f, s) : launch_kind<K, D, L, 0, false>(a, grid, f, s);
+  return vec ? launch_kind<K, D, L, 1, true>(a, grid, f, s) : launch_kind<K, D, L, 1, false>(a, grid, f, s);
+}
+
+template <int K, int D>
+hipError_t launch_kd(int taps, int variant, bool vec, const TaskArgs& a, int grid, const Filter& f, hipStream_t s) {
+  switch (taps) {
+    case 2: return launch_kdl<K, D, 2>(variant, vec, a, grid, f, s);
+    case 4: return launch_kdl<K, D, 4>(variant, vec, a, grid, f, s);
+    case 6: return launch_kdl<K, D, 6>(variant, vec, a, grid, f, s);
+    case 8: return launch_kdl<K, D, 8>(variant, vec, a, grid, f, s);
+    case 10: return launch_kdl<K, D, 10>(variant, vec, a, grid, f, s);
+    case 12: return launch_kdl<K, D, 12>(variant, vec, a, grid, f, s);
+    case 14: return launch_kdl<K, D, 14>(variant, vec, a, grid, f, s);
+    case 16: return launch_kdl<K, D, 16>(variant, vec, a, grid, f, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int K>
+hipError_t launch_k(int ndim, int taps, int variant, bool vec, const TaskArgs& a, int grid, const Filter& f,
+                    hipStream_t s) {
+  switch (ndim) {
+    case 1: return launch_kd<K, 1>(taps, variant, vec, a, grid, f, s);
+    case 2: return launch_kd<K, 2>(taps, variant, vec, a, grid, f, s);
+    case 3: return launch_kd<K, 3>(taps, variant, vec, a, grid, f, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int D, int L>
+hipError_t launch_tail_dl(int kind, const TailArgs& a, int grid, size_t lds, const Filter& f, hipStream_t s) {
+  const void* fn = kind == 0 ? (const void*)k_tail_lp<D, L>
+                             : (kind == 1 ? (const void*)k_tail_fb<D, L, false> : (const void*)k_tail_fb<D, L, true>);
+  if (lds > 65536) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (kind == 0)
+    hipLaunchKernelGGL((k_tail_lp<D, L>), dim3(grid), dim3(kTailThreads), lds, s, a, f);
+  else if (kind == 1)
+    hipLaunchKernelGGL((k_tail_fb<D, L, false>), dim3(grid), dim3(kTailThreads), lds, s, a, f);
+  else
+    hipLaunchKernelGGL((k_tail_fb<D, L, true>), dim3(grid), dim3(kTailThreads), lds, s, a, f);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_tail_d(int kind, int taps, const TailArgs& a, int grid, size_t lds, const Filter& f,
+                         hipStream_t s) {
+  switch (taps) {
+    case 2: return launch_tail_dl<D, 2>(kind, a, grid, lds, f, s);
+    case 4: return launch_tail_dl<D, 4>(kind, a, grid, lds, f, s);
+    case 6: return launch_tail_dl<D, 6>(kind, a, grid, lds, f, s);
+    case 8: return launch_tail_dl<D, 8>(kind, a, grid, lds, f, s);
+    case 10: return launch_tail_dl<D, 10>(kind, a, grid, lds, f, s);
+    case 12: return launch_tail_dl<D, 12>(kind, a, grid, lds, f, s);
+    case 14: return launch_tail_dl<D, 14>(kind, a, grid, lds, f, s);
+    case 16: return launch_tail_dl<D, 16>(kind, a, grid, lds, f, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int L>
+hipError_t launch_plain_l(const PlainPass& p, const Filter& f, hipStream_t s) {
+  int hb[3] = {p.b[0], p.b[1], p.b[2]};
+  hb[p.axis] >>= 1;
+  const int64_t total = (int64_t)hb[0] * hb[1] * hb[2];
+  const int64_t grid = (total + 255) / 256;
+  hipLaunchKernelGGL((k_plain_pass<L>), dim3((unsigned)grid), dim3(256), 0, s, p, f);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+TileShape tile_shape(int kind, int ndim, int variant, int taps) {
+  const Shape3 sh = shape_of(kind, ndim, variant, taps);
+  TileShape t;
+  t.t[0] = sh.a;
+  t.t[1] = sh.b;
+  t.t[2] = sh.c;
+  return t;
+}
+
+int tile_threads(int, int, int) { return kThreads; }
+int tail_threads() { return kTailThreads; }
+
+hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArgs& args, int grid, const Filter& f,
+                        hipStream_t stream) {
+  // the vector path needs 16-byte rows; the host decides per launch (all tasks agree)
+  const bool vec = args.vec != 0;
+  switch (kind) {
+    case K_LP_DOWN: return launch_k<K_LP_DOWN>(ndim, taps, variant, vec, args, grid, f, stream);
+    case K_LP_UP: return launch_k<K_LP_UP>(ndim, taps, variant, vec, args, grid, f, stream);
+    case K_FB_DOWN: return launch_k<K_FB_DOWN>(ndim, taps, variant, vec, args, grid, f, stream);
+    case K_FB_UP: return launch_k<K_FB_UP>(ndim, taps, variant, vec, args, grid, f, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_tail(int kind, int ndim, int taps, const TailArgs& args, int grid, size_t lds_bytes,
+                       const Filter& f, hipStream_t stream) {
+  switch (ndim) {
+    case 1: return launch_tail_d<1>(kind, taps, args, grid, lds_bytes, f, stream);
+    case 2: return launch_tail_d<2>(kind, taps, args, grid, lds_bytes, f, stream);
+    case 3: return launch_tail_d<3>(kind, taps, args, grid, lds_bytes, f, stream);
+  }
+  return hipErrorInvalidValue;
+}
+
+size_t tail_lds_bytes(int kind, int ndim, const int b[3], int nlev) {
+  const size_t B = (size_t)b[0] * b[1] * b[2];
+  if (kind == 0) {
+    size_t tot = 0, cur = B;
+    for (int j = 0; j <= nlev; ++j) { tot += cur; cur >>= ndim; }
+    return (tot + B) * sizeof(float);  // pyramid + two half-size temporaries
+  }
+  return 2 * B * sizeof(float);
+}
+
+hipError_t launch_plain_pass(const PlainPass& p, int taps, const Filter& f, hipStream_t s) {
+  switch (taps) {
+    case 2: return launch_plain_l<2>(p, f, s);
+    case 4: return launch_plain_l<4>(p, f, s);
+    case 6: return launch_plain_l<6>(p, f, s);
+    case 8: return launch_plain_l<8>(p, f, s);
+    case 10: return launch_plain_l<10>(p, f, s);
+    case 12: return launch_plain_l<12>(p, f, s);
+    case 14: return launch_plain_l<14>(p, f, s);
+    case 16: return launch_plain_l<16>(p, f, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_block_copy(const float* src, float* dst, const int b[3], const int st_src[2], const int st_dst[2],
+                             hipStream_t s) {
+  const int64_t total = (int64_t)b[0] * b[1] * b[2];
+  hipLaunchKernelGGL(k_block_copy, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, b[0], b[1], b[2],
+                     st_src[0], st_src[1], st_dst[0], st_dst[1]);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t s) {
+  // n is a multiple of 4 and both pointers 16-byte aligned (checked by the caller)
+  const int64_t n4 = n / 4;
+  int64_t grid = (n4 + 255) / 256;
+  if (grid > 8192) grid = 8192;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)grid), dim3(256), 0, s, reinterpret_cast<const float4*>(src),
+                     reinterpret_cast<float4*>(dst), n4);
+  return hipGetLastError();
+}
+
+}  // namespace es

@@ -1,0 +1,164 @@
+"""Torch-facing wrappers of the C ABI (argument marshalling only; every step runs in HIP).
+
+Arrays are float32 CUDA (HIP) tensors of shape (*batch, *grid) where `grid` is the last
+`ndim` dims.  Work is enqueued on torch's current stream of the tensor's device.
+"""
+import ctypes
+import math
+
+import torch
+
+from ._lib import (OP_ADJOINT, OP_APPLY, OP_COV, OP_SAMPLE, EsDesc, check, load, shape_arg)
+
+_NAMES = {OP_ADJOINT: "es_adjoint", OP_APPLY: "es_apply", OP_COV: "matern_cov_apply", OP_SAMPLE: "matern_sample"}
+
+
+def _split(x, ndim):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if x.dtype != torch.float32:
+        raise TypeError(f"expected float32, got {x.dtype}")
+    if x.device.type != "cuda":
+        raise TypeError("expected a GPU tensor (the library has no CPU path)")
+    if x.dim() < ndim:
+        raise ValueError(f"tensor has {x.dim()} dims, need at least ndim={ndim}")
+    grid = tuple(x.shape[x.dim() - ndim:])
+    batch = math.prod(x.shape[:x.dim() - ndim])
+    return grid, batch
+
+
+def workspace_bytes(op, grid, batch, order, levels):
+    lib = load()
+    return int(lib.es_workspace_bytes(len(grid), shape_arg(grid), int(batch), int(order), int(levels), int(op)))
+
+
+def _ws(need, device, workspace):
+    if need == 0:
+        return None
+    if workspace is not None:
+        if workspace.device != device or workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace must hold {need} bytes on {device}")
+        return workspace
+    return torch.empty(need, dtype=torch.uint8, device=device)
+
+
+def apply_op(op, x, ndim, order, levels, s, out=None, workspace=None):
+    grid, batch = _split(x, ndim)
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of the input's shape")
+    lib = load()
+    shp = shape_arg(grid)
+    need = int(lib.es_workspace_bytes(ndim, shp, batch, int(order), int(levels), op))
+    ws = _ws(need, x.device, workspace)
+    with torch.cuda.device(x.device):
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        st = getattr(lib, _NAMES[op])(ndim, shp, batch, int(order), int(levels), float(s), x.data_ptr(),
+                                      out.data_ptr(), ws.data_ptr() if ws is not None else None, need, stream)
+    check(st)
+    return out
+
+
+def es_adjoint(x, ndim, order, levels, s, out=None, workspace=None):
+    """coeff = D_s W x (packed-pyramid coefficients, same shape as x)."""
+    return apply_op(OP_ADJOINT, x, ndim, order, levels, s, out, workspace)
+
+
+def es_apply(c, ndim, order, levels, s, out=None, workspace=None):
+    """x = W^T D_s c (exact transpose of es_adjoint)."""
+    return apply_op(OP_APPLY, c, ndim, order, levels, s, out, workspace)
+
+
+def matern_cov_apply(x, ndim, order, levels, s, out=None, workspace=None):
+    """y = W^T D_2s W x = E_s E_s^* x (the paper's pixel-space E_s^*)."""
+    return apply_op(OP_COV, x, ndim, order, levels, s, out, workspace)
+
+
+def matern_sample(xi, ndim, order, levels, s, out=None, workspace=None):
+    """x = W^T D_s W xi (symmetric square root of the covariance)."""
+    return apply_op(OP_SAMPLE, xi, ndim, order, levels, s, out, workspace)
+
+
+def plain_op(op, x, ndim, order, levels, s, out=None):
+    """Reference variant: one launch per 1-D pass per level per instance."""
+    grid, batch = _split(x, ndim)
+    x = x.contiguous()
+    out = torch.empty_like(x) if out is None else out
+    lib = load()
+    shp = shape_arg(grid)
+    need = int(lib.es_workspace_bytes_plain(ndim, shp, batch, int(order), int(levels), op))
+    ws = _ws(need, x.device, None)
+    with torch.cuda.device(x.device):
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        st = lib.es_plain_apply_op(op, ndim, shp, batch, int(order), int(levels), float(s), x.data_ptr(),
+                                   out.data_ptr(), ws.data_ptr() if ws is not None else None, need, stream)
+    check(st)
+    return out
+
+
+def matern_to_s(nu, d):
+    """Sobolev index s = nu + d/2 of the Matern covariance Gamma_{nu, sqrt(2 nu)} (Prop. 3.2)."""
+    return nu + d / 2.0
+
+
+class RaggedPlan:
+    """Many instances of different geometry in one captured launch sequence (es_plan_*).
+
+    descs: list of (grid_shape, order, levels, s).  Call with lists of input and output
+    tensors (one per instance, matching the descriptors).
+    """
+
+    def __init__(self, descs, op, device=None):
+        self.lib = load()
+        self.op = int(op)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        n = len(descs)
+        arr = (EsDesc * max(1, n))()
+        self.shapes = []
+        for i, (shape, order, levels, s) in enumerate(descs):
+            arr[i].ndim = len(shape)
+            for k, v in enumerate(shape):
+                arr[i].shape[k] = int(v)
+            arr[i].order = int(order)
+            arr[i].levels = int(levels)
+            arr[i].s = float(s)
+            self.shapes.append(tuple(int(v) for v in shape))
+        self._p = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(self.lib.es_plan_create(arr, n, self.op, stream, ctypes.byref(self._p)))
+        self.ws_bytes = int(self.lib.es_plan_workspace_bytes(self._p))
+        self.workspace = torch.empty(max(1, self.ws_bytes), dtype=torch.uint8, device=self.device)
+        self.num_launches = int(self.lib.es_plan_num_launches(self._p))
+
+    def __call__(self, inputs, outputs=None, graph=True):
+        if len(inputs) != len(self.shapes):
+            raise ValueError("one input per descriptor")
+        if outputs is None:
+            outputs = [torch.empty_like(x) for x in inputs]
+        for x, y, shp in zip(inputs, outputs, self.shapes):
+            if tuple(x.shape) != shp or tuple(y.shape) != shp:
+                raise ValueError(f"tensor shape must be {shp}")
+            if x.dtype != torch.float32 or not x.is_contiguous() or not y.is_contiguous():
+                raise ValueError("contiguous float32 tensors required")
+        n = len(inputs)
+        ip = (ctypes.c_void_p * max(1, n))(*[x.data_ptr() for x in inputs])
+        op = (ctypes.c_void_p * max(1, n))(*[y.data_ptr() for y in outputs])
+        fn = self.lib.es_plan_execute if graph else self.lib.es_plan_execute_eager
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(fn(self._p, ip, op, self.workspace.data_ptr(), self.ws_bytes, stream))
+        return outputs
+
+    def close(self):
+        if getattr(self, "_p", None) is not None and self._p.value:
+            self.lib.es_plan_destroy(self._p)
+            self._p = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

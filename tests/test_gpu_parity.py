@@ -1,0 +1,135 @@
+"""GPU parity: every operator through the C ABI vs the FP64 oracle (relative L2 <= 1e-5).
+
+Sizes span several tiles with ragged tails, both tile variants, the tail kernels on and off,
+filters longer than the coarse levels (periodic folding), 1-, 2- and 3-D grids.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2507_02401_amd as es
+from tests.gpu_util import ORACLE_OPS, OP_NAMES, TOL, env, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+CASES = [
+    # shape, order, levels, s
+    ((5184,), 8, 5, 1.0),
+    ((4096,), 2, 9, 1.5),
+    ((64,), 4, 6, 2.0),
+    ((104, 136), 4, 3, 1.0),
+    ((104, 136), 8, 3, 1.5),
+    ((256, 384), 6, 5, 1.5),
+    ((64, 64), 3, 6, 1.0),
+    ((16, 16), 8, 4, 1.0),
+    ((96, 32), 1, 5, 0.5),
+    ((24, 40, 56), 4, 3, 2.0),
+    ((32, 32, 32), 2, 5, 1.0),
+    ((16, 16, 16), 8, 2, -0.5),
+    ((8, 16, 32), 6, 3, 1.5),
+]
+
+
+def _run(op, x64, order, levels, s, batch=1):
+    ndim = x64.ndim - (1 if batch > 1 else 0)
+    x32 = x64.astype(np.float32)
+    y = es.apply_op(op, torch.from_numpy(x32).to(DEV), ndim, order, levels, s)
+    torch.cuda.synchronize()
+    return x32, y.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-db{c[1]}-m{c[2]}")
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+@pytest.mark.parametrize("mode", ["auto", "wide", "narrow", "notail"])
+def test_parity(case, op, mode):
+    shape, order, levels, s = case
+    knobs = {"auto": {}, "wide": dict(ESWAVE_FORCE_VARIANT=0), "narrow": dict(ESWAVE_FORCE_VARIANT=1),
+             "notail": dict(ESWAVE_TAIL_MAX=0)}[mode]
+    gen = np.random.default_rng(hash((shape, order, levels, op)) & 0xFFFF)
+    x = gen.standard_normal(shape)
+    say("parity", OP_NAMES[op], shape, order, levels, s, mode)
+    with env(**knobs):
+        x32, y = _run(op, x, order, levels, s)
+    ref = ORACLE_OPS[op](x32.astype(np.float64), order, levels, s)
+    err = rel_l2(y, ref)
+    assert err <= TOL, f"rel L2 {err:.3e}"
+
+
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_uniform_batch(op):
+    """A batch of instances in one call equals the per-instance oracle."""
+    shape, order, levels, s = (3, 72, 88), 5, 3, 1.25
+    x = np.random.default_rng(7).standard_normal(shape)
+    say("batch", OP_NAMES[op], shape)
+    x32 = x.astype(np.float32)
+    y = es.apply_op(op, torch.from_numpy(x32).to(DEV), 2, order, levels, s).cpu().numpy()
+    for b in range(shape[0]):
+        ref = ORACLE_OPS[op](x32[b].astype(np.float64), order, levels, s)
+        assert rel_l2(y[b], ref) <= TOL
+
+
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_plain_path_parity(op):
+    shape, order, levels, s = (2, 64, 96), 4, 4, 1.5
+    x = np.random.default_rng(3).standard_normal(shape).astype(np.float32)
+    say("plain", OP_NAMES[op], shape)
+    y = es.plain_op(op, torch.from_numpy(x).to(DEV), 2, order, levels, s).cpu().numpy()
+    for b in range(shape[0]):
+        ref = ORACLE_OPS[op](x[b].astype(np.float64), order, levels, s)
+        assert rel_l2(y[b], ref) <= TOL
+
+
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_plain_path_3d_and_1d(op):
+    for shape, order, levels, s in [((16, 32, 8), 3, 2, 1.0), ((1024,), 8, 6, 2.0)]:
+        x = np.random.default_rng(4).standard_normal(shape).astype(np.float32)
+        say("plain", OP_NAMES[op], shape)
+        y = es.plain_op(op, torch.from_numpy(x).to(DEV), len(shape), order, levels, s).cpu().numpy()
+        ref = ORACLE_OPS[op](x.astype(np.float64), order, levels, s)
+        assert rel_l2(y, ref) <= TOL
+
+
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_identity_cases(op):
+    x = np.random.default_rng(5).standard_normal((32, 48)).astype(np.float32)
+    xt = torch.from_numpy(x).to(DEV)
+    say("identity", OP_NAMES[op])
+    y0 = es.apply_op(op, xt, 2, 4, 0, 1.0).cpu().numpy()
+    assert np.array_equal(y0, x)  # m = 0
+    if op >= 2:
+        y1 = es.apply_op(op, xt, 2, 4, 1, 1.0).cpu().numpy()
+        assert np.array_equal(y1, x)  # m = 1: every weight is 1
+        ys = es.apply_op(op, xt, 2, 4, 4, 0.0).cpu().numpy()
+        assert rel_l2(ys, x) <= TOL  # s = 0
+
+
+def test_constant_preserved():
+    x = np.full((64, 64), 0.75, dtype=np.float32)
+    for op in (2, 3):
+        y = es.apply_op(op, torch.from_numpy(x).to(DEV), 2, 6, 5, 1.5).cpu().numpy()
+        assert np.max(np.abs(y - 0.75)) < 1e-5
+
+
+def test_deterministic():
+    x = torch.from_numpy(np.random.default_rng(9).standard_normal((4, 256, 256)).astype(np.float32)).to(DEV)
+    for op in range(4):
+        a = es.apply_op(op, x, 2, 8, 5, 1.5)
+        b = es.apply_op(op, x, 2, 8, 5, 1.5)
+        assert torch.equal(a, b)
+
+
+def test_empty_batch():
+    x = torch.empty((0, 32, 32), device=DEV)
+    for op in range(4):
+        y = es.apply_op(op, x, 2, 4, 3, 1.0)
+        assert y.shape == x.shape
+
+
+def test_errors_raise():
+    x = torch.zeros((48, 64), device=DEV)
+    with pytest.raises(es.EswaveError):
+        es.matern_cov_apply(x, 2, 4, 5, 1.0)  # 48 not divisible by 32
+    with pytest.raises(TypeError):
+        es.matern_cov_apply(x.double(), 2, 4, 3, 1.0)
