@@ -42,6 +42,23 @@ def kernel_bytes(name, level, batch, side, ndim=2):
     return 4 * batch * 2 * n(level)  # full-bank level: read and write the level block
 
 
+def trace_summary(path):
+    """Per-dispatch-shape summary of a `rocprofv3 --kernel-trace --output-format csv` trace.
+
+    Dispatches are grouped by kernel name and grid size (the same kernel template serves
+    several pyramid levels); durations are End - Start of each dispatch.
+    """
+    import csv
+    groups = {}
+    for r in csv.DictReader(open(path)):
+        key = (r["Kernel_Name"], int(r["Grid_Size_X"]) // int(r["Workgroup_Size_X"]))
+        groups.setdefault(key, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = ["| kernel | work-groups | dispatches | avg us | min us | max us |", "|---|---|---|---|---|---|"]
+    for (name, wg), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"| `{name}` | {wg} | {len(d)} | {statistics.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} |")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,7 +67,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--trace-summary", metavar="CSV", help="summarise a rocprofv3 kernel trace and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -314,10 +314,11 @@ es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, f
     std::vector<double> w(m + 2), c(m + 1);
     for (int i = 1; i <= m; ++i) w[i] = wdet(g, tau, i);
     for (int i = 1; i <= m - 1; ++i) c[i] = w[i + 1] - w[i];
-    int T = -1;
-    for (int i = 0; i <= m - 2; ++i)
-      if (g.level_size(i) <= tail_max(D)) { T = i; break; }
-    const bool tail = T >= 0;
+    // The LDS-resident low-pass tail kernel is switched off: a 1-D run of it ended in a GPU
+    // memory-aperture fault whose cause has not been found (see the design notes).  Every
+    // level goes through the LP_DOWN / LP_UP tile kernels instead.
+    const int T = -1;
+    const bool tail = false;
     const int down_to = tail ? T : m - 1;
     for (int i = 1; i <= down_to; ++i) {
       Launch l = level_launch(K_LP_DOWN, g, i, batch);

@@ -31,6 +31,19 @@ DEVI int pmod(int v, int n) {
   return r < 0 ? r + n : r;
 }
 
+// Global-memory accessors.  Array pointers reach the kernels through the task tables, so the
+// compiler cannot tell that they address global memory and would emit flat instructions
+// (which also occupy the LDS counter and serialise against LDS traffic).  These casts to
+// the global address space make every access a global_load / global_store.
+#define GAS __attribute__((address_space(1)))
+DEVI float gld(const float* p) { return *(const GAS float*)p; }
+typedef float f4v __attribute__((ext_vector_type(4)));
+DEVI float4 gld4(const float* p) {
+  const f4v v = *(const GAS f4v*)p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+DEVI void gst(float* p, float v) { *(GAS float*)p = v; }
+
 // ---------------------------------------------------------------------------------------
 // Work-group -> task/tile mapping.
 //
@@ -136,6 +149,60 @@ DEVI void synthesis_pass(int nlines, int nch, const Filter& f, In in, Out out) {
   }
 }
 
+// Contiguous-dim analysis of NROW staged rows, results written back over the staging buffer
+// as rows of T2 (FB: [lo T2 | hi T2]) floats.  Each task is P consecutive outputs of one row;
+// a thread holds its results in registers across the barrier that frees the buffer.
+template <int L, int P, int NROW, int T2, int I2P, int NT, bool FB>
+DEVI void row_pass_inplace(float* s_in, const Filter& f) {
+  constexpr int NCH = T2 / P;
+  constexpr int NTASK = NROW * NCH;
+  constexpr int IT = (NTASK + NT - 1) / NT;
+  constexpr int W = 2 * P + L - 2;
+  constexpr int W4 = (W + 3) / 4;
+  constexpr int OUTW = FB ? 2 * T2 : T2;
+  static_assert(NROW * OUTW <= NROW * I2P, "row results must fit in the staging buffer");
+  float lo[IT][P], hi[FB ? IT : 1][P];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int task = threadIdx.x + it * NT;
+    if (task < NTASK) {
+      const int ch = task % NCH, l = task / NCH;
+      const float4* p = reinterpret_cast<const float4*>(s_in + l * I2P + 2 * P * ch);
+      float win[4 * W4];
+#pragma unroll
+      for (int v = 0; v < W4; ++v) {
+        const float4 x = p[v];
+        win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
+      }
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        float a = 0.f, d = 0.f;
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+          a = fmaf(f.h[t], win[2 * q + t], a);
+          if (FB) d = fmaf(f.g[t], win[2 * q + t], d);
+        }
+        lo[it][q] = a;
+        if (FB) hi[it][q] = d;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int task = threadIdx.x + it * NT;
+    if (task < NTASK) {
+      const int ch = task % NCH, l = task / NCH;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        s_in[l * OUTW + P * ch + q] = lo[it][q];
+        if (FB) s_in[l * OUTW + T2 + P * ch + q] = hi[FB ? it : 0][q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------------------
 // Geometry of a level kernel instantiation.
 //
@@ -168,25 +235,36 @@ struct UpGeom {
 };
 
 // Stage a periodic region into LDS: rows given by a row-offset table, 16-byte columns by a
-// column table (element offsets), both already reduced modulo the block.
-template <int NT, bool VEC>
-DEVI void stage_rows(const float* __restrict__ src, const int* s_row, const int* s_col, int nrows, int nv,
-                     float* lds, int lds_row, int b2, float scale) {
-  if (VEC) {
+// column table (element offsets), both already reduced modulo the block.  The trip count is
+// a compile-time constant: every load of a thread is issued before the first LDS store, so a
+// work-group keeps all of its global loads in flight at once.
+template <int NT, int NROWS, int NV, bool VEC>
+DEVI void stage_rows(const float* __restrict__ src, const int* s_row, const int* s_col, float* lds, int lds_row,
+                     int b2) {
+  if constexpr (VEC) {
+    constexpr int N = NROWS * NV;
+    constexpr int IT = (N + NT - 1) / NT;
     float4* d4 = reinterpret_cast<float4*>(lds);
-    const int n = nrows * nv;
-    for (int q = threadIdx.x; q < n; q += NT) {
-      const int v = q % nv, r = q / nv;
-      float4 x = *reinterpret_cast<const float4*>(src + s_row[r] + s_col[v]);
-      if (scale != 1.f) { x.x *= scale; x.y *= scale; x.z *= scale; x.w *= scale; }
-      d4[r * (lds_row >> 2) + v] = x;
+    float4 r[IT];
+    // no guard inside the unrolled loops: indices past the end are clamped to the last
+    // element (a duplicate load and an identical duplicate store), so the compiler can issue
+    // every load before the first LDS store
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, N - 1);
+      r[it] = gld4(src + s_row[q / NV] + s_col[q % NV]);
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, N - 1);
+      d4[(q / NV) * (lds_row >> 2) + q % NV] = r[it];
     }
   } else {
-    const int n = nrows * nv * 4;
-    for (int q = threadIdx.x; q < n; q += NT) {
-      const int e = q & 3, v = (q >> 2) % nv, r = (q >> 2) / nv;
+    constexpr int N = NROWS * NV * 4;
+    for (int q = threadIdx.x; q < N; q += NT) {
+      const int e = q & 3, v = (q >> 2) % NV, r = (q >> 2) / NV;
       const int col = pmod(s_col[v] + e, b2);  // s_col holds the unreduced aligned start here
-      lds[r * lds_row + 4 * v + e] = src[s_row[r] + col] * scale;
+      lds[r * lds_row + 4 * v + e] = gld(src + s_row[r] + col);
     }
   }
 }
@@ -199,7 +277,6 @@ __global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
   using G = DownGeom<D, L, T0, T1, T2>;
   constexpr int P2 = 4, P1 = 4, P0 = 2;
   __shared__ __attribute__((aligned(16))) float s_in[G::NROW * G::I2P];
-  __shared__ float s_a[G::NROW * T2];
   __shared__ float s_b[D >= 3 ? T0 * G::I1 * T2 : 1];
   __shared__ int s_row[G::NROW];
   __shared__ int s_col[G::NV];
@@ -219,29 +296,20 @@ __global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
   }
   for (int i = threadIdx.x; i < G::NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
   __syncthreads();
-  stage_rows<NT, VEC>(src, s_row, s_col, G::NROW, G::NV, s_in, G::I2P, b2, 1.f);
+  stage_rows<NT, G::NROW, G::NV, VEC>(src, s_row, s_col, s_in, G::I2P, b2);
   __syncthreads();
 
-  // contiguous dim: (NROW, I2) -> (NROW, T2)
-  analysis_pass<L, P2, false, false, NT>(
-      G::NROW, T2 / P2, f,
-      [&](int l, int j0, float* w) {
-        const float4* p = reinterpret_cast<const float4*>(s_in + l * G::I2P + j0);
-#pragma unroll
-        for (int v = 0; v < (2 * P2 + L - 2 + 3) / 4; ++v) {
-          const float4 x = p[v];
-          w[4 * v] = x.x; w[4 * v + 1] = x.y; w[4 * v + 2] = x.z; w[4 * v + 3] = x.w;
-        }
-      },
-      [&](int l, int k, float lo, float) { s_a[l * T2 + k] = lo; });
-  __syncthreads();
+  // contiguous dim: (NROW, I2) -> (NROW, T2); results go through registers so that s_a can
+  // reuse the staging buffer (smaller LDS footprint, more resident work-groups)
+  float* s_a = s_in;
+  row_pass_inplace<L, P2, G::NROW, T2, G::I2P, NT, false>(s_in, f);
 
   const int n1o = b1 >> 1, n2o = b2 >> 1, n0o = b0 >> 1;
   if constexpr (D == 1) {
     // already the output: (1, T2)
     for (int k = threadIdx.x; k < T2; k += NT) {
       const int g2 = T2 * tl.c2 + k;
-      if (g2 < n2o) dst[g2] = s_a[k];
+      if (g2 < n2o) gst(dst + g2, s_a[k]);
     }
   } else if constexpr (D == 2) {
     analysis_pass<L, P1, false, true, NT>(
@@ -252,7 +320,7 @@ __global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
         },
         [&](int c, int k, float lo, float) {
           const int g1 = T1 * tl.c1 + k, g2 = T2 * tl.c2 + c;
-          if (g1 < n1o && g2 < n2o) dst[g1 * n2o + g2] = lo;
+          if (g1 < n1o && g2 < n2o) gst(dst + g1 * n2o + g2, lo);
         });
   } else {
     // dim 0: (I0, I1, T2) -> (T0, I1, T2), lines are (i1, c)
@@ -275,7 +343,7 @@ __global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
         [&](int l, int k, float lo, float) {
           const int c = l % T2, k0 = l / T2;
           const int g0 = T0 * tl.c0 + k0, g1 = T1 * tl.c1 + k, g2 = T2 * tl.c2 + c;
-          if (g0 < n0o && g1 < n1o && g2 < n2o) dst[(g0 * n1o + g1) * n2o + g2] = lo;
+          if (g0 < n0o && g1 < n1o && g2 < n2o) gst(dst + (g0 * n1o + g1) * n2o + g2, lo);
         });
   }
 }
@@ -312,7 +380,7 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
   }
   for (int i = threadIdx.x; i < G::NV; i += NT) s_col[i] = VEC ? pmod(r2 + 4 * i, h2) : r2 + 4 * i;
   __syncthreads();
-  stage_rows<NT, VEC>(z, s_row, s_col, G::NROW, G::NV, s_in, G::J2P, h2, 1.f);
+  stage_rows<NT, G::NROW, G::NV, VEC>(z, s_row, s_col, s_in, G::J2P, h2);
   __syncthreads();
 
   // contiguous dim: (NROW, J2) -> (NROW, U2)
@@ -333,7 +401,7 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
   if constexpr (D == 1) {
     for (int p = threadIdx.x; p < U2; p += NT) {
       const int g2 = tl.c2 * U2 + p;
-      if (g2 < b2) out[g2] = fmaf(alpha, same[g2], beta * s_a[p]);
+      if (g2 < b2) gst(out + g2, fmaf(alpha, gld(same + g2), beta * s_a[p]));
     }
   } else if constexpr (D == 2) {
     synthesis_pass<L, P1, false, true, NT>(
@@ -346,9 +414,9 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
           const int g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
           if (g1 < b1 && g2 < b2) {
             const int o = g1 * b2 + g2;
-            const float s0 = same[o], s1 = same[o + b2];
-            out[o] = fmaf(alpha, s0, beta * e0);
-            out[o + b2] = fmaf(alpha, s1, beta * e1);
+            const float s0 = gld(same + o), s1 = gld(same + o + b2);
+            gst(out + o, fmaf(alpha, s0, beta * e0));
+            gst(out + o + b2, fmaf(alpha, s1, beta * e1));
           }
         });
   } else {
@@ -376,9 +444,9 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
           const int g0 = tl.c0 * U0 + p0, g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
           if (g0 < b0 && g1 < b1 && g2 < b2) {
             const int o = (g0 * b1 + g1) * b2 + g2;
-            const float s0 = same[o], s1 = same[o + b2];
-            out[o] = fmaf(alpha, s0, beta * e0);
-            out[o + b2] = fmaf(alpha, s1, beta * e1);
+            const float s0 = gld(same + o), s1 = gld(same + o + b2);
+            gst(out + o, fmaf(alpha, s0, beta * e0));
+            gst(out + o + b2, fmaf(alpha, s1, beta * e1));
           }
         });
   }
@@ -395,7 +463,6 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
   constexpr int P2 = 4, P1 = 4, P0 = 2;
   constexpr int T2x = 2 * T2;  // [lo | hi] along the contiguous dim
   __shared__ __attribute__((aligned(16))) float s_in[G::NROW * G::I2P];
-  __shared__ float s_a[G::NROW * T2x];
   __shared__ float s_b[D >= 3 ? 2 * T0 * G::I1 * T2x : 1];
   __shared__ int s_row[G::NROW];
   __shared__ int s_col[G::NV];
@@ -416,24 +483,11 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
   }
   for (int i = threadIdx.x; i < G::NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
   __syncthreads();
-  stage_rows<NT, VEC>(src, s_row, s_col, G::NROW, G::NV, s_in, G::I2P, b2, 1.f);
+  stage_rows<NT, G::NROW, G::NV, VEC>(src, s_row, s_col, s_in, G::I2P, b2);
   __syncthreads();
 
-  analysis_pass<L, P2, true, false, NT>(
-      G::NROW, T2 / P2, f,
-      [&](int l, int j0, float* w) {
-        const float4* p = reinterpret_cast<const float4*>(s_in + l * G::I2P + j0);
-#pragma unroll
-        for (int v = 0; v < (2 * P2 + L - 2 + 3) / 4; ++v) {
-          const float4 x = p[v];
-          w[4 * v] = x.x; w[4 * v + 1] = x.y; w[4 * v + 2] = x.z; w[4 * v + 3] = x.w;
-        }
-      },
-      [&](int l, int k, float lo, float hi) {
-        s_a[l * T2x + k] = lo;
-        s_a[l * T2x + T2 + k] = hi;
-      });
-  __syncthreads();
+  float* s_a = s_in;  // (NROW, [lo T2 | hi T2]) written over the staging buffer
+  row_pass_inplace<L, P2, G::NROW, T2, G::I2P, NT, true>(s_in, f);
 
   const int n0h = b0 >> 1, n1h = b1 >> 1, n2h = b2 >> 1;
   const float alpha = t.alpha, beta = t.beta;
@@ -441,10 +495,10 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
   auto emit = [&](int e0, int e1, int e2, int g0, int g1, int g2, float v) {
     if (g0 >= (D >= 3 ? n0h : 1) || g1 >= (D >= 2 ? n1h : 1) || g2 >= n2h) return;
     if ((e0 | e1 | e2) == 0) {
-      ll[(D >= 3 ? g0 * t.st_out1[0] : 0) + (D >= 2 ? g1 * t.st_out1[1] : 0) + g2] = beta * v;
+      gst(ll + (D >= 3 ? g0 * t.st_out1[0] : 0) + (D >= 2 ? g1 * t.st_out1[1] : 0) + g2, beta * v);
     } else {
       const int r0 = e0 * n0h + g0, r1 = e1 * n1h + g1, r2 = e2 * n2h + g2;
-      coef[(D >= 3 ? r0 * t.st_out0[0] : 0) + (D >= 2 ? r1 * t.st_out0[1] : 0) + r2] = alpha * v;
+      gst(coef + (D >= 3 ? r0 * t.st_out0[0] : 0) + (D >= 2 ? r1 * t.st_out0[1] : 0) + r2, alpha * v);
     }
   };
 
@@ -545,23 +599,27 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
   __syncthreads();
   {
     const float alpha = t.alpha, beta = t.beta;
-    if (VEC) {
-      const int n = NRB * 2 * G::NV;
+    if constexpr (VEC) {
+      constexpr int n = NRB * 2 * G::NV;
+      constexpr int IT = (n + NT - 1) / NT;
       float4* d4 = reinterpret_cast<float4*>(s_in);
-      for (int q = threadIdx.x; q < n; q += NT) {
+      float4 r[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int q = min(int(threadIdx.x) + it * NT, n - 1);
         const int v = q % G::NV, re = q / G::NV;  // re = row*2 + e2
         const int e2 = re & 1, row = re >> 1;
-        float4 x;
-        float sc;
-        if (e2 == 0 && s_rowl[row] >= 0) {
-          x = *reinterpret_cast<const float4*>(ap + s_rowl[row] + s_col[v]);
-          sc = beta;
-        } else {
-          x = *reinterpret_cast<const float4*>(cp + s_rowc[row] + s_col[e2 * G::NV + v]);
-          sc = alpha;
-        }
+        const bool ll = e2 == 0 && s_rowl[row] >= 0;
+        const float* p = ll ? ap + s_rowl[row] + s_col[v] : cp + s_rowc[row] + s_col[e2 * G::NV + v];
+        float4 x = gld4(p);
+        const float sc = ll ? beta : alpha;
         x.x *= sc; x.y *= sc; x.z *= sc; x.w *= sc;
-        d4[re * (G::J2P / 4) + v] = x;
+        r[it] = x;
+      }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int q = min(int(threadIdx.x) + it * NT, n - 1);
+        d4[(q / G::NV) * (G::J2P / 4) + q % G::NV] = r[it];
       }
     } else {
       const int n = NRB * 2 * G::J2P;
@@ -570,8 +628,8 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
         const int e2 = re & 1, row = re >> 1;
         const int col = pmod(r2 + c, h2);
         float v;
-        if (e2 == 0 && s_rowl[row] >= 0) v = beta * ap[s_rowl[row] + col];
-        else v = alpha * cp[s_rowc[row] + e2 * h2 + col];
+        if (e2 == 0 && s_rowl[row] >= 0) v = beta * gld(ap + s_rowl[row] + col);
+        else v = alpha * gld(cp + s_rowc[row] + e2 * h2 + col);
         s_in[re * G::J2P + c] = v;
       }
     }
@@ -594,7 +652,7 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
   if constexpr (D == 1) {
     for (int p = threadIdx.x; p < U2; p += NT) {
       const int g2 = tl.c2 * U2 + p;
-      if (g2 < b2) out[g2] = s_a[p];
+      if (g2 < b2) gst(out + g2, s_a[p]);
     }
   } else if constexpr (D == 2) {
     // rows of s_a: (e1, j1); lines are columns c
@@ -610,8 +668,8 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
         [&](int c, int p, float e0, float e1) {
           const int g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
           if (g1 < b1 && g2 < b2) {
-            out[g1 * t.st_out0[1] + g2] = e0;
-            out[(g1 + 1) * t.st_out0[1] + g2] = e1;
+            gst(out + g1 * t.st_out0[1] + g2, e0);
+            gst(out + (g1 + 1) * t.st_out0[1] + g2, e1);
           }
         });
   } else {
@@ -646,8 +704,8 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
           const int g0 = tl.c0 * U0 + p0, g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
           if (g0 < b0 && g1 < b1 && g2 < b2) {
             const int o = g0 * t.st_out0[0] + g1 * t.st_out0[1] + g2;
-            out[o] = e0;
-            out[o + t.st_out0[1]] = e1;
+            gst(out + o, e0);
+            gst(out + o + t.st_out0[1], e1);
           }
         });
   }
@@ -657,7 +715,7 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
 // Tail kernels: every remaining level of one instance inside one work-group's LDS.
 // Block sides may be shorter than the filter (periodic folding through the modulo).
 
-constexpr int kTailThreads = 512;
+constexpr int kTailThreads = 256;
 
 struct Blk {
   int n[3];
@@ -666,7 +724,8 @@ struct Blk {
 
 // One 1-D pass along `ax` on a block laid out with strides (sr0, sr1, 1) in src and
 // (sd0, sd1, 1) in dst.  Analysis (FB=false: low-pass only, output extent n/2 along ax;
-// FB=true: [lo | hi]).  Synthesis reads [lo | hi] (or lo only) of half extent.
+// FB=true: [lo | hi]).  When the axis is at least L long a sample index wraps at most once
+// and the modulo reduces to a compare; shorter axes (periodic folding) take the modulo.
 template <int L, bool FB>
 DEVI void tail_analysis_axis(const float* src, int sr0, int sr1, float* dst, int sd0, int sd1, Blk b, int ax,
                              const Filter& f) {
@@ -674,56 +733,74 @@ DEVI void tail_analysis_axis(const float* src, int sr0, int sr1, float* dst, int
   Blk o = b;
   o.n[ax] = half;
   const int total = o.size();
+  const int step = ax == 0 ? sr0 : (ax == 1 ? sr1 : 1);
+  const int dstep = ax == 0 ? sd0 : (ax == 1 ? sd1 : 1);
+  const bool longax = n >= L;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int c2 = e % o.n[2], r = e / o.n[2];
-    int c1 = r % o.n[1], c0 = r / o.n[1];
-    int c[3] = {c0, c1, c2};
-    const int k = c[ax];
-    const int step = ax == 0 ? sr0 : (ax == 1 ? sr1 : 1);
-    c[ax] = 0;
-    const float* base = src + c[0] * sr0 + c[1] * sr1 + c[2];
+    const int c2 = e % o.n[2], r = e / o.n[2];
+    const int c1 = r % o.n[1], c0 = r / o.n[1];
+    const int k = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+    const float* base = src + (ax == 0 ? 0 : c0 * sr0) + (ax == 1 ? 0 : c1 * sr1) + (ax == 2 ? 0 : c2);
     float lo = 0.f, hi = 0.f;
+    if (longax) {
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      const float x = base[((2 * k + t) % n) * step];
-      lo = fmaf(f.h[t], x, lo);
-      if (FB) hi = fmaf(f.g[t], x, hi);
+      for (int t = 0; t < L; ++t) {
+        int i = 2 * k + t;
+        i = i >= n ? i - n : i;
+        const float x = base[i * step];
+        lo = fmaf(f.h[t], x, lo);
+        if (FB) hi = fmaf(f.g[t], x, hi);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        const float x = base[((2 * k + t) % n) * step];
+        lo = fmaf(f.h[t], x, lo);
+        if (FB) hi = fmaf(f.g[t], x, hi);
+      }
     }
-    const int dstep = ax == 0 ? sd0 : (ax == 1 ? sd1 : 1);
-    float* d = dst + c[0] * sd0 + c[1] * sd1 + c[2];
+    float* d = dst + (ax == 0 ? 0 : c0 * sd0) + (ax == 1 ? 0 : c1 * sd1) + (ax == 2 ? 0 : c2);
     d[k * dstep] = lo;
     if (FB) d[(half + k) * dstep] = hi;
   }
 }
 
 // Synthesis along `ax`: output block b (full extent n along ax); input has [lo | hi] (FB) or
-// lo only (extent n/2) along ax.  mode: 0 store, 1 dst = alpha*dst_same + beta*val where
-// dst_same is read from `same` with dst strides.
+// lo only (extent n/2) along ax.  With `same`, dst = alpha*same + beta*value (same read with
+// dst strides), else dst = value.  Output p receives h[t] lo[k] + g[t] hi[k] for every tap t
+// with 2k + t = p (mod n), i.e. t = p (mod 2) and k = (p - t)/2 mod n/2.
 template <int L, bool FB>
 DEVI void tail_synthesis_axis(const float* src, int sr0, int sr1, float* dst, int sd0, int sd1, Blk b, int ax,
                               const Filter& f, const float* same, float alpha, float beta) {
   const int n = b.n[ax], half = n >> 1;
   const int total = b.size();
   const int step = ax == 0 ? sr0 : (ax == 1 ? sr1 : 1);
+  const bool longax = half >= L / 2;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    int c2 = e % b.n[2], r = e / b.n[2];
-    int c1 = r % b.n[1], c0 = r / b.n[1];
-    int c[3] = {c0, c1, c2};
-    const int p = c[ax];
-    c[ax] = 0;
-    const float* base = src + c[0] * sr0 + c[1] * sr1 + c[2];
+    const int c2 = e % b.n[2], r = e / b.n[2];
+    const int c1 = r % b.n[1], c0 = r / b.n[1];
+    const int p = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+    const float* base = src + (ax == 0 ? 0 : c0 * sr0) + (ax == 1 ? 0 : c1 * sr1) + (ax == 2 ? 0 : c2);
     float acc = 0.f;
-    // x[p] = sum_k sum_t [ (2k+t) mod n == p ] (h[t] lo[k] + g[t] hi[k])
+    const int par = p & 1, q = p >> 1;
+    if (longax) {
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      // k with 2k + t == p (mod n): 2k == p - t (mod n); solvable iff p - t even
-      const int dlt = p - t;
-      if (dlt & 1) continue;
-      const int k = pmod(dlt >> 1, half);
-      acc = fmaf(f.h[t], base[k * step], acc);
-      if (FB) acc = fmaf(f.g[t], base[(half + k) * step], acc);
+      for (int j = 0; j < L / 2; ++j) {
+        const int t = 2 * j + par;
+        int k = q - j;
+        k = k < 0 ? k + half : k;
+        acc = fmaf(f.h[t], base[k * step], acc);
+        if (FB) acc = fmaf(f.g[t], base[(half + k) * step], acc);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < L / 2; ++j) {
+        const int t = 2 * j + par;
+        const int k = pmod(q - j, half);
+        acc = fmaf(f.h[t], base[k * step], acc);
+        if (FB) acc = fmaf(f.g[t], base[(half + k) * step], acc);
+      }
     }
-    // when n < L several taps land on the same k; each (t, k) pair is visited once above
     const int o = c0 * sd0 + c1 * sd1 + c2;
     if (same) dst[o] = fmaf(alpha, same[o], beta * acc);
     else dst[o] = acc;
@@ -1094,6 +1171,7 @@ hipError_t launch_k(int ndim, int taps, int variant, bool vec, const TaskArgs& a
 
 template <int D, int L>
 hipError_t launch_tail_dl(int kind, const TailArgs& a, int grid, size_t lds, const Filter& f, hipStream_t s) {
+  if (kind == 0) return hipErrorInvalidValue;  // low-pass tail switched off (unresolved GPU fault)
   const void* fn = kind == 0 ? (const void*)k_tail_lp<D, L>
                              : (kind == 1 ? (const void*)k_tail_fb<D, L, false> : (const void*)k_tail_fb<D, L, true>);
   if (lds > 65536) {
