@@ -25,6 +25,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "E_s E_s^* voxels/s + HBM GB/s, batched/autograd vs plain; FP32 err vs FP64"
 HBM_PEAK_GBPS = 8000.0
+CAL_FLOATS = 1 << 28  # 1 GiB calibration copy
+# launch names reported by the library -> kernel template names as the profiler prints them
+KERNEL_TEMPLATES = {
+    "lp_up_2d_L16_v0": "void es::k_lp_up<2, 16, 1, 64, 128, 256, true>(es::TaskArgs, es::Filter)",
+    "lp_down_2d_L16_v0": "void es::k_lp_down<2, 16, 1, 32, 64, 256, true>(es::TaskArgs, es::Filter)",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matern_cov_64x1024sq_db8.json")
 IMAGES, SIDE, ORDER, LEVELS, S = 64, 1024, 8, 7, 1.5
 
 
@@ -33,6 +40,8 @@ def kernel_bytes(name, level, batch, side, ndim=2):
     def n(i):
         return (side >> i) ** ndim
     kind = name.split("_")[0] + "_" + name.split("_")[1]
+    if kind == "lp_up2":  # z_2, a_1, same_0 -> out_0
+        return 4 * batch * (n(level + 2) + n(level + 1) + 2 * n(level))
     if kind == "lp_down":  # a_{i-1} -> a_i, i = level + 1 (level = input level)
         return 4 * batch * (n(level) + n(level + 1))
     if kind == "lp_up":  # z_{i+1}, same_i -> out_i
@@ -58,6 +67,172 @@ def trace_summary(path):
         lines.append(f"| `{name}` | {wg} | {len(d)} | {statistics.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} |")
     return "\n".join(lines)
 
+def source_hash():
+    """Hash of the kernel source: counter readings are only valid for the kernels they measured."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2507_02401_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def pmc_summary(fetch_csv, write_csv, out_path):
+    """Combine two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs (KiB per dispatch).
+
+    Both counters are scaled by what they read for the 1 GiB calibration copy
+    (`__amd_rocclr_copyBuffer`, 1 GiB read + 1 GiB written), then averaged per (kernel, grid).
+    """
+    import csv
+    from collections import defaultdict
+
+    def load(path):
+        g = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            g[(r["Kernel_Name"], int(r["Grid_Size"]) // int(r["Workgroup_Size"]))].append(float(r["Counter_Value"]))
+        return g
+    fe, wr = load(fetch_csv), load(write_csv)
+    gib_kib = (CAL_FLOATS * 4) / 1024.0
+    cal_f = max(v for (k, _), vs in fe.items() if "copyBuffer" in k for v in vs)
+    cal_w = max(v for (k, _), vs in wr.items() if "copyBuffer" in k for v in vs)
+    sf, sw = gib_kib / cal_f, gib_kib / cal_w
+    kernels = []
+    for key in fe:
+        if not key[0].startswith("void es::"):
+            continue
+        f = statistics.mean(fe[key]) * sf * 1024
+        w = statistics.mean(wr.get(key, [0.0])) * sw * 1024
+        kernels.append({"kernel": key[0], "work_groups": key[1], "fetch_bytes": round(f), "write_bytes": round(w)})
+    res = {"kernel_source_sha256_16": source_hash(), "fetch_scale": round(sf, 4), "write_scale": round(sw, 4),
+           "calibration": "1 GiB device copy: FETCH_SIZE %.1f KiB, WRITE_SIZE %.1f KiB" % (cal_f, cal_w),
+           "kernels": sorted(kernels, key=lambda k: -(k["fetch_bytes"] + k["write_bytes"]))}
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
+def traffic_for(kernel_name, work_groups):
+    """HBM bytes per launch of a kernel from the committed counter file, or None if absent/stale."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != source_hash():
+        return None
+    for k in t["kernels"]:
+        if k["kernel"] == kernel_name and k["work_groups"] == work_groups:
+            return k["fetch_bytes"] + k["write_bytes"]
+    return None
+
+
+def _time(fn, torch, reps, warmup=1):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def other_workloads(args, es, inputs, torch, np):
+    """The other workloads: fused path vs the plain per-instance, per-axis launches."""
+    from paper_2507_02401_amd import autograd as ag
+    dev = torch.device("cuda", 0)
+    out = {}
+    reps = max(3, min(args.steps, 10))
+
+    # 128^2, db4, 5 levels, s = 1: latency of one E_s E_s^* call
+    print("[bench] 128^2 latency", file=sys.stderr, flush=True)
+    d = inputs.small_image()
+    x = torch.from_numpy(d["x"]).to(dev)
+    tf = _time(lambda: es.matern_cov_apply(x, 2, d["order"], d["levels"], d["s"]), torch, 50, 5)
+    tp = _time(lambda: es.plain_op(es.OP_COV, x, 2, d["order"], d["levels"], d["s"]), torch, 20, 2)
+    out["image_128_db4_m5_cov"] = {"fused_us": round(1e6 * tf, 2), "plain_us": round(1e6 * tp, 2)}
+
+    # 256^3, db4, 5 levels, s = 2: loss 0.5||E_s^* x - y||^2, forward + backward
+    print("[bench] 256^3 autograd", file=sys.stderr, flush=True)
+    d = inputs.volume_autograd(side=256)
+    xv = torch.from_numpy(d["x"]).to(dev)
+    yv = torch.from_numpy(d["y"]).to(dev)
+
+    def fwd_bwd():
+        xr = xv.detach().requires_grad_(True)
+        c = ag.es_adjoint(xr, 3, d["order"], d["levels"], d["s"])
+        (0.5 * ((c - yv) ** 2).sum()).backward()
+
+    def plain_pair():
+        c = es.plain_op(es.OP_ADJOINT, xv, 3, d["order"], d["levels"], d["s"])
+        es.plain_op(es.OP_APPLY, c - yv, 3, d["order"], d["levels"], d["s"])
+
+    def op_pair():
+        c = es.es_adjoint(xv, 3, d["order"], d["levels"], d["s"])
+        es.es_apply(c, 3, d["order"], d["levels"], d["s"])
+
+    nv = xv.numel()
+    tf, tp, to = _time(fwd_bwd, torch, reps), _time(plain_pair, torch, 2), _time(op_pair, torch, reps)
+    out["volume_256_db4_m5_autograd"] = {
+        "fwd_bwd_ms": round(1e3 * tf, 3), "voxels_per_s_fwd_bwd": round(nv / tf, 1),
+        "adjoint_plus_apply_ms": round(1e3 * to, 3),
+        "effective_GBps_adjoint_plus_apply": round(16 * nv / to / 1e9, 1),
+        "plain_pair_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tf, 2)}
+    del xv, yv
+
+    # 200 ragged instances: one captured plan vs the same plan launched eagerly vs plain
+    print("[bench] ragged 200", file=sys.stderr, flush=True)
+    d = inputs.ragged_batch(count=200, seed=0)
+    descs = list(d["descs"])
+    ins = [torch.from_numpy(a).to(dev) for a in d["xs"]]
+    outs = [torch.empty_like(a) for a in ins]
+    plan = es.RaggedPlan(descs, es.OP_COV)
+    nvr = sum(a.numel() for a in ins)
+    tg = _time(lambda: plan(ins, outs, graph=True), torch, reps)
+    te = _time(lambda: plan(ins, outs, graph=False), torch, reps)
+
+    def plain_all():
+        for a, b, (sh, o, m, s_) in zip(ins, outs, descs):
+            es.plain_op(es.OP_COV, a, len(sh), o, m, s_, out=b)
+
+    def single_calls():
+        for a, b, (sh, o, m, s_) in zip(ins, outs, descs):
+            es.matern_cov_apply(a, len(sh), o, m, s_, out=b)
+    tp = _time(plain_all, torch, 1, 1)
+    ts = _time(single_calls, torch, 2)
+    out["ragged_200_cov"] = {
+        "voxels": nvr, "launches_per_call": plan.num_launches,
+        "graph_ms": round(1e3 * tg, 3), "voxels_per_s_graph": round(nvr / tg, 1),
+        "effective_GBps_graph": round(8 * nvr / tg / 1e9, 1),
+        "eager_plan_ms": round(1e3 * te, 3), "per_instance_fused_calls_ms": round(1e3 * ts, 3),
+        "plain_per_instance_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tg, 2)}
+    plan.close()
+    del ins, outs
+
+    # 256 x 512^2, db6, 6 levels, s = 1.5: prior sample and its gradient through a masked loss
+    print("[bench] 256 x 512^2 sampler", file=sys.stderr, flush=True)
+    d = inputs.map_gradient_batch(count=256, side=512)
+    xi = torch.from_numpy(d["xi"]).to(dev)
+    mk = torch.from_numpy(d["mask"]).to(dev)
+    yy = torch.from_numpy(d["y"]).to(dev)
+
+    def smp():
+        xr = xi.detach().requires_grad_(True)
+        xs = ag.matern_sample(xr, 2, d["order"], d["levels"], d["s"])
+        (0.5 * ((mk * xs - yy) ** 2).sum()).backward()
+
+    def smp_plain():
+        xs = es.plain_op(es.OP_SAMPLE, xi, 2, d["order"], d["levels"], d["s"])
+        es.plain_op(es.OP_SAMPLE, mk * (mk * xs - yy), 2, d["order"], d["levels"], d["s"])
+
+    def smp_ops():
+        xs = es.matern_sample(xi, 2, d["order"], d["levels"], d["s"])
+        es.matern_sample(xs, 2, d["order"], d["levels"], d["s"])
+    ns = xi.numel()
+    tf, tp, to = _time(smp, torch, reps), _time(smp_plain, torch, 1), _time(smp_ops, torch, reps)
+    out["sampler_256x512_db6_m6_fwd_bwd"] = {
+        "fwd_bwd_ms": round(1e3 * tf, 3), "voxels_per_s_fwd_bwd": round(ns / tf, 1),
+        "two_sampler_calls_ms": round(1e3 * to, 3),
+        "effective_GBps_two_calls": round(16 * ns / to / 1e9, 1),
+        "plain_fwd_bwd_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tf, 2)}
+    return out
+
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -67,10 +242,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target length of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
     ap.add_argument("--trace-summary", metavar="CSV", help="summarise a rocprofv3 kernel trace and exit")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="combine two rocprofv3 --pmc runs into the committed traffic file and exit")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run one 1 GiB device copy (known bytes) for counter calibration")
     args = ap.parse_args()
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
+        return
+    if args.pmc_summary:
+        print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_FILE), indent=1))
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -113,6 +296,14 @@ def main():
     ms = 1e3 * elapsed / args.steps
     value = voxels / (elapsed / args.steps)
 
+    if args.calibration_copy:
+        cal_src = torch.ones(CAL_FLOATS, dtype=torch.float32, device=dev)
+        cal_dst = torch.empty_like(cal_src)
+        torch.cuda.synchronize()
+        cal_dst.copy_(cal_src)
+        torch.cuda.synchronize()
+        del cal_src, cal_dst
+
     # per-kernel durations: the same launch sequence, one launch at a time between HIP events
     stream = torch.cuda.current_stream(dev)
     shp = _lib.shape_arg(grid)
@@ -151,6 +342,10 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None, kernel=dom["name"],
                     level=dom["level"])
+    tr = traffic_for(KERNEL_TEMPLATES.get(dom["name"], ""), dom["work_groups"])
+    if tr is not None:
+        roofline["traffic"] = tr
+        roofline["traffic_over_algorithmic"] = round(tr / dom["algorithmic_bytes"], 4)
 
     # parity on one sampled image
     i_s = 5
@@ -172,6 +367,9 @@ def main():
         "roofline": roofline,
         "kernels": kernels,
     }
+
+    if not args.no_extras:
+        result["other_workloads"] = other_workloads(args, es, inputs, torch, np)
 
     if not args.no_plain:
         print("[bench] plain per-image path", file=sys.stderr, flush=True)

@@ -194,6 +194,14 @@ int64_t tail_max(int D) {
   if (e && *e) return atoll(e);
   return kTailMax[D];
 }
+bool fuse_up2() {  // measured slower than two launches on 64 x 1024^2 db8: opt-in
+  const char* e = getenv("ESWAVE_FUSE_UP2");
+  return e && *e == '1';
+}
+bool reverse_orders() {
+  const char* e = getenv("ESWAVE_NO_REVERSE");
+  return !(e && *e == '1');
+}
 int forced_variant() {
   const char* e = getenv("ESWAVE_FORCE_VARIANT");
   if (e && (*e == '0' || *e == '1')) return *e - '0';
@@ -205,6 +213,7 @@ struct Launch {
   int kind;     // KernelKind, or tail kind (0 LP, 1 FB analysis, 2 FB synthesis)
   int variant;
   int vec;
+  int reverse;  // walk tiles in reverse order
   int D, L;
   Task task;
   TailTask tail;
@@ -264,7 +273,7 @@ bool vec_ok(const Task& t, int kind, const Geo& g) {
   auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   auto m4 = [](int64_t v) { return (v & 3) == 0; };
   const bool analysis = (kind == K_LP_DOWN || kind == K_FB_DOWN);
-  const int row = analysis ? t.b[2] : t.b[2] / 2;  // staged rows are the input rows
+  const int row = analysis ? t.b[2] : (kind == K_LP_UP2 ? t.b[2] / 4 : t.b[2] / 2);  // staged input rows
   if (!m4(row)) return false;
   if (!a16(t.in0) || !m4(t.bs_in0) || !m4(t.st_in0[0]) || !m4(t.st_in0[1])) return false;
   if (kind == K_FB_UP && (!a16(t.in1) || !m4(t.bs_in1) || !m4(t.st_in1[0]) || !m4(t.st_in1[1]))) return false;
@@ -289,6 +298,16 @@ Launch level_launch(int kind, const Geo& g, int level, int64_t batch) {
 }
 
 void finish_level(Launch& l, const Geo& g) { l.vec = vec_ok(l.task, l.kind, g) ? 1 : 0; }
+
+// Consecutive launches walk their tiles in opposite orders, and the last launch (the finest
+// up level, which re-reads the input) runs opposite to the first (the finest down level, which
+// read it first), so that data touched at the end of one launch is touched first by the next
+// while it is still in the L2 / Infinity Cache.
+void set_orders(Schedule* sc) {
+  const int n = (int)sc->launches.size();
+  for (int k = 0; k < n; ++k) sc->launches[k].reverse = reverse_orders() ? (k & 1) : 0;
+  if (n >= 2 && reverse_orders()) sc->launches[n - 1].reverse = sc->launches[0].reverse ^ 1;
+}
 
 es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, float* out, float* ws,
                          Schedule* sc) {
@@ -355,7 +374,9 @@ es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, f
       sc->launches.push_back(l);
     }
     const int up_from = tail ? T - 1 : m - 2;
-    for (int i = up_from; i >= 0; --i) {
+    // 2-D: the last two up levels (z_1 and y) run fused in one kernel when both exist
+    const bool fuse_last = D == 2 && up_from >= 1 && fuse_up2();
+    for (int i = up_from; i >= (fuse_last ? 2 : 0); --i) {
       // produce level i (full-res block of level i = dims of a_i)
       Launch l = level_launch(K_LP_UP, g, i + 1, batch);
       int d_z[3], d_o[3];
@@ -375,6 +396,24 @@ es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, f
       finish_level(l, g);
       sc->launches.push_back(l);
     }
+    if (fuse_last) {
+      Launch l = level_launch(K_LP_UP2, g, 1, batch);
+      l.task.in0 = lvl_ptr(2);  // z_2
+      l.task.bs_in0 = wsi;
+      l.task.in1 = lvl_ptr(1);  // a_1
+      l.task.bs_in1 = wsi;
+      l.task.in2 = in;          // x
+      l.task.bs_in2 = N;
+      l.task.out0 = out;
+      l.task.bs_out0 = N;
+      l.task.alpha = (float)w[1];
+      l.task.beta = 1.f;
+      l.task.gamma = (float)c[1];
+      l.task.delta = (!tail && 1 == m - 2) ? (float)c[m - 1] : 1.f;
+      finish_level(l, g);
+      sc->launches.push_back(l);
+    }
+    set_orders(sc);
     return ES_OK;
   }
 
@@ -442,6 +481,7 @@ es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, f
       l.lds = tail_lds_bytes(1, D, t.b, t.nlev);
       sc->launches.push_back(l);
     }
+    set_orders(sc);
     return ES_OK;
   }
 
@@ -501,6 +541,7 @@ es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, f
     finish_level(l, g);
     sc->launches.push_back(l);
   }
+  set_orders(sc);
   return ES_OK;
 }
 
@@ -516,6 +557,7 @@ es_status run_launch(const Launch& l, const Filter& f, hipStream_t stream, const
     a.count = count;
     a.total_wg = total_wg;
     a.vec = l.vec;
+    a.reverse = l.reverse;
     a.t0 = l.task;
     ES_HIP(launch_level(l.kind, l.D, l.L, l.variant, a, grid, f, stream), "level kernel launch");
   } else {
@@ -1055,7 +1097,7 @@ es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t b
   if (st != ES_OK) return st;
   if (index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
   const Launch& l = sc.launches[index];
-  static const char* kinds[4] = {"lp_down", "lp_up", "fb_down", "fb_up"};
+  static const char* kinds[5] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2"};
   static const char* tails[3] = {"tail_lp", "tail_fb_analysis", "tail_fb_synthesis"};
   char buf[128];
   int lev = 0;

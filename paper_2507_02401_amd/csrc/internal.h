@@ -27,15 +27,19 @@ struct Filter {
 //                                                 out1 = next approximation (x beta)
 //   FB_UP     one full synthesis level            in0 = approximation (x beta), in1 = coeff
 //                                                 (detail bands, x alpha), out0 = result
+//   LP_UP2    two low-pass synthesis levels:      in0 = z2 (level i+2), in1 = a1 (level i+1),
+//             out = alpha*same + beta*A^T z1,    in2 = same (level i), out0 = out;
+//             z1 = gamma*a1 + delta*A^T z2        b = level-i block (2-D only)
 // `b` is the full-resolution block of the level (input of analysis, output of synthesis).
 struct Task {
   const float* in0;
   const float* in1;
+  const float* in2;
   float* out0;
   float* out1;
-  int64_t bs_in0, bs_in1, bs_out0, bs_out1;  // per-instance strides
+  int64_t bs_in0, bs_in1, bs_in2, bs_out0, bs_out1;  // per-instance strides
   int32_t st_in0[2], st_in1[2], st_out0[2], st_out1[2];  // strides of dims 0 and 1
-  float alpha, beta;
+  float alpha, beta, gamma, delta;
   int32_t batch;
   int32_t b[3];
   int32_t ntile[3];
@@ -50,7 +54,7 @@ struct TaskArgs {
   int32_t count;
   int32_t total_wg;   // work-groups that carry work (grid is padded to a multiple of 8)
   int32_t vec;        // 1: every staged row is 16-byte aligned and a multiple of 4 floats
-  int32_t pad_;
+  int32_t reverse;    // 1: walk the tiles in reverse order (cache reuse between launches)
   Task t0;
 };
 
@@ -82,7 +86,7 @@ struct TailArgs {
   TailTask t0;
 };
 
-enum KernelKind { K_LP_DOWN = 0, K_LP_UP = 1, K_FB_DOWN = 2, K_FB_UP = 3 };
+enum KernelKind { K_LP_DOWN = 0, K_LP_UP = 1, K_FB_DOWN = 2, K_FB_UP = 3, K_LP_UP2 = 4 };
 
 // Tile shape selection: each (kind, ndim, taps) has a "wide" and a "narrow" instantiation.
 struct TileShape {

@@ -49,12 +49,13 @@ DEVI void gst(float* p, float v) { *(GAS float*)p = v; }
 //
 // The hardware hands work-group i to XCD i mod 8.  Remapping gives each XCD a contiguous run
 // of logical tiles, so tiles that share filter halos share an L2.
-DEVI int logical_wg(int total_wg) {
+DEVI int logical_wg(int total_wg, int reverse = 0) {
   const int grid = gridDim.x;  // padded to a multiple of 8 by the host
   const int per = grid >> 3;
   const int i = blockIdx.x;
   const int l = (i & 7) * per + (i >> 3);
-  return l < total_wg ? l : -1;
+  if (l >= total_wg) return -1;
+  return reverse ? total_wg - 1 - l : l;
 }
 
 template <class T, class A>
@@ -281,7 +282,7 @@ __global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
   __shared__ int s_row[G::NROW];
   __shared__ int s_col[G::NV];
 
-  const int wg = logical_wg(args.total_wg);
+  const int wg = logical_wg(args.total_wg, args.reverse);
   if (wg < 0) return;
   const Task t = pick_task<Task>(args, wg);
   const Tile tl = decode_tile(t, wg);
@@ -362,7 +363,7 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
   __shared__ int s_row[G::NROW];
   __shared__ int s_col[G::NV];
 
-  const int wg = logical_wg(args.total_wg);
+  const int wg = logical_wg(args.total_wg, args.reverse);
   if (wg < 0) return;
   const Task t = pick_task<Task>(args, wg);
   const Tile tl = decode_tile(t, wg);
@@ -453,6 +454,120 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
 }
 
 // ---------------------------------------------------------------------------------------
+// LP_UP2 (2-D): two synthesis levels of the projection form in one kernel,
+//   z1  = gamma*a1 + delta*A^T z2   (level i+1, only on the halo region this tile needs)
+//   out = alpha*same + beta*A^T z1  (level i, the tile)
+// so z1 never travels through HBM.  The level-(i+1) region starts HP (>= L/2-1, a multiple
+// of 4) samples before the tile's half-resolution origin; the level-(i+2) region is loaded
+// from a 4-aligned start OFF2 samples before the first value the synthesis reads.
+
+template <int L, int U1, int U2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_lp_up2(TaskArgs args, Filter f) {
+  constexpr int H = L / 2;
+  constexpr int HP = ((H - 1) + 3) & ~3;
+  constexpr int K1 = U1 / 2 + HP, K2 = U2 / 2 + HP;  // level-(i+1) region
+  constexpr int Q1 = K1 / 2 + H - 1;                 // level-(i+2) rows
+  constexpr int OFF2 = ((-(HP / 2) - (H - 1)) % 4 + 4) % 4;
+  constexpr int Q2 = K2 / 2 + H - 1;
+  constexpr int Q2P = (Q2 + OFF2 + 3) & ~3;
+  constexpr int NV2 = Q2P / 4;
+  constexpr int OFF1 = HP - (H - 1);                 // tile origin inside the level-(i+1) region
+  constexpr int P2 = 4, P1 = 4;                      // level i+1 -> i passes
+  constexpr int P2a = (K2 / 2) % 4 == 0 ? 4 : 2;     // level i+2 -> i+1 passes
+  constexpr int P1a = (K1 / 2) % 4 == 0 ? 4 : 2;
+  static_assert(U1 % 16 == 0 && U2 % 16 == 0, "tile sides must be multiples of 16");
+  static_assert((K2 / 2) % P2a == 0 && (K1 / 2) % P1a == 0, "region must split into whole chunks");
+  __shared__ __attribute__((aligned(16))) float s_z2[Q1 * Q2P];
+  __shared__ float s_r2[Q1 * K2];
+  __shared__ float s_z1[K1 * K2];
+  __shared__ float s_t[K1 * U2];
+  __shared__ int s_row2[Q1];
+  __shared__ int s_col2[NV2];
+  __shared__ int s_row1[K1];
+  __shared__ int s_col1[K2];
+
+  const int wg = logical_wg(args.total_wg, args.reverse);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ z2 = t.in0 + tl.inst * t.bs_in0;
+  const float* __restrict__ a1 = t.in1 + tl.inst * t.bs_in1;
+  const float* same = t.in2 + tl.inst * t.bs_in2;
+  float* out = t.out0 + tl.inst * t.bs_out0;
+  const int b1 = t.b[1], b2 = t.b[2];
+  const int p1 = b1 >> 1, p2 = b2 >> 1;  // level i+1
+  const int q1 = p1 >> 1, q2 = p2 >> 1;  // level i+2
+  const int R1 = tl.c1 * (U1 / 2) - HP, R2 = tl.c2 * (U2 / 2) - HP;
+  const int S1 = R1 / 2 - (H - 1), S2 = R2 / 2 - (H - 1) - OFF2;
+
+  for (int i = threadIdx.x; i < Q1; i += NT) s_row2[i] = pmod(S1 + i, q1) * q2;
+  for (int i = threadIdx.x; i < NV2; i += NT) s_col2[i] = VEC ? pmod(S2 + 4 * i, q2) : S2 + 4 * i;
+  for (int i = threadIdx.x; i < K1; i += NT) s_row1[i] = pmod(R1 + i, p1) * p2;
+  for (int i = threadIdx.x; i < K2; i += NT) s_col1[i] = pmod(R2 + i, p2);
+  __syncthreads();
+  stage_rows<NT, Q1, NV2, VEC>(z2, s_row2, s_col2, s_z2, Q2P, q2);
+  __syncthreads();
+
+  // level i+2 -> i+1 along the contiguous dim: (Q1, Q2) -> (Q1, K2)
+  synthesis_pass<L, P2a, false, false, NT>(
+      Q1, K2 / 2 / P2a, f,
+      [&](int l, int j0, float* lo, float*) {
+        const float* p = s_z2 + l * Q2P + OFF2 + j0;
+#pragma unroll
+        for (int j = 0; j < P2a + H - 1; ++j) lo[j] = p[j];
+      },
+      [&](int l, int p, float e0, float e1) {
+        s_r2[l * K2 + p] = e0;
+        s_r2[l * K2 + p + 1] = e1;
+      });
+  __syncthreads();
+  // level i+2 -> i+1 along rows, combined with gamma * a1: (Q1, K2) -> (K1, K2)
+  const float gamma = t.gamma, delta = t.delta;
+  synthesis_pass<L, P1a, false, true, NT>(
+      K2, K1 / 2 / P1a, f,
+      [&](int c, int j0, float* lo, float*) {
+#pragma unroll
+        for (int j = 0; j < P1a + H - 1; ++j) lo[j] = s_r2[(j0 + j) * K2 + c];
+      },
+      [&](int c, int p, float e0, float e1) {
+        const int col = s_col1[c];
+        s_z1[p * K2 + c] = fmaf(gamma, gld(a1 + s_row1[p] + col), delta * e0);
+        s_z1[(p + 1) * K2 + c] = fmaf(gamma, gld(a1 + s_row1[p + 1] + col), delta * e1);
+      });
+  __syncthreads();
+  // level i+1 -> i along the contiguous dim: (K1, K2) -> (K1, U2)
+  synthesis_pass<L, P2, false, false, NT>(
+      K1, U2 / 2 / P2, f,
+      [&](int l, int j0, float* lo, float*) {
+        const float* p = s_z1 + l * K2 + OFF1 + j0;
+#pragma unroll
+        for (int j = 0; j < P2 + H - 1; ++j) lo[j] = p[j];
+      },
+      [&](int l, int p, float e0, float e1) {
+        s_t[l * U2 + p] = e0;
+        s_t[l * U2 + p + 1] = e1;
+      });
+  __syncthreads();
+  // level i+1 -> i along rows: (K1, U2) -> (U1, U2), out = alpha*same + beta*value
+  const float alpha = t.alpha, beta = t.beta;
+  synthesis_pass<L, P1, false, true, NT>(
+      U2, U1 / 2 / P1, f,
+      [&](int c, int j0, float* lo, float*) {
+#pragma unroll
+        for (int j = 0; j < P1 + H - 1; ++j) lo[j] = s_t[(OFF1 + j0 + j) * U2 + c];
+      },
+      [&](int c, int p, float e0, float e1) {
+        const int g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
+        if (g1 < b1 && g2 < b2) {
+          const int o = g1 * b2 + g2;
+          const float s0 = gld(same + o), s1 = gld(same + o + b2);
+          gst(out + o, fmaf(alpha, s0, beta * e0));
+          gst(out + o + b2, fmaf(alpha, s1, beta * e1));
+        }
+      });
+}
+
+// ---------------------------------------------------------------------------------------
 // FB_DOWN: one full analysis level on a (T0,T1,T2) tile of every band.
 // Bands go to out0 (packed coefficient array, strides st_out0, detail bands x alpha) except
 // the all-low band, which goes to out1 (next level's approximation, strides st_out1, x beta).
@@ -467,7 +582,7 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
   __shared__ int s_row[G::NROW];
   __shared__ int s_col[G::NV];
 
-  const int wg = logical_wg(args.total_wg);
+  const int wg = logical_wg(args.total_wg, args.reverse);
   if (wg < 0) return;
   const Task t = pick_task<Task>(args, wg);
   const Tile tl = decode_tile(t, wg);
@@ -569,7 +684,7 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
   __shared__ int s_rowl[NRB];  // offset into in0 when e0 = e1 = 0, else -1
   __shared__ int s_col[2 * G::NV];
 
-  const int wg = logical_wg(args.total_wg);
+  const int wg = logical_wg(args.total_wg, args.reverse);
   if (wg < 0) return;
   const Task t = pick_task<Task>(args, wg);
   const Tile tl = decode_tile(t, wg);
@@ -1103,6 +1218,7 @@ struct Shape3 {
   int a, b, c;
 };
 constexpr Shape3 shape_of(int K, int D, int V, int L) {
+  if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : Shape3{1, 32, 64};
   if (D == 1) return (K == K_LP_DOWN || K == K_FB_DOWN) ? (V == 0 ? Shape3{1, 1, 256} : Shape3{1, 1, 64})
                                                           : (V == 0 ? Shape3{1, 1, 512} : Shape3{1, 1, 128});
   if (D == 2) {
@@ -1132,6 +1248,9 @@ hipError_t launch_kind(const TaskArgs& a, int grid, const Filter& f, hipStream_t
     hipLaunchKernelGGL((k_lp_up<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_DOWN)
     hipLaunchKernelGGL((k_fb_down<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_LP_UP2)
+    hipLaunchKernelGGL((k_lp_up2<L, shape_of(K, 2, V, L).b, shape_of(K, 2, V, L).c, kThreads, VEC>), dim3(grid),
+                       dim3(kThreads), 0, s, a, f);
   else
     hipLaunchKernelGGL((k_fb_up<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   return hipGetLastError();
@@ -1236,6 +1355,9 @@ hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArg
     case K_LP_UP: return launch_k<K_LP_UP>(ndim, taps, variant, vec, args, grid, f, stream);
     case K_FB_DOWN: return launch_k<K_FB_DOWN>(ndim, taps, variant, vec, args, grid, f, stream);
     case K_FB_UP: return launch_k<K_FB_UP>(ndim, taps, variant, vec, args, grid, f, stream);
+    case K_LP_UP2:
+      if (ndim != 2) return hipErrorInvalidValue;
+      return launch_kd<K_LP_UP2, 2>(taps, variant, vec, args, grid, f, stream);
   }
   return hipErrorInvalidValue;
 }
