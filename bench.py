@@ -26,11 +26,23 @@ sys.path.insert(0, ROOT)
 METRIC = "E_s E_s^* voxels/s + HBM GB/s, batched/autograd vs plain; FP32 err vs FP64"
 HBM_PEAK_GBPS = 8000.0
 CAL_FLOATS = 1 << 28  # 1 GiB calibration copy
-# launch names reported by the library -> kernel template names as the profiler prints them
-KERNEL_TEMPLATES = {
-    "lp_up_2d_L16_v0": "void es::k_lp_up<2, 16, 1, 64, 128, 256, true>(es::TaskArgs, es::Filter)",
-    "lp_down_2d_L16_v0": "void es::k_lp_down<2, 16, 1, 32, 64, 256, true>(es::TaskArgs, es::Filter)",
-}
+
+
+def template_name(launch_name):
+    """Kernel template as the profiler prints it, from a launch name such as
+    'lp_up_2d_L16_v2_t1x32x128' (kind, dims, taps, variant, tile)."""
+    parts = launch_name.split("_")
+    kind = parts[0] + "_" + parts[1]
+    d = int([p for p in parts if p.endswith("d") and p[:-1].isdigit()][0][:-1])
+    taps = int([p for p in parts if p.startswith("L") and p[1:].isdigit()][0][1:])
+    tile = [p for p in parts if p.startswith("t") and "x" in p][0][1:].split("x")
+    vec = "false" if "scalar" in parts else "true"
+    kname = {"lp_down": "k_lp_down", "lp_up": "k_lp_up", "fb_down": "k_fb_down", "fb_up": "k_fb_up"}.get(kind)
+    if kind.startswith("lp_up2") or launch_name.startswith("lp_up2"):
+        return f"void es::k_lp_up2<{taps}, {tile[1]}, {tile[2]}, 256, {vec}>(es::TaskArgs, es::Filter)"
+    return f"void es::{kname}<{d}, {taps}, {tile[0]}, {tile[1]}, {tile[2]}, 256, {vec}>(es::TaskArgs, es::Filter)"
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matern_cov_64x1024sq_db8.json")
 IMAGES, SIDE, ORDER, LEVELS, S = 64, 1024, 8, 7, 1.5
 
@@ -40,7 +52,7 @@ def kernel_bytes(name, level, batch, side, ndim=2):
     def n(i):
         return (side >> i) ** ndim
     kind = name.split("_")[0] + "_" + name.split("_")[1]
-    if kind == "lp_up2":  # z_2, a_1, same_0 -> out_0
+    if name.startswith("lp_up2"):  # z_2, a_1, same_0 -> out_0
         return 4 * batch * (n(level + 2) + n(level + 1) + 2 * n(level))
     if kind == "lp_down":  # a_{i-1} -> a_i, i = level + 1 (level = input level)
         return 4 * batch * (n(level) + n(level + 1))
@@ -243,6 +255,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
+    ap.add_argument("--no-autotune", action="store_true", help="use the heuristic tile choice")
     ap.add_argument("--trace-summary", metavar="CSV", help="summarise a rocprofv3 kernel trace and exit")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="combine two rocprofv3 --pmc runs into the committed traffic file and exit")
@@ -284,6 +297,8 @@ def main():
         es.matern_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=ws)
 
     print("[bench] warmup", file=sys.stderr, flush=True)
+    if not args.no_autotune:  # one-time tile selection, outside the timed region
+        es.autotune(es.OP_COV, x, 2, ORDER, LEVELS, S, out=y)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -342,7 +357,7 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBPS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBPS, 4), traffic=None, kernel=dom["name"],
                     level=dom["level"])
-    tr = traffic_for(KERNEL_TEMPLATES.get(dom["name"], ""), dom["work_groups"])
+    tr = traffic_for(template_name(dom["name"]), dom["work_groups"])
     if tr is not None:
         roofline["traffic"] = tr
         roofline["traffic_over_algorithmic"] = round(tr / dom["algorithmic_bytes"], 4)
@@ -364,6 +379,7 @@ def main():
         "hbm_GBps_effective": round(8.0 * value / 1e9, 1),
         "frac_of_hbm_peak_whole_op": round(8.0 * value / 1e9 / HBM_PEAK_GBPS, 4),
         "rel_l2_vs_fp64_oracle_image5": rel,
+        "autotuned": not args.no_autotune,
         "roofline": roofline,
         "kernels": kernels,
     }

@@ -37,6 +37,7 @@ SIGNATURES = [
     ("es_plan_workspace_bytes", ctypes.c_size_t, [_fp]),
     ("es_plan_num_launches", ctypes.c_int32, [_fp]),
     ("es_plan_destroy", None, [_fp]),
+    ("es_autotune", ctypes.c_int, [ctypes.c_int] + _OP_ARGS[:-1] + [ctypes.c_int32, _fp]),
     ("es_schedule_length", ctypes.c_int32, [ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
     ("es_schedule_describe", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                             ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t, _i64p,

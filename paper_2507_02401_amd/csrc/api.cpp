@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <tuple>
 #include <cstdlib>
 #include <cmath>
 #include <cstdarg>
@@ -204,13 +206,14 @@ bool reverse_orders() {
 }
 int forced_variant() {
   const char* e = getenv("ESWAVE_FORCE_VARIANT");
-  if (e && (*e == '0' || *e == '1')) return *e - '0';
+  if (e && *e >= '0' && *e < '0' + kNumVariants) return *e - '0';
   return -1;
 }
 
 struct Launch {
   int is_tail;
   int kind;     // KernelKind, or tail kind (0 LP, 1 FB analysis, 2 FB synthesis)
+  int level;    // pyramid level passed to set_tiles (level kernels)
   int variant;
   int vec;
   int reverse;  // walk tiles in reverse order
@@ -292,12 +295,105 @@ Launch level_launch(int kind, const Geo& g, int level, int64_t batch) {
   l.kind = kind;
   l.D = g.D;
   l.L = g.L;
+  l.level = level;
   l.variant = pick_variant(kind, g, level, batch);
   set_tiles(l.task, kind, g, level, l.variant, batch);
   return l;
 }
 
 void finish_level(Launch& l, const Geo& g) { l.vec = vec_ok(l.task, l.kind, g) ? 1 : 0; }
+
+void apply_variant(Launch& l, const Geo& g, int v, int64_t batch) {
+  l.variant = v;
+  set_tiles(l.task, l.kind, g, l.level, v, batch);
+  finish_level(l, g);
+}
+
+// ------------------------------------------------------------------------------------------
+// Autotune cache: for a geometry (op, ndim, sides, taps, levels, batch) the measured fastest
+// tile variant of every launch of its schedule.  Filled by es_autotune; optionally persisted
+// as text lines in the file named by ESWAVE_TUNE_CACHE.
+
+struct TuneKey {
+  int op, D, n0, n1, n2, L, m;
+  int64_t batch;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(op, D, n0, n1, n2, L, m, batch) < std::tie(o.op, o.D, o.n0, o.n1, o.n2, o.L, o.m, o.batch);
+  }
+};
+
+struct TuneCache {
+  std::mutex mu;
+  std::map<TuneKey, std::vector<int>> map;
+  bool loaded = false;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+TuneKey tune_key(int op, const Geo& g, int64_t batch) { return TuneKey{op, g.D, g.n[0], g.n[1], g.n[2], g.L, g.m, batch}; }
+
+void tune_load_locked(TuneCache& c) {
+  if (c.loaded) return;
+  c.loaded = true;
+  const char* path = getenv("ESWAVE_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[1024];
+  while (fgets(line, sizeof line, f)) {
+    TuneKey k;
+    long long b;
+    int used = 0;
+    if (sscanf(line, "eswave-tune-v1 %d %d %d %d %d %d %d %lld :%n", &k.op, &k.D, &k.n0, &k.n1, &k.n2, &k.L, &k.m, &b,
+               &used) < 8 || used == 0)
+      continue;
+    k.batch = b;
+    std::vector<int> v;
+    const char* p = line + used;
+    int x, n;
+    while (sscanf(p, "%d%n", &x, &n) == 1) { v.push_back(x); p += n; }
+    c.map[k] = v;
+  }
+  fclose(f);
+}
+
+bool tune_lookup(const TuneKey& k, std::vector<int>* v) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  tune_load_locked(c);
+  auto it = c.map.find(k);
+  if (it == c.map.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void tune_store(const TuneKey& k, const std::vector<int>& v) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  tune_load_locked(c);
+  c.map[k] = v;
+  const char* path = getenv("ESWAVE_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "eswave-tune-v1 %d %d %d %d %d %d %d %lld :", k.op, k.D, k.n0, k.n1, k.n2, k.L, k.m, (long long)k.batch);
+  for (int x : v) fprintf(f, " %d", x);
+  fprintf(f, "\n");
+  fclose(f);
+}
+
+// Use the tuned variants when the cache holds this geometry (and no variant is forced).
+void apply_tuned(Schedule* sc, int op, const Geo& g, int64_t batch) {
+  if (forced_variant() >= 0) return;
+  std::vector<int> v;
+  if (!tune_lookup(tune_key(op, g, batch), &v) || v.size() != sc->launches.size()) return;
+  for (size_t j = 0; j < v.size(); ++j) {
+    Launch& l = sc->launches[j];
+    if (!l.is_tail && v[j] >= 0 && v[j] < kNumVariants) apply_variant(l, g, v[j], batch);
+  }
+}
 
 // Consecutive launches walk their tiles in opposite orders, and the last launch (the finest
 // up level, which re-reads the input) runs opposite to the first (the finest down level, which
@@ -309,8 +405,8 @@ void set_orders(Schedule* sc) {
   if (n >= 2 && reverse_orders()) sc->launches[n - 1].reverse = sc->launches[0].reverse ^ 1;
 }
 
-es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, float* out, float* ws,
-                         Schedule* sc) {
+es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* in, float* out, float* ws,
+                             Schedule* sc) {
   sc->launches.clear();
   sc->identity = false;
   if (!get_filter(g.L, &sc->f)) return fail(ES_EUNSUPPORTED, "filter derivation failed for order %d", g.L / 2);
@@ -543,6 +639,13 @@ es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, f
   }
   set_orders(sc);
   return ES_OK;
+}
+
+es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, float* out, float* ws,
+                         Schedule* sc) {
+  es_status st = build_schedule_raw(op, g, batch, in, out, ws, sc);
+  if (st == ES_OK && !sc->identity) apply_tuned(sc, op, g, batch);
+  return st;
 }
 
 int64_t round8(int64_t v) { return (v + 7) & ~(int64_t)7; }
@@ -1102,8 +1205,13 @@ es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t b
   char buf[128];
   int lev = 0;
   while (lev < 31 && (g.n[2] >> lev) != (l.is_tail ? l.tail.b[2] : l.task.b[2])) ++lev;
-  snprintf(buf, sizeof buf, "%s_%dd_L%d_v%d%s", l.is_tail ? tails[l.kind] : kinds[l.kind], l.D, l.L, l.variant,
-           l.vec ? "" : "_scalar");
+  if (l.is_tail) {
+    snprintf(buf, sizeof buf, "%s_%dd_L%d", tails[l.kind], l.D, l.L);
+  } else {
+    const TileShape ts = tile_shape(l.kind, l.D, l.variant, l.L);
+    snprintf(buf, sizeof buf, "%s_%dd_L%d_v%d_t%dx%dx%d%s", kinds[l.kind], l.D, l.L, l.variant, ts.t[0], ts.t[1],
+             ts.t[2], l.vec ? "" : "_scalar");
+  }
   if (name && name_len) {
     strncpy(name, buf, name_len - 1);
     name[name_len - 1] = 0;
@@ -1132,6 +1240,63 @@ es_status es_schedule_run_step(int op, int ndim, const int64_t* shape, int64_t b
   const Launch& l = sc.launches[index];
   const int64_t total = (l.is_tail ? 1 : l.task.tiles_per_inst) * batch;
   return run_launch(l, sc.f, (hipStream_t)stream, nullptr, 1, (int)total, nullptr);
+}
+
+es_status es_autotune(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                      const float* in, float* out, void* ws, size_t ws_bytes, int32_t reps, void* stream) {
+  if (op < 0 || op > 3) return fail(ES_EINVAL, "unknown op %d", op);
+  Geo g;
+  es_status st = make_geo(ndim, shape, order, levels, s, &g);
+  if (st != ES_OK) return st;
+  const size_t need = (size_t)(batch > 0 ? batch : 0) * (size_t)ws_floats_per_instance(g) * sizeof(float);
+  const bool identity = (op >= ES_OP_COV) ? levels <= 1 : levels == 0;
+  st = check_io(in, out, batch, g.N(), ws, ws_bytes, identity ? 0 : need);
+  if (st != ES_OK) return st;
+  if (batch < 1 || identity) return ES_OK;
+  if (reps < 1) reps = 3;
+  st = check_device();
+  if (st != ES_OK) return st;
+  Schedule sc;
+  st = build_schedule_raw(op, g, batch, in, out, (float*)ws, &sc);
+  if (st != ES_OK) return st;
+  const hipStream_t hs = (hipStream_t)stream;
+  // one full pass so that every launch finds valid inputs in the workspace
+  st = run_schedule(sc, g, batch, in, out, hs);
+  if (st != ES_OK) return st;
+  hipEvent_t e0, e1;
+  ES_HIP(hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(ES_EDEVICE, "hipEventCreate"); }
+  std::vector<int> best(sc.launches.size(), -1);
+  for (size_t j = 0; j < sc.launches.size() && st == ES_OK; ++j) {
+    if (sc.launches[j].is_tail) continue;
+    float best_ms = 1e30f;
+    for (int v = 0; v < kNumVariants && st == ES_OK; ++v) {
+      Launch l = sc.launches[j];
+      apply_variant(l, g, v, batch);
+      const int total = (int)(l.task.tiles_per_inst * batch);
+      st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);  // warm
+      if (st != ES_OK) break;
+      if (hipEventRecord(e0, hs) != hipSuccess) { st = fail(ES_EDEVICE, "hipEventRecord"); break; }
+      for (int r = 0; r < reps && st == ES_OK; ++r) st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);
+      if (st != ES_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(ES_EDEVICE, "event timing failed");
+        break;
+      }
+      if (ms < best_ms) { best_ms = ms; best[j] = v; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ES_OK) return st;
+  tune_store(tune_key(op, g, batch), best);
+  // the timing runs repeated in-place launches: recompute the result with the tuned schedule
+  Schedule tuned;
+  st = build_schedule(op, g, batch, in, out, (float*)ws, &tuned);
+  if (st != ES_OK) return st;
+  return run_schedule(tuned, g, batch, in, out, hs);
 }
 
 es_status es_filter(int order, double* h_out) {

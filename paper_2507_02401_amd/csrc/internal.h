@@ -88,7 +88,8 @@ struct TailArgs {
 
 enum KernelKind { K_LP_DOWN = 0, K_LP_UP = 1, K_FB_DOWN = 2, K_FB_UP = 3, K_LP_UP2 = 4 };
 
-// Tile shape selection: each (kind, ndim, taps) has a "wide" and a "narrow" instantiation.
+// Tile shape selection: each (kind, ndim, taps) has wide (0), narrow (1) and medium (2) tiles.
+constexpr int kNumVariants = 3;
 struct TileShape {
   int t[3];  // output tile in the kernel's tiling space (half-res for analysis kinds,
              // full-res for synthesis kinds); padded dims are 1

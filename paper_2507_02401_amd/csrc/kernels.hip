@@ -1218,22 +1218,31 @@ struct Shape3 {
   int a, b, c;
 };
 constexpr Shape3 shape_of(int K, int D, int V, int L) {
-  if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : Shape3{1, 32, 64};
-  if (D == 1) return (K == K_LP_DOWN || K == K_FB_DOWN) ? (V == 0 ? Shape3{1, 1, 256} : Shape3{1, 1, 64})
-                                                          : (V == 0 ? Shape3{1, 1, 512} : Shape3{1, 1, 128});
+  // V: 0 wide, 1 narrow, 2 medium
+  if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 32, 64} : Shape3{1, 32, 128});
+  if (D == 1) {
+    const bool an = (K == K_LP_DOWN || K == K_FB_DOWN);
+    return an ? (V == 0 ? Shape3{1, 1, 256} : (V == 1 ? Shape3{1, 1, 64} : Shape3{1, 1, 128}))
+              : (V == 0 ? Shape3{1, 1, 512} : (V == 1 ? Shape3{1, 1, 128} : Shape3{1, 1, 256}));
+  }
   if (D == 2) {
     switch (K) {
-      case K_LP_DOWN: return V == 0 ? Shape3{1, 32, 64} : Shape3{1, 8, 16};
-      case K_LP_UP: return V == 0 ? Shape3{1, 64, 128} : Shape3{1, 16, 32};
-      case K_FB_DOWN: return V == 0 ? Shape3{1, 16, 32} : Shape3{1, 8, 16};
-      default: return V == 0 ? Shape3{1, 32, 64} : Shape3{1, 16, 32};
+      case K_LP_DOWN: return V == 0 ? Shape3{1, 32, 64} : (V == 1 ? Shape3{1, 8, 16} : Shape3{1, 16, 64});
+      case K_LP_UP: return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 16, 32} : Shape3{1, 32, 128});
+      case K_FB_DOWN: return V == 0 ? Shape3{1, 16, 32} : (V == 1 ? Shape3{1, 8, 16} : Shape3{1, 16, 64});
+      default: return V == 0 ? Shape3{1, 32, 64} : (V == 1 ? Shape3{1, 16, 32} : Shape3{1, 32, 128});
     }
   }
   switch (K) {
-    case K_LP_DOWN: return V == 0 ? (L <= 8 ? Shape3{4, 8, 16} : Shape3{2, 4, 16}) : Shape3{2, 4, 8};
-    case K_LP_UP: return V == 0 ? Shape3{4, 16, 32} : Shape3{4, 8, 16};
-    case K_FB_DOWN: return V == 0 ? (L <= 8 ? Shape3{2, 8, 16} : Shape3{2, 4, 8}) : Shape3{2, 4, 8};
-    default: return V == 0 ? (L <= 8 ? Shape3{4, 16, 16} : Shape3{4, 8, 16}) : Shape3{4, 8, 16};
+    case K_LP_DOWN:
+      return V == 0 ? (L <= 8 ? Shape3{4, 8, 16} : Shape3{2, 4, 16})
+                    : (V == 1 ? Shape3{2, 4, 8} : (L <= 8 ? Shape3{2, 8, 16} : Shape3{2, 4, 8}));
+    case K_LP_UP: return V == 0 ? Shape3{4, 16, 32} : (V == 1 ? Shape3{4, 8, 16} : Shape3{4, 8, 32});
+    case K_FB_DOWN:
+      return V == 0 ? (L <= 8 ? Shape3{2, 8, 16} : Shape3{2, 4, 8}) : (V == 1 ? Shape3{2, 4, 8} : Shape3{2, 4, 16});
+    default:
+      return V == 0 ? (L <= 8 ? Shape3{4, 16, 16} : Shape3{4, 8, 16})
+                    : (V == 1 ? Shape3{4, 8, 16} : (L <= 8 ? Shape3{4, 8, 32} : Shape3{4, 8, 16}));
   }
 }
 constexpr int kThreads = 256;
@@ -1259,6 +1268,7 @@ hipError_t launch_kind(const TaskArgs& a, int grid, const Filter& f, hipStream_t
 template <int K, int D, int L>
 hipError_t launch_kdl(int variant, bool vec, const TaskArgs& a, int grid, const Filter& f, hipStream_t s) {
   if (variant == 0) return vec ? launch_kind<K, D, L, 0, true>(a, grid, f, s) : launch_kind<K, D, L, 0, false>(a, grid, f, s);
+  if (variant == 2) return vec ? launch_kind<K, D, L, 2, true>(a, grid, f, s) : launch_kind<K, D, L, 2, false>(a, grid, f, s);
   return vec ? launch_kind<K, D, L, 1, true>(a, grid, f, s) : launch_kind<K, D, L, 1, false>(a, grid, f, s);
 }
 

@@ -98,6 +98,24 @@ def plain_op(op, x, ndim, order, levels, s, out=None):
     return out
 
 
+def autotune(op, x, ndim, order, levels, s, out=None, reps=3):
+    """Measure every tile variant of every launch for this geometry and batch; later calls with
+    the same geometry use the fastest.  Returns the operator's result (computed with them)."""
+    grid, batch = _split(x, ndim)
+    x = x.contiguous()
+    out = torch.empty_like(x) if out is None else out
+    lib = load()
+    shp = shape_arg(grid)
+    need = int(lib.es_workspace_bytes(ndim, shp, batch, int(order), int(levels), int(op)))
+    ws = _ws(need, x.device, None)
+    with torch.cuda.device(x.device):
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        st = lib.es_autotune(int(op), ndim, shp, batch, int(order), int(levels), float(s), x.data_ptr(), out.data_ptr(),
+                             ws.data_ptr() if ws is not None else None, need, int(reps), stream)
+    check(st)
+    return out
+
+
 def matern_to_s(nu, d):
     """Sobolev index s = nu + d/2 of the Matern covariance Gamma_{nu, sqrt(2 nu)} (Prop. 3.2)."""
     return nu + d / 2.0
