@@ -429,11 +429,13 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
     std::vector<double> w(m + 2), c(m + 1);
     for (int i = 1; i <= m; ++i) w[i] = wdet(g, tau, i);
     for (int i = 1; i <= m - 1; ++i) c[i] = w[i + 1] - w[i];
-    // The LDS-resident low-pass tail kernel is switched off: a 1-D run of it ended in a GPU
-    // memory-aperture fault whose cause has not been found (see the design notes).  Every
-    // level goes through the LP_DOWN / LP_UP tile kernels instead.
-    const int T = -1;
-    const bool tail = false;
+    // Coarse levels whose block fits kCoarseMaxBlock run in one work-group per instance
+    // (tail kind 3).  The first low-pass tail kernel (kind 0) stays switched off: a 1-D run of
+    // it ended in a GPU memory-aperture fault whose cause has not been found.
+    int T = -1;
+    for (int i = 0; i <= m - 2; ++i)
+      if (g.level_size(i) <= std::min<int64_t>(tail_max(D), kCoarseMaxBlock)) { T = i; break; }
+    const bool tail = T >= 0;
     const int down_to = tail ? T : m - 1;
     for (int i = 1; i <= down_to; ++i) {
       Launch l = level_launch(K_LP_DOWN, g, i, batch);
@@ -452,7 +454,7 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
     if (tail) {
       Launch l{};
       l.is_tail = 1;
-      l.kind = 0;
+      l.kind = 3;
       l.D = D;
       l.L = g.L;
       TailTask& t = l.tail;
@@ -466,7 +468,7 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
       t.batch = (int32_t)batch;
       t.coef[0] = (float)(T == 0 ? w[1] : c[T]);
       for (int j = 1; j <= K; ++j) t.coef[j] = (float)c[T + j];
-      l.lds = tail_lds_bytes(0, D, t.b, K);
+      l.lds = 0;  // static LDS
       sc->launches.push_back(l);
     }
     const int up_from = tail ? T - 1 : m - 2;
@@ -1201,7 +1203,7 @@ es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t b
   if (index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
   const Launch& l = sc.launches[index];
   static const char* kinds[5] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2"};
-  static const char* tails[3] = {"tail_lp", "tail_fb_analysis", "tail_fb_synthesis"};
+  static const char* tails[4] = {"tail_lp_off", "tail_fb_analysis", "tail_fb_synthesis", "lp_coarse"};
   char buf[128];
   int lev = 0;
   while (lev < 31 && (g.n[2] >> lev) != (l.is_tail ? l.tail.b[2] : l.task.b[2])) ++lev;

@@ -59,8 +59,8 @@ struct TaskArgs {
 };
 
 // Tail: all coarse levels of one instance in one work-group (LDS resident).
-// kind: 0 = low-pass projection form (cov / sample), 1 = full analysis (adjoint),
-//       2 = full synthesis (apply).
+// kind: 0 = low-pass projection form, first version (switched off), 1 = full analysis
+//       (adjoint), 2 = full synthesis (apply), 3 = low-pass projection form (cov / sample).
 struct TailTask {
   const float* in;   // LP: a_T (contiguous block b); FBA: a_T; FBS: coeff (strided)
   float* out;        // LP: z_T in place of a_T, or y when T == 0; FBA: coeff; FBS: a_T or x
@@ -103,6 +103,8 @@ hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArg
 hipError_t launch_tail(int kind, int ndim, int taps, const TailArgs& args, int grid, size_t lds_bytes,
                        const Filter& f, hipStream_t stream);
 size_t tail_lds_bytes(int kind, int ndim, const int b[3], int nlev);
+// Largest block (floats) the low-pass coarse-level kernel (tail kind 3) holds in LDS.
+constexpr int kCoarseMaxBlock = 4096;
 int tail_threads();
 
 // Plain reference path: one launch per 1-D pass.

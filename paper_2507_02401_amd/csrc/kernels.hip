@@ -1028,6 +1028,171 @@ __global__ void __launch_bounds__(kTailThreads) k_tail_lp(TailArgs args, Filter 
   }
 }
 
+// ---------------------------------------------------------------------------------------
+// LP_COARSE: the coarse levels of the projection form for one instance in one work-group.
+// Input a_T (a contiguous block of at most kCoarseMax floats), output z_T in place (or y when
+// T = 0).  Everything between the load and the store stays in a static LDS array addressed by
+// integer offsets: A_0 = a_T, A_1 = a_{T+1}, ..., A_K, then two half-size temporaries.
+//   down:  A_{j+1} = A A_j                       (separable, contiguous axis first)
+//   top:   A_K *= c_{T+K}
+//   up:    A_j = coef_j A_j + A^T A_{j+1}        (j = K-1 .. 0; coef_0 is the output weight)
+// Axes at least L long wrap with one compare; shorter ones use the modulo (periodic folding).
+
+constexpr int kCoarseMax = kCoarseMaxBlock;
+constexpr int kCoarseLds = kCoarseMax * 2 + kCoarseMax;  // pyramid (<= 2B in 1-D) + temporaries
+
+// Index decomposition of a flat element index over (o0, o1, o2); shifts when o1, o2 are
+// powers of two (the common case), divisions otherwise.
+DEVI void split3(int e, int o1, int o2, int l1, int l2, int& c0, int& c1, int& c2) {
+  if (l1 >= 0 && l2 >= 0) {
+    c2 = e & (o2 - 1);
+    const int r = e >> l2;
+    c1 = r & (o1 - 1);
+    c0 = r >> l1;
+  } else {
+    c2 = e % o2;
+    const int r = e / o2;
+    c1 = r % o1;
+    c0 = r / o1;
+  }
+}
+
+DEVI int ilog2_or_neg(int v) { return (v & (v - 1)) == 0 ? 31 - __builtin_clz(v) : -1; }
+
+template <int L>
+DEVI void coarse_analysis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f) {
+  // sm[src] holds an (n0, n1, n2) block; writes the low half along ax, (.., n_ax/2, ..), to sm[dst]
+  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+  const int o0 = ax == 0 ? n0 >> 1 : n0, o1 = ax == 1 ? n1 >> 1 : n1, o2 = ax == 2 ? n2 >> 1 : n2;
+  const int l1 = ilog2_or_neg(o1), l2 = ilog2_or_neg(o2);
+  const int step = ax == 0 ? n1 * n2 : (ax == 1 ? n2 : 1);
+  const int total = o0 * o1 * o2;
+  const bool longax = n >= L;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, o1, o2, l1, l2, c0, c1, c2);
+    const int k = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+    const int base = src + (ax == 0 ? 0 : c0 * n1 * n2) + (ax == 1 ? 0 : c1 * n2) + (ax == 2 ? 0 : c2);
+    float acc = 0.f;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      int i = 2 * k + t;
+      i = longax ? (i >= n ? i - n : i) : i % n;
+      acc = fmaf(f.h[t], sm[base + i * step], acc);
+    }
+    sm[dst + e] = acc;
+  }
+}
+
+template <int L>
+DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f, bool combine,
+                           float alpha) {
+  // sm[src] holds the low half along ax of an (n0, n1, n2) block; writes the full block to
+  // sm[dst] (dst = alpha*dst + value when combine)
+  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2), half = n >> 1;
+  const int h0 = ax == 0 ? half : n0, h1 = ax == 1 ? half : n1, h2 = ax == 2 ? half : n2;
+  const int step = ax == 0 ? h1 * h2 : (ax == 1 ? h2 : 1);
+  const int total = n0 * n1 * n2;
+  const int l1 = ilog2_or_neg(n1), l2 = ilog2_or_neg(n2);
+  const bool longax = half >= L / 2;
+  (void)h0;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, n1, n2, l1, l2, c0, c1, c2);
+    const int p = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+    const int base = src + (ax == 0 ? 0 : c0 * h1 * h2) + (ax == 1 ? 0 : c1 * h2) + (ax == 2 ? 0 : c2);
+    const int par = p & 1, q = p >> 1;
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < L / 2; ++j) {
+      int k = q - j;
+      k = longax ? (k < 0 ? k + half : k) : pmod(k, half);
+      acc = fmaf(f.h[2 * j + par], sm[base + k * step], acc);
+    }
+    sm[dst + e] = combine ? fmaf(alpha, sm[dst + e], acc) : acc;
+  }
+}
+
+constexpr int kCoarseThreads = 1024;
+
+template <int D, int L>
+__global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Filter f) {
+  __shared__ float sm[kCoarseLds];
+  const int wg = logical_wg(args.total_wg);
+  if (wg < 0) return;
+  int ti = 0;
+  if (args.table != nullptr) {
+    int lo = 0, hi = args.count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (args.table[mid].tile_begin <= wg) lo = mid;
+      else hi = mid - 1;
+    }
+    ti = lo;
+  }
+  const TailTask* tp = args.table != nullptr ? args.table + ti : &args.t0;
+  const int inst = wg - tp->tile_begin;
+  const float* in = tp->in + inst * tp->bs_in;
+  float* out = tp->out + inst * tp->bs_out;
+  const int K = tp->nlev;
+  const int m0 = tp->b[0], m1 = tp->b[1], m2 = tp->b[2];
+  const int B = m0 * m1 * m2;
+  // offsets of A_0 .. A_K, then the temporaries
+  int tmpA = 0;
+  for (int j = 0; j <= K; ++j) tmpA += B >> (D * j);
+  const int tmpB = tmpA + (B >> 1);
+  for (int e = threadIdx.x; e < B; e += blockDim.x) sm[e] = gld(in + e);
+  __syncthreads();
+  int off = 0;
+  for (int j = 0; j < K; ++j) {
+    const int a0 = D >= 3 ? m0 >> j : 1, a1 = D >= 2 ? m1 >> j : 1, a2 = m2 >> j;
+    const int nxt = off + a0 * a1 * a2;
+    if (D == 1) {
+      coarse_analysis<L>(sm, off, nxt, a0, a1, a2, 2, f);
+    } else if (D == 2) {
+      coarse_analysis<L>(sm, off, tmpA, a0, a1, a2, 2, f);
+      __syncthreads();
+      coarse_analysis<L>(sm, tmpA, nxt, a0, a1, a2 >> 1, 1, f);
+    } else {
+      coarse_analysis<L>(sm, off, tmpA, a0, a1, a2, 2, f);
+      __syncthreads();
+      coarse_analysis<L>(sm, tmpA, tmpB, a0, a1, a2 >> 1, 1, f);
+      __syncthreads();
+      coarse_analysis<L>(sm, tmpB, nxt, a0, a1 >> 1, a2 >> 1, 0, f);
+    }
+    __syncthreads();
+    off = nxt;
+  }
+  {
+    const int sz = B >> (D * K);
+    const float ck = tp->coef[K];
+    for (int e = threadIdx.x; e < sz; e += blockDim.x) sm[off + e] *= ck;
+  }
+  __syncthreads();
+  for (int j = K - 1; j >= 0; --j) {
+    const int a0 = D >= 3 ? m0 >> j : 1, a1 = D >= 2 ? m1 >> j : 1, a2 = m2 >> j;  // output block
+    const int cur = off - a0 * a1 * a2;  // A_j precedes A_{j+1}
+    const float alpha = tp->coef[j];
+    if (D == 1) {
+      coarse_synthesis<L>(sm, off, cur, a0, a1, a2, 2, f, true, alpha);
+    } else if (D == 2) {
+      // contiguous axis first: (a1/2, a2/2) -> (a1/2, a2) in tmpA, then rows -> A_j
+      coarse_synthesis<L>(sm, off, tmpA, a0, a1 >> 1, a2, 2, f, false, 0.f);
+      __syncthreads();
+      coarse_synthesis<L>(sm, tmpA, cur, a0, a1, a2, 1, f, true, alpha);
+    } else {
+      coarse_synthesis<L>(sm, off, tmpA, a0 >> 1, a1 >> 1, a2, 2, f, false, 0.f);
+      __syncthreads();
+      coarse_synthesis<L>(sm, tmpA, tmpB, a0 >> 1, a1, a2, 1, f, false, 0.f);
+      __syncthreads();
+      coarse_synthesis<L>(sm, tmpB, cur, a0, a1, a2, 0, f, true, alpha);
+    }
+    __syncthreads();
+    off = cur;
+  }
+  for (int e = threadIdx.x; e < B; e += blockDim.x) gst(out + e, sm[e]);
+}
+
 // Full-bank tail.  SYN = false: analysis of levels T+1..m from a_T (contiguous `in`) into the
 // packed coefficient block (strided `out`).  SYN = true: synthesis from the packed block
 // (strided `in`) down to a_T (contiguous `out`, or strided when st_out is set).
@@ -1300,7 +1465,11 @@ hipError_t launch_k(int ndim, int taps, int variant, bool vec, const TaskArgs& a
 
 template <int D, int L>
 hipError_t launch_tail_dl(int kind, const TailArgs& a, int grid, size_t lds, const Filter& f, hipStream_t s) {
-  if (kind == 0) return hipErrorInvalidValue;  // low-pass tail switched off (unresolved GPU fault)
+  if (kind == 3) {  // low-pass coarse levels: static LDS
+    hipLaunchKernelGGL((k_lp_coarse<D, L>), dim3(grid), dim3(kCoarseThreads), 0, s, a, f);
+    return hipGetLastError();
+  }
+  if (kind == 0) return hipErrorInvalidValue;  // the first low-pass tail kernel stays switched off
   const void* fn = kind == 0 ? (const void*)k_tail_lp<D, L>
                              : (kind == 1 ? (const void*)k_tail_fb<D, L, false> : (const void*)k_tail_fb<D, L, true>);
   if (lds > 65536) {
