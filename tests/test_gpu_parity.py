@@ -153,3 +153,19 @@ def test_autotune_bit_identical(op, tmp_path, monkeypatch):
     for b in range(shape[0]):
         o = ORACLE_OPS[op](x[b].double().cpu().numpy(), order, levels, s)
         assert rel_l2(again[b].cpu().numpy(), o) <= TOL
+
+
+@pytest.mark.parametrize("streams", [2, 3, 4])
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_sub_batch_streams(op, streams, monkeypatch):
+    """Splitting a batch over several streams gives bit-identical results."""
+    shape, order, levels, s = (7, 96, 128), 4, 4, 1.5
+    x = torch.from_numpy(np.random.default_rng(12).standard_normal(shape).astype(np.float32)).to(DEV)
+    monkeypatch.setenv("ESWAVE_STREAMS", "1")
+    ref = es.apply_op(op, x, 2, order, levels, s)
+    monkeypatch.setenv("ESWAVE_STREAMS", str(streams))
+    monkeypatch.setenv("ESWAVE_SPLIT_MIN", "1")
+    say("streams", streams, OP_NAMES[op])
+    y = es.apply_op(op, x, 2, order, levels, s)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
