@@ -259,15 +259,23 @@ double tile_waste(int kind, const Geo& g, int level, int variant) {
   return covered / needed;
 }
 
+// Work-group count the tile heuristic assumes; ragged plans set it to their instance count so
+// that a level shared by many instances is tiled for the whole launch, not for one instance.
+thread_local int64_t g_variant_batch = 0;
+
 int pick_variant(int kind, const Geo& g, int level, int64_t batch) {
   const int fv = forced_variant();
   if (fv >= 0) return fv;
+  if (g_variant_batch > batch) batch = g_variant_batch;
   const double w0 = tile_waste(kind, g, level, 0), w1 = tile_waste(kind, g, level, 1);
   Task t{};
   set_tiles(t, kind, g, level, 0, batch);
   const int64_t wg0 = (int64_t)t.tiles_per_inst * batch;
-  if (w0 <= 1.25 && wg0 >= 1024) return 0;
-  if (w0 <= w1 && wg0 >= 2048) return 0;
+  // large levels: wide tiles for analysis, medium tiles for the synthesis kernels (measured
+  // fastest on 64 x 1024^2 db8); small levels: narrow tiles (more work-groups)
+  const int big = (kind == K_LP_UP || kind == K_FB_UP) ? 2 : 0;
+  if (w0 <= 1.25 && wg0 >= 1024) return big;
+  if (w0 <= w1 && wg0 >= 2048) return big;
   return 1;
 }
 
@@ -524,7 +532,7 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
   for (int i = 1; i <= m; ++i) w[i] = wdet(g, 1.0, i);
   int T = m;  // tail handles levels T+1..m from a_T
   for (int i = 0; i <= m - 1; ++i)
-    if (g.level_size(i) <= tail_max(D)) { T = i; break; }
+    if (g.level_size(i) <= std::min<int64_t>(tail_max(D), kFbCoarseMaxBlock)) { T = i; break; }
   const bool tail = T < m;
   auto approx_region = [&](int32_t st[2]) { st[0] = st_full[0]; st[1] = st_full[1]; };
 
@@ -942,8 +950,11 @@ namespace {
 es_status instance_schedule(const es_plan* p, int k, const float* in, float* out, void* ws, Schedule* sc) {
   const Geo& g = p->geos[k];
   float* wsk = ws ? (float*)ws + p->ws_off[k] : (float*)(uintptr_t)256;
-  return build_schedule(p->op, g, 1, in ? in : (const float*)(uintptr_t)256, out ? out : (float*)(uintptr_t)512, wsk,
-                        sc);
+  g_variant_batch = (int64_t)p->geos.size();
+  const es_status st = build_schedule(p->op, g, 1, in ? in : (const float*)(uintptr_t)256,
+                                      out ? out : (float*)(uintptr_t)512, wsk, sc);
+  g_variant_batch = 0;
+  return st;
 }
 
 // Phase of step j of an instance schedule: down steps get their level index, the tail 1000,

@@ -59,8 +59,8 @@ struct TaskArgs {
 };
 
 // Tail: all coarse levels of one instance in one work-group (LDS resident).
-// kind: 0 = low-pass projection form, first version (switched off), 1 = full analysis
-//       (adjoint), 2 = full synthesis (apply), 3 = low-pass projection form (cov / sample).
+// kind: 1 = full analysis (adjoint), 2 = full synthesis (apply), 3 = low-pass projection
+//       form (cov / sample).  (Kind 0, a first low-pass version, was removed.)
 struct TailTask {
   const float* in;   // LP: a_T (contiguous block b); FBA: a_T; FBS: coeff (strided)
   float* out;        // LP: z_T in place of a_T, or y when T == 0; FBA: coeff; FBS: a_T or x
@@ -105,6 +105,8 @@ hipError_t launch_tail(int kind, int ndim, int taps, const TailArgs& args, int g
 size_t tail_lds_bytes(int kind, int ndim, const int b[3], int nlev);
 // Largest block (floats) the low-pass coarse-level kernel (tail kind 3) holds in LDS.
 constexpr int kCoarseMaxBlock = 4096;
+// Largest block (floats) the full-bank coarse-level kernels (tail kinds 1, 2) hold in LDS.
+constexpr int kFbCoarseMaxBlock = 8192;
 int tail_threads();
 
 // Plain reference path: one launch per 1-D pass.

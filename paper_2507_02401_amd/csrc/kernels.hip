@@ -827,208 +827,6 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
 }
 
 // ---------------------------------------------------------------------------------------
-// Tail kernels: every remaining level of one instance inside one work-group's LDS.
-// Block sides may be shorter than the filter (periodic folding through the modulo).
-
-constexpr int kTailThreads = 256;
-
-struct Blk {
-  int n[3];
-  DEVI int size() const { return n[0] * n[1] * n[2]; }
-};
-
-// One 1-D pass along `ax` on a block laid out with strides (sr0, sr1, 1) in src and
-// (sd0, sd1, 1) in dst.  Analysis (FB=false: low-pass only, output extent n/2 along ax;
-// FB=true: [lo | hi]).  When the axis is at least L long a sample index wraps at most once
-// and the modulo reduces to a compare; shorter axes (periodic folding) take the modulo.
-template <int L, bool FB>
-DEVI void tail_analysis_axis(const float* src, int sr0, int sr1, float* dst, int sd0, int sd1, Blk b, int ax,
-                             const Filter& f) {
-  const int n = b.n[ax], half = n >> 1;
-  Blk o = b;
-  o.n[ax] = half;
-  const int total = o.size();
-  const int step = ax == 0 ? sr0 : (ax == 1 ? sr1 : 1);
-  const int dstep = ax == 0 ? sd0 : (ax == 1 ? sd1 : 1);
-  const bool longax = n >= L;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int c2 = e % o.n[2], r = e / o.n[2];
-    const int c1 = r % o.n[1], c0 = r / o.n[1];
-    const int k = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
-    const float* base = src + (ax == 0 ? 0 : c0 * sr0) + (ax == 1 ? 0 : c1 * sr1) + (ax == 2 ? 0 : c2);
-    float lo = 0.f, hi = 0.f;
-    if (longax) {
-#pragma unroll
-      for (int t = 0; t < L; ++t) {
-        int i = 2 * k + t;
-        i = i >= n ? i - n : i;
-        const float x = base[i * step];
-        lo = fmaf(f.h[t], x, lo);
-        if (FB) hi = fmaf(f.g[t], x, hi);
-      }
-    } else {
-#pragma unroll
-      for (int t = 0; t < L; ++t) {
-        const float x = base[((2 * k + t) % n) * step];
-        lo = fmaf(f.h[t], x, lo);
-        if (FB) hi = fmaf(f.g[t], x, hi);
-      }
-    }
-    float* d = dst + (ax == 0 ? 0 : c0 * sd0) + (ax == 1 ? 0 : c1 * sd1) + (ax == 2 ? 0 : c2);
-    d[k * dstep] = lo;
-    if (FB) d[(half + k) * dstep] = hi;
-  }
-}
-
-// Synthesis along `ax`: output block b (full extent n along ax); input has [lo | hi] (FB) or
-// lo only (extent n/2) along ax.  With `same`, dst = alpha*same + beta*value (same read with
-// dst strides), else dst = value.  Output p receives h[t] lo[k] + g[t] hi[k] for every tap t
-// with 2k + t = p (mod n), i.e. t = p (mod 2) and k = (p - t)/2 mod n/2.
-template <int L, bool FB>
-DEVI void tail_synthesis_axis(const float* src, int sr0, int sr1, float* dst, int sd0, int sd1, Blk b, int ax,
-                              const Filter& f, const float* same, float alpha, float beta) {
-  const int n = b.n[ax], half = n >> 1;
-  const int total = b.size();
-  const int step = ax == 0 ? sr0 : (ax == 1 ? sr1 : 1);
-  const bool longax = half >= L / 2;
-  for (int e = threadIdx.x; e < total; e += blockDim.x) {
-    const int c2 = e % b.n[2], r = e / b.n[2];
-    const int c1 = r % b.n[1], c0 = r / b.n[1];
-    const int p = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
-    const float* base = src + (ax == 0 ? 0 : c0 * sr0) + (ax == 1 ? 0 : c1 * sr1) + (ax == 2 ? 0 : c2);
-    float acc = 0.f;
-    const int par = p & 1, q = p >> 1;
-    if (longax) {
-#pragma unroll
-      for (int j = 0; j < L / 2; ++j) {
-        const int t = 2 * j + par;
-        int k = q - j;
-        k = k < 0 ? k + half : k;
-        acc = fmaf(f.h[t], base[k * step], acc);
-        if (FB) acc = fmaf(f.g[t], base[(half + k) * step], acc);
-      }
-    } else {
-#pragma unroll
-      for (int j = 0; j < L / 2; ++j) {
-        const int t = 2 * j + par;
-        const int k = pmod(q - j, half);
-        acc = fmaf(f.h[t], base[k * step], acc);
-        if (FB) acc = fmaf(f.g[t], base[(half + k) * step], acc);
-      }
-    }
-    const int o = c0 * sd0 + c1 * sd1 + c2;
-    if (same) dst[o] = fmaf(alpha, same[o], beta * acc);
-    else dst[o] = acc;
-  }
-}
-
-// Weight of the packed-pyramid element at (c0,c1,c2) of a tail block: tail level j detail
-// -> coef[j]; approximation (inside block >> nlev) -> coef[nlev].
-DEVI float tail_weight(const float* coef, int nlev, Blk b, int c0, int c1, int c2, int D) {
-  int j = 0;
-  while (j < nlev) {
-    const int s = j + 1;
-    const bool inside = (c2 < (b.n[2] >> s)) && (D < 2 || c1 < (b.n[1] >> s)) && (D < 3 || c0 < (b.n[0] >> s));
-    if (!inside) break;
-    ++j;
-  }
-  return coef[j];
-}
-
-template <int D>
-DEVI Blk half_blk(Blk b) {
-  Blk o = b;
-  o.n[2] >>= 1;
-  if (D >= 2) o.n[1] >>= 1;
-  if (D >= 3) o.n[0] >>= 1;
-  return o;
-}
-
-// Low-pass projection-form tail (cov / sample).
-template <int D, int L>
-__global__ void __launch_bounds__(kTailThreads) k_tail_lp(TailArgs args, Filter f) {
-  extern __shared__ float lds[];
-  const int wg = logical_wg(args.total_wg);
-  if (wg < 0) return;
-  const TailTask t = pick_task<TailTask>(args, wg);
-  const int inst = wg - t.tile_begin;
-  const float* in = t.in + inst * t.bs_in;
-  float* out = t.out + inst * t.bs_out;
-  const int K = t.nlev;
-  Blk lev[32];
-  lev[0] = Blk{{t.b[0], t.b[1], t.b[2]}};
-  for (int j = 1; j <= K; ++j) lev[j] = half_blk<D>(lev[j - 1]);
-  // LDS: A[0..K] back to back, then tmpA, tmpB (each half of A[0])
-  float* A[32];
-  int off = 0;
-  for (int j = 0; j <= K; ++j) { A[j] = lds + off; off += lev[j].size(); }
-  float* tmpA = lds + off;
-  float* tmpB = tmpA + (lev[0].size() >> 1);
-  const Blk b0 = lev[0];
-  // load a_T (contiguous)
-  for (int e = threadIdx.x; e < b0.size(); e += blockDim.x) A[0][e] = in[e];
-  __syncthreads();
-  // down
-  for (int j = 0; j < K; ++j) {
-    Blk cur = lev[j];
-    // dim 2
-    Blk o2 = cur; o2.n[2] >>= 1;
-    float* dst2 = (D == 1) ? A[j + 1] : tmpA;
-    tail_analysis_axis<L, false>(A[j], cur.n[1] * cur.n[2], cur.n[2], dst2, o2.n[1] * o2.n[2], o2.n[2], cur, 2, f);
-    __syncthreads();
-    if (D >= 2) {
-      Blk o1 = o2; o1.n[1] >>= 1;
-      float* dst1 = (D == 2) ? A[j + 1] : tmpB;
-      tail_analysis_axis<L, false>(tmpA, o2.n[1] * o2.n[2], o2.n[2], dst1, o1.n[1] * o1.n[2], o1.n[2], o2, 1, f);
-      __syncthreads();
-      if (D >= 3) {
-        Blk o0 = o1; o0.n[0] >>= 1;
-        tail_analysis_axis<L, false>(tmpB, o1.n[1] * o1.n[2], o1.n[2], A[j + 1], o0.n[1] * o0.n[2], o0.n[2], o1, 0,
-                                     f);
-        __syncthreads();
-      }
-    }
-  }
-  // z_{m-1} = c_{m-1} a_{m-1}
-  for (int e = threadIdx.x; e < lev[K].size(); e += blockDim.x) A[K][e] *= t.coef[K];
-  __syncthreads();
-  // up: A[j] = coef[j] A[j] + A^T A[j+1]; j = 0 goes to global
-  for (int j = K - 1; j >= 0; --j) {
-    const Blk cur = lev[j];   // output dims
-    const Blk hz = lev[j + 1];
-    const bool last = (j == 0);
-    float* dst = last ? out : A[j];
-    const float* same = A[j];
-    const float alpha = t.coef[j];
-    if (D == 1) {
-      tail_synthesis_axis<L, false>(A[j + 1], 0, 0, dst, 0, 0, cur, 2, f, same, alpha, 1.f);
-      __syncthreads();
-    } else if (D == 2) {
-      // dim 2 first: (h1, h2) -> (h1, 2 h2) in tmpA
-      Blk m1 = hz; m1.n[2] = cur.n[2];
-      tail_synthesis_axis<L, false>(A[j + 1], hz.n[1] * hz.n[2], hz.n[2], tmpA, m1.n[1] * m1.n[2], m1.n[2], m1, 2, f,
-                                    nullptr, 0.f, 1.f);
-      __syncthreads();
-      tail_synthesis_axis<L, false>(tmpA, m1.n[1] * m1.n[2], m1.n[2], dst, cur.n[1] * cur.n[2], cur.n[2], cur, 1, f,
-                                    same, alpha, 1.f);
-      __syncthreads();
-    } else {
-      Blk m1 = hz; m1.n[2] = cur.n[2];
-      tail_synthesis_axis<L, false>(A[j + 1], hz.n[1] * hz.n[2], hz.n[2], tmpA, m1.n[1] * m1.n[2], m1.n[2], m1, 2, f,
-                                    nullptr, 0.f, 1.f);
-      __syncthreads();
-      Blk m2 = m1; m2.n[1] = cur.n[1];
-      tail_synthesis_axis<L, false>(tmpA, m1.n[1] * m1.n[2], m1.n[2], tmpB, m2.n[1] * m2.n[2], m2.n[2], m2, 1, f,
-                                    nullptr, 0.f, 1.f);
-      __syncthreads();
-      tail_synthesis_axis<L, false>(tmpB, m2.n[1] * m2.n[2], m2.n[2], dst, cur.n[1] * cur.n[2], cur.n[2], cur, 0, f,
-                                    same, alpha, 1.f);
-      __syncthreads();
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------------------
 // LP_COARSE: the coarse levels of the projection form for one instance in one work-group.
 // Input a_T (a contiguous block of at most kCoarseMax floats), output z_T in place (or y when
 // T = 0).  Everything between the load and the store stays in a static LDS array addressed by
@@ -1193,95 +991,179 @@ __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Fil
   for (int e = threadIdx.x; e < B; e += blockDim.x) gst(out + e, sm[e]);
 }
 
-// Full-bank tail.  SYN = false: analysis of levels T+1..m from a_T (contiguous `in`) into the
-// packed coefficient block (strided `out`).  SYN = true: synthesis from the packed block
-// (strided `in`) down to a_T (contiguous `out`, or strided when st_out is set).
+// ---------------------------------------------------------------------------------------
+// FB_COARSE: the coarse levels of the full filter bank for one instance in one work-group.
+// The packed pyramid of a block of at most kFbCoarseMax floats lives in a static LDS array
+// (two copies for ping-pong), addressed by integer offsets; level j works on the leading
+// sub-block (n_k >> j per axis).  SYN = false: analysis of levels T+1..m from a_T (contiguous
+// input) into the packed coefficient block (strided output, detail bands weighted).
+// SYN = true: synthesis from the packed block (strided input, weighted) down to a_T.
+
+constexpr int kFbCoarseMax = kFbCoarseMaxBlock;
+constexpr int kFbCoarseThreads = 1024;
+
+template <int L>
+DEVI void fbc_analysis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+  const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2), half = n >> 1;
+  const int o0 = ax == 0 ? half : b0, o1 = ax == 1 ? half : b1, o2 = ax == 2 ? half : b2;
+  const int l1 = ilog2_or_neg(o1), l2 = ilog2_or_neg(o2);
+  const int step = ax == 0 ? S0 : (ax == 1 ? S1 : 1);
+  const int total = o0 * o1 * o2;
+  const bool longax = n >= L;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, o1, o2, l1, l2, c0, c1, c2);
+    const int k = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+    const int other = (ax == 0 ? 0 : c0 * S0) + (ax == 1 ? 0 : c1 * S1) + (ax == 2 ? 0 : c2);
+    float lo = 0.f, hi = 0.f;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+      int i = 2 * k + t;
+      i = longax ? (i >= n ? i - n : i) : i % n;
+      const float x = sm[src + other + i * step];
+      lo = fmaf(f.h[t], x, lo);
+      hi = fmaf(f.g[t], x, hi);
+    }
+    sm[dst + other + k * step] = lo;
+    sm[dst + other + (half + k) * step] = hi;
+  }
+}
+
+template <int L>
+DEVI void fbc_synthesis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+  const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2), half = n >> 1;
+  const int l1 = ilog2_or_neg(b1), l2 = ilog2_or_neg(b2);
+  const int step = ax == 0 ? S0 : (ax == 1 ? S1 : 1);
+  const int total = b0 * b1 * b2;
+  const bool longax = half >= L / 2;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, b1, b2, l1, l2, c0, c1, c2);
+    const int p = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
+    const int other = (ax == 0 ? 0 : c0 * S0) + (ax == 1 ? 0 : c1 * S1) + (ax == 2 ? 0 : c2);
+    const int par = p & 1, q = p >> 1;
+    float acc = 0.f;
+#pragma unroll
+    for (int j = 0; j < L / 2; ++j) {
+      int k = q - j;
+      k = longax ? (k < 0 ? k + half : k) : pmod(k, half);
+      acc = fmaf(f.h[2 * j + par], sm[src + other + k * step], acc);
+      acc = fmaf(f.g[2 * j + par], sm[src + other + (half + k) * step], acc);
+    }
+    sm[dst + other + p * step] = acc;
+  }
+}
+
+// Weight of the packed-pyramid element at (c0,c1,c2) of a coarse block: detail of coarse
+// level j -> coef[j]; approximation (inside the block >> nlev) -> coef[nlev].
+DEVI float fbc_weight(const float* coef, int nlev, int n0, int n1, int n2, int c0, int c1, int c2, int D) {
+  int j = 0;
+  while (j < nlev) {
+    const int sh = j + 1;
+    const bool inside = (c2 < (n2 >> sh)) && (D < 2 || c1 < (n1 >> sh)) && (D < 3 || c0 < (n0 >> sh));
+    if (!inside) break;
+    ++j;
+  }
+  return coef[j];
+}
+
 template <int D, int L, bool SYN>
-__global__ void __launch_bounds__(kTailThreads) k_tail_fb(TailArgs args, Filter f) {
-  extern __shared__ float lds[];
+__global__ void __launch_bounds__(kFbCoarseThreads) k_fb_coarse(TailArgs args, Filter f) {
+  __shared__ float sm[2 * kFbCoarseMax];
   const int wg = logical_wg(args.total_wg);
   if (wg < 0) return;
-  const TailTask t = pick_task<TailTask>(args, wg);
-  const int inst = wg - t.tile_begin;
-  const float* in = t.in + inst * t.bs_in;
-  float* out = t.out + inst * t.bs_out;
-  const Blk B = Blk{{t.b[0], t.b[1], t.b[2]}};
-  const int S0 = B.n[1] * B.n[2], S1 = B.n[2];  // LDS strides of the packed block
-  float* cur = lds;
-  float* tmp = lds + B.size();
-  const int nl = t.nlev;
-
-  if (!SYN) {
-    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) cur[e] = in[e];
-    __syncthreads();
-    Blk sb = B;
-    for (int j = 0; j < nl; ++j) {
-      // passes dim 2 (cur->tmp), dim 1 (tmp->cur), dim 0 (cur->tmp); copy back if needed
-      tail_analysis_axis<L, true>(cur, S0, S1, tmp, S0, S1, sb, 2, f);
-      __syncthreads();
-      float* res = tmp;
-      if (D >= 2) {
-        tail_analysis_axis<L, true>(tmp, S0, S1, cur, S0, S1, sb, 1, f);
-        __syncthreads();
-        res = cur;
-        if (D >= 3) {
-          tail_analysis_axis<L, true>(cur, S0, S1, tmp, S0, S1, sb, 0, f);
-          __syncthreads();
-          res = tmp;
-        }
-      }
-      if (res != cur) {
-        for (int e = threadIdx.x; e < sb.size(); e += blockDim.x) {
-          const int c2 = e % sb.n[2], r = e / sb.n[2], c1 = r % sb.n[1], c0 = r / sb.n[1];
-          const int o = c0 * S0 + c1 * S1 + c2;
-          cur[o] = tmp[o];
-        }
-        __syncthreads();
-      }
-      sb = half_blk<D>(sb);
+  int ti = 0;
+  if (args.table != nullptr) {
+    int lo = 0, hi = args.count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (args.table[mid].tile_begin <= wg) lo = mid;
+      else hi = mid - 1;
     }
-    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) {
-      const int c2 = e % B.n[2], r = e / B.n[2], c1 = r % B.n[1], c0 = r / B.n[1];
-      const float w = tail_weight(t.coef, nl, B, c0, c1, c2, D);
-      out[(D >= 3 ? c0 * t.st_out[0] : 0) + (D >= 2 ? c1 * t.st_out[1] : 0) + c2] = w * cur[e];
+    ti = lo;
+  }
+  const TailTask* tp = args.table != nullptr ? args.table + ti : &args.t0;
+  const int inst = wg - tp->tile_begin;
+  const float* in = tp->in + inst * tp->bs_in;
+  float* out = tp->out + inst * tp->bs_out;
+  const int n0 = tp->b[0], n1 = tp->b[1], n2 = tp->b[2];
+  const int B = n0 * n1 * n2, S0 = n1 * n2, S1 = n2;
+  const int l1 = ilog2_or_neg(n1), l2 = ilog2_or_neg(n2);
+  const int nl = tp->nlev;
+  const int in0 = tp->st_in[0], in1 = tp->st_in[1], out0 = tp->st_out[0], out1 = tp->st_out[1];
+  constexpr int CUR = 0, TMP = kFbCoarseMax;
+  auto copy_back = [&](int b0, int b1, int b2) {  // TMP sub-block -> CUR
+    const int t1 = ilog2_or_neg(b1), t2 = ilog2_or_neg(b2);
+    for (int e = threadIdx.x; e < b0 * b1 * b2; e += blockDim.x) {
+      int c0, c1, c2;
+      split3(e, b1, b2, t1, t2, c0, c1, c2);
+      const int o = c0 * S0 + c1 * S1 + c2;
+      sm[CUR + o] = sm[TMP + o];
+    }
+  };
+  if (!SYN) {
+    for (int e = threadIdx.x; e < B; e += blockDim.x) sm[CUR + e] = gld(in + e);
+    __syncthreads();
+    for (int j = 0; j < nl; ++j) {
+      const int b0 = D >= 3 ? n0 >> j : 1, b1 = D >= 2 ? n1 >> j : 1, b2 = n2 >> j;
+      // dim 2: CUR -> TMP, dim 1: TMP -> CUR, dim 0: CUR -> TMP
+      fbc_analysis<L>(sm, CUR, TMP, S0, S1, b0, b1, b2, 2, f);
+      __syncthreads();
+      bool in_tmp = true;
+      if (D >= 2) {
+        fbc_analysis<L>(sm, TMP, CUR, S0, S1, b0, b1, b2, 1, f);
+        __syncthreads();
+        in_tmp = false;
+        if (D >= 3) {
+          fbc_analysis<L>(sm, CUR, TMP, S0, S1, b0, b1, b2, 0, f);
+          __syncthreads();
+          in_tmp = true;
+        }
+      }
+      if (in_tmp) {
+        copy_back(b0, b1, b2);
+        __syncthreads();
+      }
+    }
+    for (int e = threadIdx.x; e < B; e += blockDim.x) {
+      int c0, c1, c2;
+      split3(e, n1, n2, l1, l2, c0, c1, c2);
+      const float w = fbc_weight(tp->coef, nl, n0, n1, n2, c0, c1, c2, D);
+      gst(out + (D >= 3 ? c0 * out0 : 0) + (D >= 2 ? c1 * out1 : 0) + c2, w * sm[CUR + e]);
     }
   } else {
-    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) {
-      const int c2 = e % B.n[2], r = e / B.n[2], c1 = r % B.n[1], c0 = r / B.n[1];
-      const float w = tail_weight(t.coef, nl, B, c0, c1, c2, D);
-      cur[e] = w * in[(D >= 3 ? c0 * t.st_in[0] : 0) + (D >= 2 ? c1 * t.st_in[1] : 0) + c2];
+    for (int e = threadIdx.x; e < B; e += blockDim.x) {
+      int c0, c1, c2;
+      split3(e, n1, n2, l1, l2, c0, c1, c2);
+      const float w = fbc_weight(tp->coef, nl, n0, n1, n2, c0, c1, c2, D);
+      sm[CUR + e] = w * gld(in + (D >= 3 ? c0 * in0 : 0) + (D >= 2 ? c1 * in1 : 0) + c2);
     }
     __syncthreads();
     for (int j = nl - 1; j >= 0; --j) {
-      Blk sb = B;
-      for (int q = 0; q < j; ++q) sb = half_blk<D>(sb);
-      // passes in reverse: dim 0 (3-D), dim 1, dim 2; ping-pong cur/tmp
-      float* a = cur;
-      float* bb = tmp;
+      const int b0 = D >= 3 ? n0 >> j : 1, b1 = D >= 2 ? n1 >> j : 1, b2 = n2 >> j;
+      // dim 0 (3-D), dim 1, dim 2, ping-pong starting from CUR
+      int a = CUR, bb = TMP;
       if (D >= 3) {
-        tail_synthesis_axis<L, true>(a, S0, S1, bb, S0, S1, sb, 0, f, nullptr, 0.f, 1.f);
+        fbc_synthesis<L>(sm, a, bb, S0, S1, b0, b1, b2, 0, f);
         __syncthreads();
-        float* s = a; a = bb; bb = s;
+        const int t = a; a = bb; bb = t;
       }
       if (D >= 2) {
-        tail_synthesis_axis<L, true>(a, S0, S1, bb, S0, S1, sb, 1, f, nullptr, 0.f, 1.f);
+        fbc_synthesis<L>(sm, a, bb, S0, S1, b0, b1, b2, 1, f);
         __syncthreads();
-        float* s = a; a = bb; bb = s;
+        const int t = a; a = bb; bb = t;
       }
-      tail_synthesis_axis<L, true>(a, S0, S1, bb, S0, S1, sb, 2, f, nullptr, 0.f, 1.f);
+      fbc_synthesis<L>(sm, a, bb, S0, S1, b0, b1, b2, 2, f);
       __syncthreads();
-      if (bb != cur) {
-        for (int e = threadIdx.x; e < sb.size(); e += blockDim.x) {
-          const int c2 = e % sb.n[2], r = e / sb.n[2], c1 = r % sb.n[1], c0 = r / sb.n[1];
-          const int o = c0 * S0 + c1 * S1 + c2;
-          cur[o] = bb[o];
-        }
+      if (bb != CUR) {
+        copy_back(b0, b1, b2);
         __syncthreads();
       }
     }
-    for (int e = threadIdx.x; e < B.size(); e += blockDim.x) {
-      const int c2 = e % B.n[2], r = e / B.n[2], c1 = r % B.n[1], c0 = r / B.n[1];
-      out[(D >= 3 ? c0 * t.st_out[0] : 0) + (D >= 2 ? c1 * t.st_out[1] : 0) + c2] = cur[e];
+    for (int e = threadIdx.x; e < B; e += blockDim.x) {
+      int c0, c1, c2;
+      split3(e, n1, n2, l1, l2, c0, c1, c2);
+      gst(out + (D >= 3 ? c0 * out0 : 0) + (D >= 2 ? c1 * out1 : 0) + c2, sm[CUR + e]);
     }
   }
 }
@@ -1464,24 +1346,13 @@ hipError_t launch_k(int ndim, int taps, int variant, bool vec, const TaskArgs& a
 }
 
 template <int D, int L>
-hipError_t launch_tail_dl(int kind, const TailArgs& a, int grid, size_t lds, const Filter& f, hipStream_t s) {
-  if (kind == 3) {  // low-pass coarse levels: static LDS
-    hipLaunchKernelGGL((k_lp_coarse<D, L>), dim3(grid), dim3(kCoarseThreads), 0, s, a, f);
-    return hipGetLastError();
+hipError_t launch_tail_dl(int kind, const TailArgs& a, int grid, size_t, const Filter& f, hipStream_t s) {
+  switch (kind) {
+    case 1: hipLaunchKernelGGL((k_fb_coarse<D, L, false>), dim3(grid), dim3(kFbCoarseThreads), 0, s, a, f); break;
+    case 2: hipLaunchKernelGGL((k_fb_coarse<D, L, true>), dim3(grid), dim3(kFbCoarseThreads), 0, s, a, f); break;
+    case 3: hipLaunchKernelGGL((k_lp_coarse<D, L>), dim3(grid), dim3(kCoarseThreads), 0, s, a, f); break;
+    default: return hipErrorInvalidValue;  // kind 0 (first low-pass tail) was removed
   }
-  if (kind == 0) return hipErrorInvalidValue;  // the first low-pass tail kernel stays switched off
-  const void* fn = kind == 0 ? (const void*)k_tail_lp<D, L>
-                             : (kind == 1 ? (const void*)k_tail_fb<D, L, false> : (const void*)k_tail_fb<D, L, true>);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  if (kind == 0)
-    hipLaunchKernelGGL((k_tail_lp<D, L>), dim3(grid), dim3(kTailThreads), lds, s, a, f);
-  else if (kind == 1)
-    hipLaunchKernelGGL((k_tail_fb<D, L, false>), dim3(grid), dim3(kTailThreads), lds, s, a, f);
-  else
-    hipLaunchKernelGGL((k_tail_fb<D, L, true>), dim3(grid), dim3(kTailThreads), lds, s, a, f);
   return hipGetLastError();
 }
 
@@ -1523,7 +1394,7 @@ TileShape tile_shape(int kind, int ndim, int variant, int taps) {
 }
 
 int tile_threads(int, int, int) { return kThreads; }
-int tail_threads() { return kTailThreads; }
+int tail_threads() { return kFbCoarseThreads; }
 
 hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArgs& args, int grid, const Filter& f,
                         hipStream_t stream) {
@@ -1551,15 +1422,7 @@ hipError_t launch_tail(int kind, int ndim, int taps, const TailArgs& args, int g
   return hipErrorInvalidValue;
 }
 
-size_t tail_lds_bytes(int kind, int ndim, const int b[3], int nlev) {
-  const size_t B = (size_t)b[0] * b[1] * b[2];
-  if (kind == 0) {
-    size_t tot = 0, cur = B;
-    for (int j = 0; j <= nlev; ++j) { tot += cur; cur >>= ndim; }
-    return (tot + B) * sizeof(float);  // pyramid + two half-size temporaries
-  }
-  return 2 * B * sizeof(float);
-}
+size_t tail_lds_bytes(int, int, const int[3], int) { return 0; }  // the coarse kernels use static LDS
 
 hipError_t launch_plain_pass(const PlainPass& p, int taps, const Filter& f, hipStream_t s) {
   switch (taps) {
