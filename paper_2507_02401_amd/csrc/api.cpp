@@ -204,6 +204,13 @@ bool reverse_orders() {
   const char* e = getenv("ESWAVE_NO_REVERSE");
   return !(e && *e == '1');
 }
+// Kernel family of 3-D full-bank levels: ESWAVE_STREAM3D=0 plain 3-D tiles only, 2 streamed
+// tiles at every level, otherwise (default) streamed where the level fills the chip.
+int stream3d() {
+  const char* e = getenv("ESWAVE_STREAM3D");
+  if (e && (*e == '0' || *e == '2')) return *e - '0';
+  return 1;
+}
 int forced_variant() {
   const char* e = getenv("ESWAVE_FORCE_VARIANT");
   if (e && *e >= '0' && *e < '0' + kNumVariants) return *e - '0';
@@ -233,7 +240,7 @@ void set_tiles(Task& t, int kind, const Geo& g, int level, int variant, int64_t 
   int b[3];
   g.level_dims(level - 1, b);  // full-res block of the level
   const TileShape ts = tile_shape(kind, g.D, variant, g.L);
-  const bool analysis = (kind == K_LP_DOWN || kind == K_FB_DOWN);
+  const bool analysis = kind_is_analysis(kind);
   for (int k = 0; k < 3; ++k) {
     t.b[k] = b[k];
     const bool real = k >= 3 - g.D;
@@ -249,7 +256,7 @@ double tile_waste(int kind, const Geo& g, int level, int variant) {
   int b[3];
   g.level_dims(level - 1, b);
   const TileShape ts = tile_shape(kind, g.D, variant, g.L);
-  const bool analysis = (kind == K_LP_DOWN || kind == K_FB_DOWN);
+  const bool analysis = kind_is_analysis(kind);
   double covered = 1, needed = 1;
   for (int k = 3 - g.D; k < 3; ++k) {
     const int extent = analysis ? b[k] / 2 : b[k];
@@ -283,11 +290,11 @@ int pick_variant(int kind, const Geo& g, int level, int64_t batch) {
 bool vec_ok(const Task& t, int kind, const Geo& g) {
   auto a16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
   auto m4 = [](int64_t v) { return (v & 3) == 0; };
-  const bool analysis = (kind == K_LP_DOWN || kind == K_FB_DOWN);
+  const bool analysis = kind_is_analysis(kind);
   const int row = analysis ? t.b[2] : (kind == K_LP_UP2 ? t.b[2] / 4 : t.b[2] / 2);  // staged input rows
   if (!m4(row)) return false;
   if (!a16(t.in0) || !m4(t.bs_in0) || !m4(t.st_in0[0]) || !m4(t.st_in0[1])) return false;
-  if (kind == K_FB_UP && (!a16(t.in1) || !m4(t.bs_in1) || !m4(t.st_in1[0]) || !m4(t.st_in1[1]))) return false;
+  if ((kind == K_FB_UP || kind == K_FB_UP_S) && (!a16(t.in1) || !m4(t.bs_in1) || !m4(t.st_in1[0]) || !m4(t.st_in1[1]))) return false;
   (void)g;
   return true;
 }
@@ -297,7 +304,23 @@ void strides_of(const int dims[3], int32_t st[2]) {
   st[1] = dims[2];
 }
 
+// 3-D full-bank levels have two kernel families: plain 3-D tiles, and tiles streamed along
+// axis 0 (no axis-0 halo re-reads, but one work-group walks R slices in sequence).  Streaming
+// wins when the level has enough tiles to fill the chip.
+bool is_fb3(const Launch& l) {
+  return !l.is_tail && l.D == 3 && (l.kind == K_FB_DOWN || l.kind == K_FB_UP || l.kind == K_FB_DOWN_S || l.kind == K_FB_UP_S);
+}
+int streamed_kind(int kind) { return kind_is_analysis(kind) ? K_FB_DOWN_S : K_FB_UP_S; }
+int tiled_kind(int kind) { return kind_is_analysis(kind) ? K_FB_DOWN : K_FB_UP; }
+
 Launch level_launch(int kind, const Geo& g, int level, int64_t batch) {
+  const int mode = stream3d();
+  if (g.D == 3 && (kind == K_FB_DOWN || kind == K_FB_UP) && mode != 0) {
+    const int sk = streamed_kind(kind);
+    Task t{};
+    set_tiles(t, sk, g, level, pick_variant(sk, g, level, batch), batch);
+    if (mode == 2 || (int64_t)t.tiles_per_inst * std::max<int64_t>(batch, g_variant_batch) >= 1024) kind = sk;
+  }
   Launch l{};
   l.is_tail = 0;
   l.kind = kind;
@@ -315,6 +338,14 @@ void apply_variant(Launch& l, const Geo& g, int v, int64_t batch) {
   l.variant = v;
   set_tiles(l.task, l.kind, g, l.level, v, batch);
   finish_level(l, g);
+}
+
+// Tunable choices of a level launch: its tile variants, and for 3-D full-bank levels the tile
+// variants of both kernel families (choice = variant + kNumVariants for the streamed family).
+int num_choices(const Launch& l) { return is_fb3(l) ? 2 * kNumVariants : kNumVariants; }
+void apply_choice(Launch& l, const Geo& g, int c, int64_t batch) {
+  if (is_fb3(l)) l.kind = c >= kNumVariants ? streamed_kind(l.kind) : tiled_kind(l.kind);
+  apply_variant(l, g, c % kNumVariants, batch);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -399,7 +430,7 @@ void apply_tuned(Schedule* sc, int op, const Geo& g, int64_t batch) {
   if (!tune_lookup(tune_key(op, g, batch), &v) || v.size() != sc->launches.size()) return;
   for (size_t j = 0; j < v.size(); ++j) {
     Launch& l = sc->launches[j];
-    if (!l.is_tail && v[j] >= 0 && v[j] < kNumVariants) apply_variant(l, g, v[j], batch);
+    if (!l.is_tail && v[j] >= 0 && v[j] < num_choices(l)) apply_choice(l, g, v[j], batch);
   }
 }
 
@@ -965,7 +996,7 @@ void step_phases(int op, const Geo& g, const Schedule& sc, std::vector<int>* ph)
   for (const Launch& l : sc.launches) {
     if (l.is_tail) {
       ph->push_back(op == ES_OP_APPLY ? 0 : 1000);
-    } else if (l.kind == K_LP_DOWN || l.kind == K_FB_DOWN) {
+    } else if (kind_is_analysis(l.kind)) {
       ph->push_back(++down);
     } else {
       // LP_UP / FB_UP: task.b is the full-res output block; its level index follows from size
@@ -1288,7 +1319,7 @@ es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t b
   if (st != ES_OK) return st;
   if (index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
   const Launch& l = sc.launches[index];
-  static const char* kinds[5] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2"};
+  static const char* kinds[7] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2", "fb_down_s", "fb_up_s"};
   static const char* tails[4] = {"tail_lp_off", "tail_fb_analysis", "tail_fb_synthesis", "lp_coarse"};
   char buf[128];
   int lev = 0;
@@ -1361,9 +1392,9 @@ es_status es_autotune(int op, int ndim, const int64_t* shape, int64_t batch, int
   for (size_t j = 0; j < sc.launches.size() && st == ES_OK; ++j) {
     if (sc.launches[j].is_tail) continue;
     float best_ms = 1e30f;
-    for (int v = 0; v < kNumVariants && st == ES_OK; ++v) {
+    for (int v = 0; v < num_choices(sc.launches[j]) && st == ES_OK; ++v) {
       Launch l = sc.launches[j];
-      apply_variant(l, g, v, batch);
+      apply_choice(l, g, v, batch);
       const int total = (int)(l.task.tiles_per_inst * batch);
       st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);  // warm
       if (st != ES_OK) break;

@@ -86,7 +86,16 @@ struct TailArgs {
   TailTask t0;
 };
 
-enum KernelKind { K_LP_DOWN = 0, K_LP_UP = 1, K_FB_DOWN = 2, K_FB_UP = 3, K_LP_UP2 = 4 };
+enum KernelKind {
+  K_LP_DOWN = 0,
+  K_LP_UP = 1,
+  K_FB_DOWN = 2,
+  K_FB_UP = 3,
+  K_LP_UP2 = 4,
+  K_FB_DOWN_S = 5,  // 3-D full analysis level, streamed along axis 0 (same Task fields as FB_DOWN)
+  K_FB_UP_S = 6     // 3-D full synthesis level, streamed along axis 0 (same Task fields as FB_UP)
+};
+inline bool kind_is_analysis(int k) { return k == K_LP_DOWN || k == K_FB_DOWN || k == K_FB_DOWN_S; }
 
 // Tile shape selection: each (kind, ndim, taps) has wide (0), narrow (1) and medium (2) tiles.
 constexpr int kNumVariants = 3;

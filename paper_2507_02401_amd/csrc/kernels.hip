@@ -44,6 +44,26 @@ DEVI float4 gld4(const float* p) {
 }
 DEVI void gst(float* p, float v) { *(GAS float*)p = v; }
 
+// Load n (at most U * NT) elements into LDS with every load of a thread issued before the
+// first LDS store, so that one work-group keeps U loads per thread in flight.  src(e) gives
+// the element's value (a global load), dst(e) its LDS slot.
+template <int NT, int U, class Src, class Dst>
+DEVI void gather_to_lds(int n, Src src, Dst dst) {
+  for (int base = threadIdx.x; base < n; base += U * NT) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NT;
+      v[u] = e < n ? src(e) : 0.f;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NT;
+      if (e < n) dst(e, v[u]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Work-group -> task/tile mapping.
 //
@@ -92,7 +112,9 @@ DEVI Tile decode_tile(const Task& t, int wg) {
 // analysis_pass: line l, chunk ch: window samples s[j] = In(l, 2*P*ch + j), j < 2P+L-2;
 // outputs k = P*ch + q:  lo = sum_t h[t] s[2q+t],  hi = sum_t g[t] s[2q+t].
 // synthesis_pass: window samples lo/hi In(l, P*ch + j), j < P+L/2-1; outputs p = 2(P*ch+q)+e:
-//   x = sum_{j<L/2} h[2j+e] lo[q+L/2-1-j] + g[2j+e] hi[q+L/2-1-j].
+//   x = sum_{j<L/2} h[2j+e] lo[q+L/2-1-j] + g[2j+e] hi[q+L/2-1-j],
+// summed from the oldest window sample (j = L/2-1) to the newest (j = 0), the order in which a
+// kernel streaming along the axis receives them.
 // LINES_FAST puts consecutive lanes on consecutive lines (strided passes: lines are columns
 // and LDS accesses are conflict-free); otherwise consecutive lanes take consecutive chunks
 // of one line (contiguous pass).
@@ -135,7 +157,7 @@ DEVI void synthesis_pass(int nlines, int nch, const Filter& f, In in, Out out) {
     for (int q = 0; q < P; ++q) {
       float e0 = 0.f, e1 = 0.f;
 #pragma unroll
-      for (int j = 0; j < H; ++j) {
+      for (int j = H - 1; j >= 0; --j) {
         const float a = lo[q + H - 1 - j];
         e0 = fmaf(f.h[2 * j], a, e0);
         e1 = fmaf(f.h[2 * j + 1], a, e1);
@@ -568,6 +590,325 @@ __global__ void __launch_bounds__(NT) k_lp_up2(TaskArgs args, Filter f) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Streamed 3-D full-bank levels.  A work-group owns an in-plane tile (axes 1, 2) and a run of
+// R output slices along axis 0, and visits the input slices the run needs in order: each slice
+// is staged (with its in-plane halo) and filtered in-plane once, and the axis-0 filter combines
+// the filtered slices (analysis: running sums in registers; synthesis: a ring of the last L/2
+// filtered slices in LDS).  Axis-0 halos are neither re-read nor recomputed except at the start
+// of a run, and the in-plane halo is the 2-D one.  The axes are filtered in the order 2, 1, 0
+// with the same arithmetic as the plain 3-D tiles, so both give identical results.
+
+// FB_DOWN_S: in-plane tile T1 x T2 per band, R output slices.  Iteration p stages input slices
+// 2p and 2p+1 of the work-group's run (with the in-plane halo), filters both in-plane, and adds
+// them to the axis-0 sums each thread keeps in registers for its in-plane positions.  Output
+// slice k takes input slices 2k .. 2k+L-1 in that order, so after iteration p output p-(H-1)
+// is complete; the sums then shift by one output.
+template <int L, int R, int T1, int T2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
+  constexpr int H = L / 2;
+  constexpr int I1 = 2 * T1 + L - 2, I2 = 2 * T2 + L - 2;
+  constexpr int I2P = (I2 + 3) & ~3, NV = I2P / 4;
+  constexpr int PL = 4 * T1 * T2;  // one filtered slice: rows [lo T1 | hi T1] x cols [lo T2 | hi T2]
+  constexpr int T2x = 2 * T2;
+  constexpr int P1 = T1 % 4 == 0 ? 4 : 2;
+  constexpr int NP = R + H - 1;  // iterations
+  constexpr int QT = PL / NT;    // in-plane positions per thread
+  static_assert(PL % NT == 0, "positions must divide evenly among the threads");
+  __shared__ __attribute__((aligned(16))) float s_in[2 * I1 * I2P];
+  __shared__ float s_pl[2 * PL];
+  __shared__ int s_row[I1];
+  __shared__ int s_col[NV];
+
+  const int wg = logical_wg(args.total_wg, args.reverse);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ src = t.in0 + tl.inst * t.bs_in0;
+  float* __restrict__ coef = t.out0 + tl.inst * t.bs_out0;
+  float* __restrict__ ll = t.out1 + tl.inst * t.bs_out1;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int h0 = b0 >> 1, h1 = b1 >> 1, h2 = b2 >> 1;
+  const int k0 = R * tl.c0, o1 = 2 * T1 * tl.c1, o2 = 2 * T2 * tl.c2;
+  const float alpha = t.alpha, beta = t.beta;
+
+  for (int i = threadIdx.x; i < I1; i += NT) s_row[i] = pmod(o1 + i, b1) * t.st_in0[1];
+  for (int i = threadIdx.x; i < NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
+  __syncthreads();
+
+  // vector path: the next pair's loads are issued before this pair is filtered, so their
+  // latency overlaps the in-plane passes (row length I2P = 4 NV: LDS slot = load index)
+  constexpr int NLD = 2 * I1 * NV, ITL = (NLD + NT - 1) / NT;
+  float4 pf[VEC ? ITL : 1];
+  auto load_pair = [&](int p) {
+    const int off0 = pmod(2 * (k0 + p), b0) * t.st_in0[0], off1 = pmod(2 * (k0 + p) + 1, b0) * t.st_in0[0];
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
+      const int e = q >= I1 * NV, r = q - e * I1 * NV;
+      pf[it] = gld4(src + (e ? off1 : off0) + s_row[r / NV] + s_col[r % NV]);
+    }
+  };
+  if constexpr (VEC) load_pair(0);
+
+  float alo[H][QT], ahi[H][QT];
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+#pragma unroll
+    for (int u = 0; u < QT; ++u) alo[j][u] = ahi[j][u] = 0.f;
+
+  for (int p = 0; p < NP; ++p) {
+    if constexpr (VEC) {
+      float4* d4 = reinterpret_cast<float4*>(s_in);
+#pragma unroll
+      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
+      __syncthreads();
+      load_pair(min(p + 1, NP - 1));
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        stage_rows<NT, I1, NV, false>(src + pmod(2 * (k0 + p) + e, b0) * t.st_in0[0], s_row, s_col,
+                                      s_in + e * I1 * I2P, I2P, b2);
+      __syncthreads();
+    }
+    row_pass_inplace<L, 4, 2 * I1, T2, I2P, NT, true>(s_in, f);  // rows (e, i1) of [lo T2 | hi T2]
+    analysis_pass<L, P1, true, true, NT>(
+        2 * T2x, T1 / P1, f,
+        [&](int l, int j0, float* w) {
+          const int e = l / T2x, c = l - e * T2x;
+#pragma unroll
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_in[(e * I1 + j0 + j) * T2x + c];
+        },
+        [&](int l, int k, float lo, float hi) {
+          const int e = l / T2x, c = l - e * T2x;
+          s_pl[e * PL + k * T2x + c] = lo;
+          s_pl[e * PL + (T1 + k) * T2x + c] = hi;
+        });
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < QT; ++u) {
+      const int q = threadIdx.x + u * NT;
+      const float x0 = s_pl[q], x1 = s_pl[PL + q];
+#pragma unroll
+      for (int j = 0; j < H; ++j) {  // output p - j takes taps 2j, 2j+1
+        alo[j][u] = fmaf(f.h[2 * j], x0, alo[j][u]);
+        ahi[j][u] = fmaf(f.g[2 * j], x0, ahi[j][u]);
+        alo[j][u] = fmaf(f.h[2 * j + 1], x1, alo[j][u]);
+        ahi[j][u] = fmaf(f.g[2 * j + 1], x1, ahi[j][u]);
+      }
+    }
+    const int g0 = k0 + p - (H - 1);  // output completed by this iteration
+    if (p >= H - 1 && g0 < h0) {
+#pragma unroll
+      for (int u = 0; u < QT; ++u) {
+        const int q = threadIdx.x + u * NT;
+        const int r = q / T2x, c = q - r * T2x;
+        const int e1 = r >= T1, e2 = c >= T2;
+        const int g1 = T1 * tl.c1 + r - e1 * T1, g2 = T2 * tl.c2 + c - e2 * T2;
+        if (g1 < h1 && g2 < h2) {
+          // band (e0, e1, e2) at half-res position (g0, g1, g2)
+          const float lo = alo[H - 1][u], hi = ahi[H - 1][u];
+          if ((e1 | e2) == 0) {
+            gst(ll + g0 * t.st_out1[0] + g1 * t.st_out1[1] + g2, beta * lo);
+          } else {
+            gst(coef + g0 * t.st_out0[0] + (e1 * h1 + g1) * t.st_out0[1] + e2 * h2 + g2, alpha * lo);
+          }
+          gst(coef + (h0 + g0) * t.st_out0[0] + (e1 * h1 + g1) * t.st_out0[1] + e2 * h2 + g2, alpha * hi);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = H - 1; j > 0; --j)
+#pragma unroll
+      for (int u = 0; u < QT; ++u) {
+        alo[j][u] = alo[j - 1][u];
+        ahi[j][u] = ahi[j - 1][u];
+      }
+#pragma unroll
+    for (int u = 0; u < QT; ++u) alo[0][u] = ahi[0][u] = 0.f;
+  }
+}
+
+// FB_UP_S: full-res output tile U1 x U2 in-plane, R output slices (R even).  Output pair Q (full-
+// res slices 2Q, 2Q+1) takes the half-res slices Q-(H-1) .. Q of the low (e0 = 0) and high
+// (e0 = 1) bands along axis 0.  Iteration p stages half-res slices 2p, 2p+1 of the run (8 bands
+// each, in-plane halo), synthesises them in-plane into a low and a high plane, and adds them to
+// the axis-0 sums each thread keeps in registers for its in-plane positions: slice r adds to
+// pairs r .. r+H-1, and pair r is complete once slice r is in.
+template <int L, int R, int U1, int U2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_fb_up_s(TaskArgs args, Filter f) {
+  constexpr int H = L / 2;
+  constexpr int J1 = U1 / 2 + H - 1, J2 = U2 / 2 + H - 1;
+  constexpr int OFF = (4 - ((H - 1) & 3)) & 3;
+  constexpr int J2P = (J2 + OFF + 3) & ~3, NV = J2P / 4;
+  constexpr int NR = 4 * J1;         // staged rows of one slice: (e0, e1, j1), each holding both e2 halves
+  constexpr int PLN = U1 * U2;        // one full-res in-plane plane
+  constexpr int P2 = 4, P1 = U1 / 2 % 4 == 0 ? 4 : 2;
+  constexpr int NS = R / 2 + H - 1;   // half-res slices the run needs
+  constexpr int NP = (NS + 1) / 2;    // iterations
+  constexpr int QT = PLN / NT;        // in-plane positions per thread
+  static_assert(R % 2 == 0, "R must be even");
+  static_assert(PLN % NT == 0, "positions must divide evenly among the threads");
+  __shared__ __attribute__((aligned(16))) float s_in[2 * NR * 2 * J2P];
+  __shared__ float s_a[2 * NR * U2];
+  __shared__ float s_pl[4 * PLN];  // (slice e, band e0) planes
+  __shared__ int s_rowc[2 * J1];   // in-plane row offsets into in1 for (e1, j1)
+  __shared__ int s_rowl[2 * J1];   // in-plane row offsets into in0 for j1 (used when e1 = 0)
+  __shared__ int s_col[2 * NV];
+
+  const int wg = logical_wg(args.total_wg, args.reverse);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ ap = t.in0 + tl.inst * t.bs_in0;
+  const float* __restrict__ cp = t.in1 + tl.inst * t.bs_in1;
+  float* __restrict__ out = t.out0 + tl.inst * t.bs_out0;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int h0 = b0 >> 1, h1 = b1 >> 1, h2 = b2 >> 1;
+  const int q0 = tl.c0 * (R / 2);  // first output pair (half-res index)
+  const int r1 = tl.c1 * (U1 / 2) - (H - 1), r2 = tl.c2 * (U2 / 2) - (H - 1) - OFF;
+  const float alpha = t.alpha, beta = t.beta;
+
+  for (int i = threadIdx.x; i < 2 * J1; i += NT) {
+    const int e1 = i / J1, j1 = i - e1 * J1;
+    s_rowc[i] = (e1 * h1 + pmod(r1 + j1, h1)) * t.st_in1[1];
+    s_rowl[i] = pmod(r1 + j1, h1) * t.st_in0[1];
+  }
+  for (int i = threadIdx.x; i < 2 * NV; i += NT) {
+    const int e2 = i / NV, v = i - e2 * NV;
+    s_col[i] = VEC ? pmod(r2 + 4 * v, h2) + e2 * h2 : r2 + 4 * v;
+  }
+  __syncthreads();
+
+  // vector path: the next pair's loads are issued before this pair is filtered
+  // (row length J2P = 4 NV: LDS slot = load index)
+  constexpr int NL1 = NR * 2 * NV, NLD = 2 * NL1, ITL = (NLD + NT - 1) / NT;
+  float4 pf[VEC ? ITL : 1];
+  auto load_pair = [&](int p) {
+    const int s0 = pmod(q0 - (H - 1) + 2 * p, h0), s1 = pmod(q0 - (H - 1) + 2 * p + 1, h0);
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
+      const int e = q >= NL1, qq = q - e * NL1;
+      const int r0g = e ? s1 : s0;
+      const int v = qq % NV, re = qq / NV;  // re = row * 2 + e2
+      const int e2 = re & 1, row = re >> 1;
+      const int e0 = row / (2 * J1), rr = row - e0 * 2 * J1;  // rr = e1 * J1 + j1
+      const bool isll = e0 == 0 && e2 == 0 && rr < J1;
+      const float* ptr = isll ? ap + r0g * t.st_in0[0] + s_rowl[rr] + s_col[v]
+                              : cp + (e0 * h0 + r0g) * t.st_in1[0] + s_rowc[rr] + s_col[e2 * NV + v];
+      float4 x = gld4(ptr);
+      const float sc = isll ? beta : alpha;
+      x.x *= sc; x.y *= sc; x.z *= sc; x.w *= sc;
+      pf[it] = x;
+    }
+  };
+  if constexpr (VEC) load_pair(0);
+
+  float ac0[H][QT], ac1[H][QT];  // pair r + j: full-res slices 2(r+j) and 2(r+j)+1
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+#pragma unroll
+    for (int u = 0; u < QT; ++u) ac0[j][u] = ac1[j][u] = 0.f;
+
+  for (int p = 0; p < NP; ++p) {
+    // stage: per slice, rows (e0, e1, j1) x (e2, J2P); band (0,0,0) from in0 (x beta), the rest
+    // from in1 (x alpha)
+    if constexpr (VEC) {
+      float4* d4 = reinterpret_cast<float4*>(s_in);
+#pragma unroll
+      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
+      __syncthreads();
+      load_pair(min(p + 1, NP - 1));
+    } else {
+      constexpr int N1 = NR * 2 * J2P;
+      for (int q = threadIdx.x; q < 2 * N1; q += NT) {
+        const int e = q >= N1, qq = q - e * N1;
+        const int r0g = pmod(q0 - (H - 1) + 2 * p + e, h0);
+        const int c = qq % J2P, re = qq / J2P;
+        const int e2 = re & 1, row = re >> 1;
+        const int e0 = row / (2 * J1), rr = row - e0 * 2 * J1;
+        const int col = pmod(r2 + c, h2);
+        const bool isll = e0 == 0 && e2 == 0 && rr < J1;
+        const float v = isll ? beta * gld(ap + r0g * t.st_in0[0] + s_rowl[rr] + col)
+                             : alpha * gld(cp + (e0 * h0 + r0g) * t.st_in1[0] + s_rowc[rr] + e2 * h2 + col);
+        s_in[q] = v;
+      }
+      __syncthreads();
+    }
+    // in-plane axis 2: every staged row (e, e0, e1, j1) -> U2 full-res values
+    synthesis_pass<L, P2, true, false, NT>(
+        2 * NR, U2 / 2 / P2, f,
+        [&](int l, int j0, float* lo, float* hi) {
+          const float* ptr = s_in + (2 * l) * J2P + OFF + j0;
+#pragma unroll
+          for (int j = 0; j < P2 + H - 1; ++j) { lo[j] = ptr[j]; hi[j] = ptr[J2P + j]; }
+        },
+        [&](int l, int pp, float e0, float e1) {
+          s_a[l * U2 + pp] = e0;
+          s_a[l * U2 + pp + 1] = e1;
+        });
+    __syncthreads();
+    // in-plane axis 1: lines (e, e0, column) -> U1 full-res rows of plane (e, e0)
+    synthesis_pass<L, P1, true, true, NT>(
+        4 * U2, U1 / 2 / P1, f,
+        [&](int l, int j0, float* lo, float* hi) {
+          const int ee = l / U2, c = l - ee * U2;  // ee = e * 2 + e0
+          const float* base = s_a + ee * 2 * J1 * U2 + c;
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) {
+            lo[j] = base[(j0 + j) * U2];
+            hi[j] = base[(J1 + j0 + j) * U2];
+          }
+        },
+        [&](int l, int pp, float v0, float v1) {
+          const int ee = l / U2, c = l - ee * U2;
+          s_pl[ee * PLN + pp * U2 + c] = v0;
+          s_pl[ee * PLN + (pp + 1) * U2 + c] = v1;
+        });
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+#pragma unroll
+      for (int u = 0; u < QT; ++u) {
+        const int pos = threadIdx.x + u * NT;
+        const float lo = s_pl[(2 * e) * PLN + pos], hi = s_pl[(2 * e + 1) * PLN + pos];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {  // same per-term order as synthesis_pass
+          ac0[j][u] = fmaf(f.h[2 * j], lo, ac0[j][u]);
+          ac1[j][u] = fmaf(f.h[2 * j + 1], lo, ac1[j][u]);
+          ac0[j][u] = fmaf(f.g[2 * j], hi, ac0[j][u]);
+          ac1[j][u] = fmaf(f.g[2 * j + 1], hi, ac1[j][u]);
+        }
+      }
+      const int rel = 2 * p + e - (H - 1);  // pair completed by this slice, relative to q0
+      if (rel >= 0 && rel < R / 2 && 2 * (q0 + rel) < b0) {
+        const int g0 = 2 * (q0 + rel);
+#pragma unroll
+        for (int u = 0; u < QT; ++u) {
+          const int pos = threadIdx.x + u * NT;
+          const int p1 = pos / U2, c = pos - p1 * U2;
+          const int g1 = tl.c1 * U1 + p1, g2 = tl.c2 * U2 + c;
+          if (g1 < b1 && g2 < b2) {
+            const int o = g0 * t.st_out0[0] + g1 * t.st_out0[1] + g2;
+            gst(out + o, ac0[0][u]);
+            gst(out + o + t.st_out0[0], ac1[0][u]);
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < H - 1; ++j)
+#pragma unroll
+        for (int u = 0; u < QT; ++u) {
+          ac0[j][u] = ac0[j + 1][u];
+          ac1[j][u] = ac1[j + 1][u];
+        }
+#pragma unroll
+      for (int u = 0; u < QT; ++u) ac0[H - 1][u] = ac1[H - 1][u] = 0.f;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // FB_DOWN: one full analysis level on a (T0,T1,T2) tile of every band.
 // Bands go to out0 (packed coefficient array, strides st_out0, detail bands x alpha) except
 // the all-low band, which goes to out1 (next level's approximation, strides st_out1, x beta).
@@ -578,7 +919,7 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
   constexpr int P2 = 4, P1 = 4, P0 = 2;
   constexpr int T2x = 2 * T2;  // [lo | hi] along the contiguous dim
   __shared__ __attribute__((aligned(16))) float s_in[G::NROW * G::I2P];
-  __shared__ float s_b[D >= 3 ? 2 * T0 * G::I1 * T2x : 1];
+  __shared__ float s_b[D >= 3 ? G::I0 * 2 * T1 * T2x : 1];
   __shared__ int s_row[G::NROW];
   __shared__ int s_col[G::NV];
 
@@ -635,31 +976,33 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
           emit(0, 1, e2, 0, g1, g2, hi);
         });
   } else {
-    constexpr int T0x = 2 * T0;
-    analysis_pass<L, P0, true, true, NT>(
-        G::I1 * T2x, T0 / P0, f,
+    // axis 1 then axis 0 (the order of the streamed kernel, so both give identical bits)
+    constexpr int T1x = 2 * T1;
+    analysis_pass<L, P1, true, true, NT>(
+        G::I0 * T2x, T1 / P1, f,
         [&](int l, int j0, float* w) {
+          const int c = l % T2x, i0 = l / T2x;
 #pragma unroll
-          for (int j = 0; j < 2 * P0 + L - 2; ++j) w[j] = s_a[(j0 + j) * G::I1 * T2x + l];
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_a[(i0 * G::I1 + j0 + j) * T2x + c];
         },
         [&](int l, int k, float lo, float hi) {
-          s_b[k * G::I1 * T2x + l] = lo;
-          s_b[(T0 + k) * G::I1 * T2x + l] = hi;
+          const int c = l % T2x, i0 = l / T2x;
+          s_b[(i0 * T1x + k) * T2x + c] = lo;
+          s_b[(i0 * T1x + T1 + k) * T2x + c] = hi;
         });
     __syncthreads();
-    analysis_pass<L, P1, true, true, NT>(
-        T0x * T2x, T1 / P1, f,
+    analysis_pass<L, P0, true, true, NT>(
+        T1x * T2x, T0 / P0, f,
         [&](int l, int j0, float* w) {
-          const int c = l % T2x, k0 = l / T2x;
 #pragma unroll
-          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_b[(k0 * G::I1 + j0 + j) * T2x + c];
+          for (int j = 0; j < 2 * P0 + L - 2; ++j) w[j] = s_b[(j0 + j) * T1x * T2x + l];
         },
         [&](int l, int k, float lo, float hi) {
-          const int c = l % T2x, k0x = l / T2x;
-          const int e2 = c >= T2, e0 = k0x >= T0;
-          const int g2 = T2 * tl.c2 + c - e2 * T2, g0 = T0 * tl.c0 + k0x - e0 * T0, g1 = T1 * tl.c1 + k;
-          emit(e0, 0, e2, g0, g1, g2, lo);
-          emit(e0, 1, e2, g0, g1, g2, hi);
+          const int c = l % T2x, k1x = l / T2x;
+          const int e2 = c >= T2, e1 = k1x >= T1;
+          const int g2 = T2 * tl.c2 + c - e2 * T2, g1 = T1 * tl.c1 + k1x - e1 * T1, g0 = T0 * tl.c0 + k;
+          emit(0, e1, e2, g0, g1, g2, lo);
+          emit(1, e1, e2, g0, g1, g2, hi);
         });
   }
 }
@@ -679,7 +1022,7 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
   // LDS rows: index ((e0*J0 + j0)*2*J1 + e1*J1 + j1) * 2 + e2, each J2P long
   __shared__ __attribute__((aligned(16))) float s_in[NRB * 2 * G::J2P];
   __shared__ float s_a[NRB * U2];
-  __shared__ float s_b[D >= 3 ? U0 * 2 * G::J1 * U2 : 1];
+  __shared__ float s_b[D >= 3 ? 2 * G::J0 * U1 * U2 : 1];
   __shared__ int s_rowc[NRB];  // offset into in1 of staged row r (band rows of e0,e1)
   __shared__ int s_rowl[NRB];  // offset into in0 when e0 = e1 = 0, else -1
   __shared__ int s_col[2 * G::NV];
@@ -788,39 +1131,41 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
           }
         });
   } else {
-    // s_a rows: (e0, j0, e1, j1); dim 0 first -> s_b rows (p0, e1, j1)
+    // s_a rows: (e0, j0, e1, j1); axis 1 first -> s_b rows (e0, j0, p1), then axis 0 (the
+    // order of the streamed kernel, so both give identical bits)
     constexpr int R1 = 2 * G::J1;  // (e1, j1)
+    synthesis_pass<L, P1, true, true, NT>(
+        2 * G::J0 * U2, U1 / 2 / P1, f,
+        [&](int l, int j0, float* lo, float* hi) {
+          const int c = l % U2, r = l / U2;  // r = e0 * J0 + j0
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) {
+            lo[j] = s_a[(r * R1 + j0 + j) * U2 + c];
+            hi[j] = s_a[(r * R1 + G::J1 + j0 + j) * U2 + c];
+          }
+        },
+        [&](int l, int p, float e0, float e1) {
+          const int c = l % U2, r = l / U2;
+          s_b[(r * U1 + p) * U2 + c] = e0;
+          s_b[(r * U1 + p + 1) * U2 + c] = e1;
+        });
+    __syncthreads();
     synthesis_pass<L, P0, true, true, NT>(
-        R1 * U2, U0 / 2 / P0, f,
+        U1 * U2, U0 / 2 / P0, f,
         [&](int l, int j0, float* lo, float* hi) {
 #pragma unroll
           for (int j = 0; j < P0 + H - 1; ++j) {
-            lo[j] = s_a[(j0 + j) * R1 * U2 + l];
-            hi[j] = s_a[(G::J0 + j0 + j) * R1 * U2 + l];
+            lo[j] = s_b[(j0 + j) * U1 * U2 + l];
+            hi[j] = s_b[(G::J0 + j0 + j) * U1 * U2 + l];
           }
         },
         [&](int l, int p, float e0, float e1) {
-          s_b[p * R1 * U2 + l] = e0;
-          s_b[(p + 1) * R1 * U2 + l] = e1;
-        });
-    __syncthreads();
-    synthesis_pass<L, P1, true, true, NT>(
-        U0 * U2, U1 / 2 / P1, f,
-        [&](int l, int j0, float* lo, float* hi) {
-          const int c = l % U2, p0 = l / U2;
-#pragma unroll
-          for (int j = 0; j < P1 + H - 1; ++j) {
-            lo[j] = s_b[(p0 * R1 + j0 + j) * U2 + c];
-            hi[j] = s_b[(p0 * R1 + G::J1 + j0 + j) * U2 + c];
-          }
-        },
-        [&](int l, int p, float e0, float e1) {
-          const int c = l % U2, p0 = l / U2;
-          const int g0 = tl.c0 * U0 + p0, g1 = tl.c1 * U1 + p, g2 = tl.c2 * U2 + c;
+          const int c = l % U2, p1 = l / U2;
+          const int g0 = tl.c0 * U0 + p, g1 = tl.c1 * U1 + p1, g2 = tl.c2 * U2 + c;
           if (g0 < b0 && g1 < b1 && g2 < b2) {
             const int o = g0 * t.st_out0[0] + g1 * t.st_out0[1] + g2;
             gst(out + o, e0);
-            gst(out + o + t.st_out0[1], e1);
+            gst(out + o + t.st_out0[0], e1);
           }
         });
   }
@@ -939,7 +1284,8 @@ __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Fil
   int tmpA = 0;
   for (int j = 0; j <= K; ++j) tmpA += B >> (D * j);
   const int tmpB = tmpA + (B >> 1);
-  for (int e = threadIdx.x; e < B; e += blockDim.x) sm[e] = gld(in + e);
+  gather_to_lds<kCoarseThreads, kCoarseMax / kCoarseThreads>(
+      B, [&](int e) { return gld(in + e); }, [&](int e, float v) { sm[e] = v; });
   __syncthreads();
   int off = 0;
   for (int j = 0; j < K; ++j) {
@@ -1101,8 +1447,10 @@ __global__ void __launch_bounds__(kFbCoarseThreads) k_fb_coarse(TailArgs args, F
       sm[CUR + o] = sm[TMP + o];
     }
   };
+  constexpr int U = kFbCoarseMax / kFbCoarseThreads;
   if (!SYN) {
-    for (int e = threadIdx.x; e < B; e += blockDim.x) sm[CUR + e] = gld(in + e);
+    gather_to_lds<kFbCoarseThreads, U>(
+        B, [&](int e) { return gld(in + e); }, [&](int e, float v) { sm[CUR + e] = v; });
     __syncthreads();
     for (int j = 0; j < nl; ++j) {
       const int b0 = D >= 3 ? n0 >> j : 1, b1 = D >= 2 ? n1 >> j : 1, b2 = n2 >> j;
@@ -1132,12 +1480,18 @@ __global__ void __launch_bounds__(kFbCoarseThreads) k_fb_coarse(TailArgs args, F
       gst(out + (D >= 3 ? c0 * out0 : 0) + (D >= 2 ? c1 * out1 : 0) + c2, w * sm[CUR + e]);
     }
   } else {
-    for (int e = threadIdx.x; e < B; e += blockDim.x) {
-      int c0, c1, c2;
-      split3(e, n1, n2, l1, l2, c0, c1, c2);
-      const float w = fbc_weight(tp->coef, nl, n0, n1, n2, c0, c1, c2, D);
-      sm[CUR + e] = w * gld(in + (D >= 3 ? c0 * in0 : 0) + (D >= 2 ? c1 * in1 : 0) + c2);
-    }
+    gather_to_lds<kFbCoarseThreads, U>(
+        B,
+        [&](int e) {
+          int c0, c1, c2;
+          split3(e, n1, n2, l1, l2, c0, c1, c2);
+          return gld(in + (D >= 3 ? c0 * in0 : 0) + (D >= 2 ? c1 * in1 : 0) + c2);
+        },
+        [&](int e, float v) {
+          int c0, c1, c2;
+          split3(e, n1, n2, l1, l2, c0, c1, c2);
+          sm[CUR + e] = fbc_weight(tp->coef, nl, n0, n1, n2, c0, c1, c2, D) * v;
+        });
     __syncthreads();
     for (int j = nl - 1; j >= 0; --j) {
       const int b0 = D >= 3 ? n0 >> j : 1, b1 = D >= 2 ? n1 >> j : 1, b2 = n2 >> j;
@@ -1267,6 +1621,8 @@ struct Shape3 {
 constexpr Shape3 shape_of(int K, int D, int V, int L) {
   // V: 0 wide, 1 narrow, 2 medium
   if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 32, 64} : Shape3{1, 32, 128});
+  if (K == K_FB_DOWN_S) return V == 0 ? Shape3{16, 8, 32} : (V == 1 ? Shape3{8, 8, 16} : Shape3{8, 8, 32});
+  if (K == K_FB_UP_S) return V == 0 ? Shape3{16, 16, 32} : (V == 1 ? Shape3{8, 8, 32} : Shape3{8, 16, 32});
   if (D == 1) {
     const bool an = (K == K_LP_DOWN || K == K_FB_DOWN);
     return an ? (V == 0 ? Shape3{1, 1, 256} : (V == 1 ? Shape3{1, 1, 64} : Shape3{1, 1, 128}))
@@ -1304,6 +1660,10 @@ hipError_t launch_kind(const TaskArgs& a, int grid, const Filter& f, hipStream_t
     hipLaunchKernelGGL((k_lp_up<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_DOWN)
     hipLaunchKernelGGL((k_fb_down<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_FB_DOWN_S)
+    hipLaunchKernelGGL((k_fb_down_s<L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_FB_UP_S)
+    hipLaunchKernelGGL((k_fb_up_s<L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_LP_UP2)
     hipLaunchKernelGGL((k_lp_up2<L, shape_of(K, 2, V, L).b, shape_of(K, 2, V, L).c, kThreads, VEC>), dim3(grid),
                        dim3(kThreads), 0, s, a, f);
@@ -1408,6 +1768,12 @@ hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArg
     case K_LP_UP2:
       if (ndim != 2) return hipErrorInvalidValue;
       return launch_kd<K_LP_UP2, 2>(taps, variant, vec, args, grid, f, stream);
+    case K_FB_DOWN_S:
+      if (ndim != 3) return hipErrorInvalidValue;
+      return launch_kd<K_FB_DOWN_S, 3>(taps, variant, vec, args, grid, f, stream);
+    case K_FB_UP_S:
+      if (ndim != 3) return hipErrorInvalidValue;
+      return launch_kd<K_FB_UP_S, 3>(taps, variant, vec, args, grid, f, stream);
   }
   return hipErrorInvalidValue;
 }
