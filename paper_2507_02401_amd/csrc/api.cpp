@@ -204,10 +204,11 @@ bool reverse_orders() {
   const char* e = getenv("ESWAVE_NO_REVERSE");
   return !(e && *e == '1');
 }
-// Kernel family of 3-D full-bank levels: ESWAVE_STREAM3D=0 plain 3-D tiles only, 2 streamed
-// tiles at every level, otherwise (default) streamed where the level fills the chip.
-int stream3d() {
-  const char* e = getenv("ESWAVE_STREAM3D");
+// Kernel family of the levels that have a streamed variant (3-D full-bank levels, 2-D low-pass
+// analysis): ESWAVE_STREAMED=0 plain tiles only, 2 streamed tiles at every such level,
+// otherwise (default) streamed where the level fills the chip.
+int streamed_mode() {
+  const char* e = getenv("ESWAVE_STREAMED");
   if (e && (*e == '0' || *e == '2')) return *e - '0';
   return 1;
 }
@@ -295,7 +296,8 @@ bool vec_ok(const Task& t, int kind, const Geo& g) {
   if (!m4(row)) return false;
   if (!a16(t.in0) || !m4(t.bs_in0) || !m4(t.st_in0[0]) || !m4(t.st_in0[1])) return false;
   if ((kind == K_FB_UP || kind == K_FB_UP_S) && (!a16(t.in1) || !m4(t.bs_in1) || !m4(t.st_in1[0]) || !m4(t.st_in1[1]))) return false;
-  (void)g;
+  // 2-D LP_UP reads `same` and writes `out` as 16-byte vectors on the vector path
+  if (kind == K_LP_UP && g.D == 2 && (!a16(t.in1) || !m4(t.bs_in1) || !a16(t.out0) || !m4(t.bs_out0))) return false;
   return true;
 }
 
@@ -304,18 +306,26 @@ void strides_of(const int dims[3], int32_t st[2]) {
   st[1] = dims[2];
 }
 
-// 3-D full-bank levels have two kernel families: plain 3-D tiles, and tiles streamed along
-// axis 0 (no axis-0 halo re-reads, but one work-group walks R slices in sequence).  Streaming
-// wins when the level has enough tiles to fill the chip.
-bool is_fb3(const Launch& l) {
-  return !l.is_tail && l.D == 3 && (l.kind == K_FB_DOWN || l.kind == K_FB_UP || l.kind == K_FB_DOWN_S || l.kind == K_FB_UP_S);
+// 3-D full-bank levels and 2-D low-pass analysis levels have two kernel families: plain tiles,
+// and tiles streamed along the slowest axis (no halo re-reads along it, but one work-group walks
+// its run in sequence).  Streaming wins when the level has enough tiles to fill the chip.
+bool has_family(int kind, int D) {
+  return (D == 3 && (kind == K_FB_DOWN || kind == K_FB_UP || kind == K_FB_DOWN_S || kind == K_FB_UP_S)) ||
+         (D == 2 && (kind == K_LP_DOWN || kind == K_LP_DOWN_S));
 }
-int streamed_kind(int kind) { return kind_is_analysis(kind) ? K_FB_DOWN_S : K_FB_UP_S; }
-int tiled_kind(int kind) { return kind_is_analysis(kind) ? K_FB_DOWN : K_FB_UP; }
+bool is_family(const Launch& l) { return !l.is_tail && has_family(l.kind, l.D); }
+int streamed_kind(int kind) {
+  if (kind == K_LP_DOWN || kind == K_LP_DOWN_S) return K_LP_DOWN_S;
+  return kind_is_analysis(kind) ? K_FB_DOWN_S : K_FB_UP_S;
+}
+int tiled_kind(int kind) {
+  if (kind == K_LP_DOWN || kind == K_LP_DOWN_S) return K_LP_DOWN;
+  return kind_is_analysis(kind) ? K_FB_DOWN : K_FB_UP;
+}
 
 Launch level_launch(int kind, const Geo& g, int level, int64_t batch) {
-  const int mode = stream3d();
-  if (g.D == 3 && (kind == K_FB_DOWN || kind == K_FB_UP) && mode != 0) {
+  const int mode = streamed_mode();
+  if (has_family(kind, g.D) && mode != 0) {
     const int sk = streamed_kind(kind);
     Task t{};
     set_tiles(t, sk, g, level, pick_variant(sk, g, level, batch), batch);
@@ -340,11 +350,11 @@ void apply_variant(Launch& l, const Geo& g, int v, int64_t batch) {
   finish_level(l, g);
 }
 
-// Tunable choices of a level launch: its tile variants, and for 3-D full-bank levels the tile
-// variants of both kernel families (choice = variant + kNumVariants for the streamed family).
-int num_choices(const Launch& l) { return is_fb3(l) ? 2 * kNumVariants : kNumVariants; }
+// Tunable choices of a level launch: its tile variants, and for levels with two kernel families
+// the tile variants of both (choice = variant + kNumVariants for the streamed family).
+int num_choices(const Launch& l) { return is_family(l) ? 2 * kNumVariants : kNumVariants; }
 void apply_choice(Launch& l, const Geo& g, int c, int64_t batch) {
-  if (is_fb3(l)) l.kind = c >= kNumVariants ? streamed_kind(l.kind) : tiled_kind(l.kind);
+  if (is_family(l)) l.kind = c >= kNumVariants ? streamed_kind(l.kind) : tiled_kind(l.kind);
   apply_variant(l, g, c % kNumVariants, batch);
 }
 
@@ -1025,6 +1035,9 @@ es_status plan_fill_tables(es_plan* p, const float* const* in, float* const* out
         p->h_tails[gr.table_off + q] = t;
         wg += 1;
       } else {
+        // the launch's vector path was chosen when the plan was built; every instance must allow it
+        if (l.vec < gr.proto.vec)
+          return fail(ES_EINVAL, "instance %d: pointers not aligned as the plan's vector path requires", gr.inst[q]);
         Task t = l.task;
         t.tile_begin = (int32_t)wg;
         t.batch = 1;
@@ -1319,7 +1332,7 @@ es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t b
   if (st != ES_OK) return st;
   if (index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
   const Launch& l = sc.launches[index];
-  static const char* kinds[7] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2", "fb_down_s", "fb_up_s"};
+  static const char* kinds[8] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2", "fb_down_s", "fb_up_s", "lp_down_s"};
   static const char* tails[4] = {"tail_lp_off", "tail_fb_analysis", "tail_fb_synthesis", "lp_coarse"};
   char buf[128];
   int lev = 0;

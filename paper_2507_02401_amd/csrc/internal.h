@@ -93,9 +93,12 @@ enum KernelKind {
   K_FB_UP = 3,
   K_LP_UP2 = 4,
   K_FB_DOWN_S = 5,  // 3-D full analysis level, streamed along axis 0 (same Task fields as FB_DOWN)
-  K_FB_UP_S = 6     // 3-D full synthesis level, streamed along axis 0 (same Task fields as FB_UP)
+  K_FB_UP_S = 6,    // 3-D full synthesis level, streamed along axis 0 (same Task fields as FB_UP)
+  K_LP_DOWN_S = 7   // 2-D low-pass analysis level, streamed along axis 1 (same Task fields as LP_DOWN)
 };
-inline bool kind_is_analysis(int k) { return k == K_LP_DOWN || k == K_FB_DOWN || k == K_FB_DOWN_S; }
+inline bool kind_is_analysis(int k) {
+  return k == K_LP_DOWN || k == K_FB_DOWN || k == K_FB_DOWN_S || k == K_LP_DOWN_S;
+}
 
 // Tile shape selection: each (kind, ndim, taps) has wide (0), narrow (1) and medium (2) tiles.
 constexpr int kNumVariants = 3;

@@ -43,6 +43,11 @@ DEVI float4 gld4(const float* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 DEVI void gst(float* p, float v) { *(GAS float*)p = v; }
+DEVI void gst4(float* p, float4 v) {
+  f4v w;
+  w.x = v.x; w.y = v.y; w.z = v.z; w.w = v.w;
+  *(GAS f4v*)p = w;
+}
 
 // Load n (at most U * NT) elements into LDS with every load of a thread issued before the
 // first LDS store, so that one work-group keeps U loads per thread in flight.  src(e) gives
@@ -372,6 +377,115 @@ __global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
 }
 
 // ---------------------------------------------------------------------------------------
+// LP_DOWN_S (2-D): a_out = A a_in, streamed along axis 1.  A work-group owns a strip of T2 output
+// columns and a run of R output rows.  It visits the input rows of the run in chunks of 2 RB
+// (with the next chunk's 16-byte loads in flight while the current one is filtered), filters
+// each row along axis 2 once into a ring of the last 2 RB + L - 2 filtered rows, and forms RB
+// output rows per chunk from the ring along axis 1.  Input rows are read once per run (plus
+// L - 2 at its start) instead of once per tile row; the arithmetic per output is that of
+// k_lp_down, so both give identical results.
+template <int L, int R, int T2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_lp_down_s(TaskArgs args, Filter f) {
+  constexpr int RB = 4, CR = 2 * RB;     // output rows / input rows per chunk
+  constexpr int W = CR + L - 2;          // ring rows
+  constexpr int NC = (2 * R + L - 2 + CR - 1) / CR;
+  constexpr int I2 = 2 * T2 + L - 2, I2P = (I2 + 3) & ~3, NV = I2P / 4;
+  constexpr int P = 4, NCH = T2 / P;     // row pass: P outputs per task
+  constexpr int CPT = NT / T2 > 0 ? NT / T2 : 1, RPT = RB / CPT;  // column pass: threads per column, rows per thread
+  static_assert(T2 % P == 0 && RB % CPT == 0, "tile shape");
+  __shared__ __attribute__((aligned(16))) float s_in[CR * I2P];
+  __shared__ float s_ring[W * T2];
+  __shared__ int s_row[NC * CR];
+  __shared__ int s_col[NV];
+
+  const int wg = logical_wg(args.total_wg, args.reverse);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ src = t.in0 + tl.inst * t.bs_in0;
+  float* __restrict__ dst = t.out0 + tl.inst * t.bs_out0;
+  const int b1 = t.b[1], b2 = t.b[2];
+  const int h1 = b1 >> 1, h2 = b2 >> 1;
+  const int k0 = R * tl.c1, o2 = 2 * T2 * tl.c2;
+
+  for (int i = threadIdx.x; i < NC * CR; i += NT) s_row[i] = pmod(2 * k0 + i, b1) * t.st_in0[1];
+  for (int i = threadIdx.x; i < NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
+  __syncthreads();
+
+  constexpr int NLD = CR * NV, ITL = (NLD + NT - 1) / NT;
+  float4 pf[VEC ? ITL : 1];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
+      pf[it] = gld4(src + s_row[c * CR + q / NV] + s_col[q % NV]);
+    }
+  };
+  if constexpr (VEC) load_chunk(0);
+
+  for (int c = 0; c < NC; ++c) {
+    if constexpr (VEC) {
+      float4* d4 = reinterpret_cast<float4*>(s_in);  // row length I2P = 4 NV: LDS slot = load index
+#pragma unroll
+      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
+      __syncthreads();
+      load_chunk(min(c + 1, NC - 1));
+    } else {
+      stage_rows<NT, CR, NV, false>(src, s_row + c * CR, s_col, s_in, I2P, b2);
+      __syncthreads();
+    }
+    // axis 2: the chunk's rows into their ring slots
+    const int sb = (c * CR) % W;
+    for (int task = threadIdx.x; task < CR * NCH; task += NT) {
+      const int ch = task % NCH, r = task / NCH;
+      constexpr int WN = 2 * P + L - 2, W4 = (WN + 3) / 4;
+      const float4* p4 = reinterpret_cast<const float4*>(s_in + r * I2P + 2 * P * ch);
+      float win[4 * W4];
+#pragma unroll
+      for (int v = 0; v < W4; ++v) {
+        const float4 x = p4[v];
+        win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
+      }
+      const int slot = sb + r >= W ? sb + r - W : sb + r;
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        float a = 0.f;
+#pragma unroll
+        for (int tt = 0; tt < L; ++tt) a = fmaf(f.h[tt], win[2 * q + tt], a);
+        s_ring[slot * T2 + P * ch + q] = a;
+      }
+    }
+    __syncthreads();
+    // axis 1: outputs kb .. kb+RB-1 of the run from ring rows 2 kb .. 2 kb + W - 1
+    const int kb = RB * c - (L / 2 - 1);
+    if (kb + RB > 0) {
+      const int rb = pmod(2 * kb, W);
+      for (int task = threadIdx.x; task < T2 * CPT; task += NT) {
+        const int col = task % T2, part = task / T2;
+        constexpr int WC = 2 * RPT + L - 2;
+        float win[WC];
+#pragma unroll
+        for (int j = 0; j < WC; ++j) {
+          int sl = rb + 2 * RPT * part + j;
+          sl = sl >= W ? sl - W : sl;
+          sl = sl >= W ? sl - W : sl;
+          win[j] = s_ring[sl * T2 + col];
+        }
+        const int g2 = T2 * tl.c2 + col;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          float a = 0.f;
+#pragma unroll
+          for (int tt = 0; tt < L; ++tt) a = fmaf(f.h[tt], win[2 * r + tt], a);
+          const int k = kb + RPT * part + r;
+          if (k >= 0 && k < R && k0 + k < h1 && g2 < h2) gst(dst + (k0 + k) * h2 + g2, a);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // LP_UP: out = alpha*same + beta*(A^T z) on a (U0,U1,U2) full-resolution tile.
 
 template <int D, int L, int U0, int U1, int U2, int NT, bool VEC>
@@ -396,6 +510,27 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
   const int h0 = b0 >> 1, h1 = b1 >> 1, h2 = b2 >> 1;  // z dims
   const int r0 = tl.c0 * (U0 / 2) - (H - 1), r1 = tl.c1 * (U1 / 2) - (H - 1);
   const int r2 = tl.c2 * (U2 / 2) - (H - 1) - G::OFF;
+
+  // 2-D vector path: the last pass gives each lane 4 adjacent columns and PQ row pairs; the
+  // lane's `same` values are loaded first, so that their latency overlaps the staging and
+  // filtering of z (same has no halo: each work-group reads and writes only its own tile)
+  constexpr int C4 = U2 / 4, PQ = 2;
+  constexpr bool FAST2 = D == 2 && VEC && (U1 / 2) % PQ == 0;
+  constexpr int NT2 = C4 * (U1 / 2 / PQ), IT2 = (NT2 + NT - 1) / NT;
+  float4 xs[FAST2 ? IT2 : 1][FAST2 ? 2 * PQ : 1];
+  if constexpr (FAST2) {
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int task = threadIdx.x + it * NT;
+      const int c4 = task % C4, ch = task / C4;
+      const int g2 = tl.c2 * U2 + 4 * c4;
+#pragma unroll
+      for (int r = 0; r < 2 * PQ; ++r) {
+        const int g1 = tl.c1 * U1 + 2 * PQ * ch + r;
+        xs[it][r] = (task < NT2 && g1 < b1 && g2 < b2) ? gld4(same + g1 * b2 + g2) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+  }
 
   for (int i = threadIdx.x; i < G::NROW; i += NT) {
     const int i1 = i % G::J1, i0 = i / G::J1;
@@ -425,6 +560,42 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
     for (int p = threadIdx.x; p < U2; p += NT) {
       const int g2 = tl.c2 * U2 + p;
       if (g2 < b2) gst(out + g2, fmaf(alpha, gld(same + g2), beta * s_a[p]));
+    }
+  } else if constexpr (FAST2) {
+    // axis 1 with 4 columns per lane: float4 LDS reads, float4 global stores; per output the
+    // arithmetic of synthesis_pass (oldest window sample first)
+#pragma unroll
+    for (int it = 0; it < IT2; ++it) {
+      const int task = threadIdx.x + it * NT;
+      if (task < NT2) {
+        const int c4 = task % C4, ch = task / C4;
+        const int g2 = tl.c2 * U2 + 4 * c4;
+        float4 lo[PQ + H - 1];
+#pragma unroll
+        for (int j = 0; j < PQ + H - 1; ++j) lo[j] = *reinterpret_cast<const float4*>(s_a + (PQ * ch + j) * U2 + 4 * c4);
+#pragma unroll
+        for (int q = 0; q < PQ; ++q) {
+          float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0;
+#pragma unroll
+          for (int j = H - 1; j >= 0; --j) {
+            const float4 v = lo[q + H - 1 - j];
+            e0.x = fmaf(f.h[2 * j], v.x, e0.x); e1.x = fmaf(f.h[2 * j + 1], v.x, e1.x);
+            e0.y = fmaf(f.h[2 * j], v.y, e0.y); e1.y = fmaf(f.h[2 * j + 1], v.y, e1.y);
+            e0.z = fmaf(f.h[2 * j], v.z, e0.z); e1.z = fmaf(f.h[2 * j + 1], v.z, e1.z);
+            e0.w = fmaf(f.h[2 * j], v.w, e0.w); e1.w = fmaf(f.h[2 * j + 1], v.w, e1.w);
+          }
+          const int g1 = tl.c1 * U1 + 2 * (PQ * ch + q);
+          if (g1 < b1 && g2 < b2) {
+            const float4 s0 = xs[it][2 * q], s1 = xs[it][2 * q + 1];
+            const float4 y0 = make_float4(fmaf(alpha, s0.x, beta * e0.x), fmaf(alpha, s0.y, beta * e0.y),
+                                          fmaf(alpha, s0.z, beta * e0.z), fmaf(alpha, s0.w, beta * e0.w));
+            const float4 y1 = make_float4(fmaf(alpha, s1.x, beta * e1.x), fmaf(alpha, s1.y, beta * e1.y),
+                                          fmaf(alpha, s1.z, beta * e1.z), fmaf(alpha, s1.w, beta * e1.w));
+            gst4(out + g1 * b2 + g2, y0);
+            gst4(out + (g1 + 1) * b2 + g2, y1);
+          }
+        }
+      }
     }
   } else if constexpr (D == 2) {
     synthesis_pass<L, P1, false, true, NT>(
@@ -1202,34 +1373,37 @@ DEVI void split3(int e, int o1, int o2, int l1, int l2, int& c0, int& c1, int& c
 
 DEVI int ilog2_or_neg(int v) { return (v & (v - 1)) == 0 ? 31 - __builtin_clz(v) : -1; }
 
-template <int L>
-DEVI void coarse_analysis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f) {
+template <int L, bool SHORT>
+DEVI void coarse_analysis_w(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f) {
   // sm[src] holds an (n0, n1, n2) block; writes the low half along ax, (.., n_ax/2, ..), to sm[dst]
   const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
   const int o0 = ax == 0 ? n0 >> 1 : n0, o1 = ax == 1 ? n1 >> 1 : n1, o2 = ax == 2 ? n2 >> 1 : n2;
   const int l1 = ilog2_or_neg(o1), l2 = ilog2_or_neg(o2);
   const int step = ax == 0 ? n1 * n2 : (ax == 1 ? n2 : 1);
   const int total = o0 * o1 * o2;
-  const bool longax = n >= L;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     int c0, c1, c2;
     split3(e, o1, o2, l1, l2, c0, c1, c2);
     const int k = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
     const int base = src + (ax == 0 ? 0 : c0 * n1 * n2) + (ax == 1 ? 0 : c1 * n2) + (ax == 2 ? 0 : c2);
     float acc = 0.f;
+    if (!SHORT) {  // n >= L: an index wraps at most once
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      int i = 2 * k + t;
-      i = longax ? (i >= n ? i - n : i) : i % n;
-      acc = fmaf(f.h[t], sm[base + i * step], acc);
+      for (int t = 0; t < L; ++t) {
+        const int i = 2 * k + t;
+        acc = fmaf(f.h[t], sm[base + (i >= n ? i - n : i) * step], acc);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < L; ++t) acc = fmaf(f.h[t], sm[base + ((2 * k + t) % n) * step], acc);
     }
     sm[dst + e] = acc;
   }
 }
 
-template <int L>
-DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f, bool combine,
-                           float alpha) {
+template <int L, bool SHORT>
+DEVI void coarse_synthesis_w(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f, bool combine,
+                             float alpha) {
   // sm[src] holds the low half along ax of an (n0, n1, n2) block; writes the full block to
   // sm[dst] (dst = alpha*dst + value when combine)
   const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2), half = n >> 1;
@@ -1237,7 +1411,6 @@ DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, 
   const int step = ax == 0 ? h1 * h2 : (ax == 1 ? h2 : 1);
   const int total = n0 * n1 * n2;
   const int l1 = ilog2_or_neg(n1), l2 = ilog2_or_neg(n2);
-  const bool longax = half >= L / 2;
   (void)h0;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     int c0, c1, c2;
@@ -1246,14 +1419,34 @@ DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, 
     const int base = src + (ax == 0 ? 0 : c0 * h1 * h2) + (ax == 1 ? 0 : c1 * h2) + (ax == 2 ? 0 : c2);
     const int par = p & 1, q = p >> 1;
     float acc = 0.f;
+    if (!SHORT) {  // half >= L/2: an index wraps at most once
 #pragma unroll
-    for (int j = 0; j < L / 2; ++j) {
-      int k = q - j;
-      k = longax ? (k < 0 ? k + half : k) : pmod(k, half);
-      acc = fmaf(f.h[2 * j + par], sm[base + k * step], acc);
+      for (int j = 0; j < L / 2; ++j) {
+        const int k = q - j;
+        acc = fmaf(par ? f.h[2 * j + 1] : f.h[2 * j], sm[base + (k < 0 ? k + half : k) * step], acc);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < L / 2; ++j)
+        acc = fmaf(par ? f.h[2 * j + 1] : f.h[2 * j], sm[base + pmod(q - j, half) * step], acc);
     }
     sm[dst + e] = combine ? fmaf(alpha, sm[dst + e], acc) : acc;
   }
+}
+
+// Uniform dispatch on whether the filtered axis is shorter than the filter (periodic folding).
+template <int L>
+DEVI void coarse_analysis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f) {
+  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+  if (n >= L) coarse_analysis_w<L, false>(sm, src, dst, n0, n1, n2, ax, f);
+  else coarse_analysis_w<L, true>(sm, src, dst, n0, n1, n2, ax, f);
+}
+template <int L>
+DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f, bool combine,
+                           float alpha) {
+  const int half = (ax == 0 ? n0 : (ax == 1 ? n1 : n2)) >> 1;
+  if (half >= L / 2) coarse_synthesis_w<L, false>(sm, src, dst, n0, n1, n2, ax, f, combine, alpha);
+  else coarse_synthesis_w<L, true>(sm, src, dst, n0, n1, n2, ax, f, combine, alpha);
 }
 
 constexpr int kCoarseThreads = 1024;
@@ -1348,40 +1541,46 @@ __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Fil
 constexpr int kFbCoarseMax = kFbCoarseMaxBlock;
 constexpr int kFbCoarseThreads = 1024;
 
-template <int L>
-DEVI void fbc_analysis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+template <int L, bool SHORT>
+DEVI void fbc_analysis_w(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
   const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2), half = n >> 1;
   const int o0 = ax == 0 ? half : b0, o1 = ax == 1 ? half : b1, o2 = ax == 2 ? half : b2;
   const int l1 = ilog2_or_neg(o1), l2 = ilog2_or_neg(o2);
   const int step = ax == 0 ? S0 : (ax == 1 ? S1 : 1);
   const int total = o0 * o1 * o2;
-  const bool longax = n >= L;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     int c0, c1, c2;
     split3(e, o1, o2, l1, l2, c0, c1, c2);
     const int k = ax == 0 ? c0 : (ax == 1 ? c1 : c2);
     const int other = (ax == 0 ? 0 : c0 * S0) + (ax == 1 ? 0 : c1 * S1) + (ax == 2 ? 0 : c2);
     float lo = 0.f, hi = 0.f;
+    if (!SHORT) {  // n >= L: an index wraps at most once
 #pragma unroll
-    for (int t = 0; t < L; ++t) {
-      int i = 2 * k + t;
-      i = longax ? (i >= n ? i - n : i) : i % n;
-      const float x = sm[src + other + i * step];
-      lo = fmaf(f.h[t], x, lo);
-      hi = fmaf(f.g[t], x, hi);
+      for (int t = 0; t < L; ++t) {
+        const int i = 2 * k + t;
+        const float x = sm[src + other + (i >= n ? i - n : i) * step];
+        lo = fmaf(f.h[t], x, lo);
+        hi = fmaf(f.g[t], x, hi);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        const float x = sm[src + other + ((2 * k + t) % n) * step];
+        lo = fmaf(f.h[t], x, lo);
+        hi = fmaf(f.g[t], x, hi);
+      }
     }
     sm[dst + other + k * step] = lo;
     sm[dst + other + (half + k) * step] = hi;
   }
 }
 
-template <int L>
-DEVI void fbc_synthesis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+template <int L, bool SHORT>
+DEVI void fbc_synthesis_w(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
   const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2), half = n >> 1;
   const int l1 = ilog2_or_neg(b1), l2 = ilog2_or_neg(b2);
   const int step = ax == 0 ? S0 : (ax == 1 ? S1 : 1);
   const int total = b0 * b1 * b2;
-  const bool longax = half >= L / 2;
   for (int e = threadIdx.x; e < total; e += blockDim.x) {
     int c0, c1, c2;
     split3(e, b1, b2, l1, l2, c0, c1, c2);
@@ -1389,15 +1588,36 @@ DEVI void fbc_synthesis(float* sm, int src, int dst, int S0, int S1, int b0, int
     const int other = (ax == 0 ? 0 : c0 * S0) + (ax == 1 ? 0 : c1 * S1) + (ax == 2 ? 0 : c2);
     const int par = p & 1, q = p >> 1;
     float acc = 0.f;
+    if (!SHORT) {  // half >= L/2: an index wraps at most once
 #pragma unroll
-    for (int j = 0; j < L / 2; ++j) {
-      int k = q - j;
-      k = longax ? (k < 0 ? k + half : k) : pmod(k, half);
-      acc = fmaf(f.h[2 * j + par], sm[src + other + k * step], acc);
-      acc = fmaf(f.g[2 * j + par], sm[src + other + (half + k) * step], acc);
+      for (int j = 0; j < L / 2; ++j) {
+        const int k = q - j < 0 ? q - j + half : q - j;
+        acc = fmaf(par ? f.h[2 * j + 1] : f.h[2 * j], sm[src + other + k * step], acc);
+        acc = fmaf(par ? f.g[2 * j + 1] : f.g[2 * j], sm[src + other + (half + k) * step], acc);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < L / 2; ++j) {
+        const int k = pmod(q - j, half);
+        acc = fmaf(par ? f.h[2 * j + 1] : f.h[2 * j], sm[src + other + k * step], acc);
+        acc = fmaf(par ? f.g[2 * j + 1] : f.g[2 * j], sm[src + other + (half + k) * step], acc);
+      }
     }
     sm[dst + other + p * step] = acc;
   }
+}
+
+template <int L>
+DEVI void fbc_analysis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+  const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2);
+  if (n >= L) fbc_analysis_w<L, false>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
+  else fbc_analysis_w<L, true>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
+}
+template <int L>
+DEVI void fbc_synthesis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+  const int half = (ax == 0 ? b0 : (ax == 1 ? b1 : b2)) >> 1;
+  if (half >= L / 2) fbc_synthesis_w<L, false>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
+  else fbc_synthesis_w<L, true>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
 }
 
 // Weight of the packed-pyramid element at (c0,c1,c2) of a coarse block: detail of coarse
@@ -1621,6 +1841,7 @@ struct Shape3 {
 constexpr Shape3 shape_of(int K, int D, int V, int L) {
   // V: 0 wide, 1 narrow, 2 medium
   if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 32, 64} : Shape3{1, 32, 128});
+  if (K == K_LP_DOWN_S) return V == 0 ? Shape3{1, 64, 256} : (V == 1 ? Shape3{1, 16, 128} : Shape3{1, 32, 256});
   if (K == K_FB_DOWN_S) return V == 0 ? Shape3{16, 8, 32} : (V == 1 ? Shape3{8, 8, 16} : Shape3{8, 8, 32});
   if (K == K_FB_UP_S) return V == 0 ? Shape3{16, 16, 32} : (V == 1 ? Shape3{8, 8, 32} : Shape3{8, 16, 32});
   if (D == 1) {
@@ -1660,6 +1881,9 @@ hipError_t launch_kind(const TaskArgs& a, int grid, const Filter& f, hipStream_t
     hipLaunchKernelGGL((k_lp_up<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_DOWN)
     hipLaunchKernelGGL((k_fb_down<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_LP_DOWN_S)
+    hipLaunchKernelGGL((k_lp_down_s<L, shape_of(K, 2, V, L).b, shape_of(K, 2, V, L).c, kThreads, VEC>), dim3(grid),
+                       dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_DOWN_S)
     hipLaunchKernelGGL((k_fb_down_s<L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_UP_S)
@@ -1768,6 +1992,9 @@ hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArg
     case K_LP_UP2:
       if (ndim != 2) return hipErrorInvalidValue;
       return launch_kd<K_LP_UP2, 2>(taps, variant, vec, args, grid, f, stream);
+    case K_LP_DOWN_S:
+      if (ndim != 2) return hipErrorInvalidValue;
+      return launch_kd<K_LP_DOWN_S, 2>(taps, variant, vec, args, grid, f, stream);
     case K_FB_DOWN_S:
       if (ndim != 3) return hipErrorInvalidValue;
       return launch_kd<K_FB_DOWN_S, 3>(taps, variant, vec, args, grid, f, stream);

@@ -62,26 +62,31 @@ def test_parity(case, op, mode):
 
 
 CASES_3D = [c for c in CASES if len(c[0]) == 3] + [((16, 24, 20), 3, 2, 1.0), ((40, 24, 32), 5, 3, 0.75)]
+# 2-D low-pass analysis levels stream along axis 1: runs longer than the level, ragged strips,
+# rows not a multiple of 4 (scalar staging), filters longer than the coarse levels
+CASES_2D = [c for c in CASES if len(c[0]) == 2] + [((200, 776), 8, 3, 1.5), ((40, 36), 2, 2, 1.0),
+                                                    ((1024, 96), 7, 5, 0.5)]
+FAMILY_CASES = [(c, op) for c in CASES_3D for op in (0, 1)] + [(c, op) for c in CASES_2D for op in (2, 3)]
 FAMILY_KNOBS = {
-    "streamed": dict(ESWAVE_STREAM3D=2),
-    "streamed-wide": dict(ESWAVE_STREAM3D=2, ESWAVE_FORCE_VARIANT=0),
-    "streamed-narrow": dict(ESWAVE_STREAM3D=2, ESWAVE_FORCE_VARIANT=1),
-    "streamed-medium": dict(ESWAVE_STREAM3D=2, ESWAVE_FORCE_VARIANT=2),
-    "streamed-notail": dict(ESWAVE_STREAM3D=2, ESWAVE_TAIL_MAX=0),
-    "tiled": dict(ESWAVE_STREAM3D=0),
+    "streamed": dict(ESWAVE_STREAMED=2),
+    "streamed-wide": dict(ESWAVE_STREAMED=2, ESWAVE_FORCE_VARIANT=0),
+    "streamed-narrow": dict(ESWAVE_STREAMED=2, ESWAVE_FORCE_VARIANT=1),
+    "streamed-medium": dict(ESWAVE_STREAMED=2, ESWAVE_FORCE_VARIANT=2),
+    "streamed-notail": dict(ESWAVE_STREAMED=2, ESWAVE_TAIL_MAX=0),
+    "tiled": dict(ESWAVE_STREAMED=0),
 }
 
 
-@pytest.mark.parametrize("case", CASES_3D, ids=lambda c: f"{c[0]}-db{c[1]}-m{c[2]}")
-@pytest.mark.parametrize("op", [0, 1], ids=OP_NAMES[:2])
+@pytest.mark.parametrize("case_op", FAMILY_CASES, ids=lambda c: f"{OP_NAMES[c[1]]}-{c[0][0]}-db{c[0][1]}-m{c[0][2]}")
 @pytest.mark.parametrize("family", list(FAMILY_KNOBS))
-def test_parity_3d_families(case, op, family):
-    """3-D full-bank levels in both kernel families (plain 3-D tiles, tiles streamed along axis 0),
-    every tile variant, with and without the coarse-level kernel, batch of two."""
-    shape, order, levels, s = case
+def test_parity_families(case_op, family):
+    """Levels with two kernel families (3-D full bank: plain tiles / streamed along axis 0; 2-D
+    low-pass analysis: plain tiles / streamed along axis 1), every tile variant, with and without
+    the coarse-level kernel, batch of two."""
+    (shape, order, levels, s), op = case_op
     gen = np.random.default_rng(hash((shape, order, levels, op, 3)) & 0xFFFF)
     x = gen.standard_normal((2,) + shape)
-    say("parity-3d", OP_NAMES[op], shape, order, levels, s, family)
+    say("parity-family", OP_NAMES[op], shape, order, levels, s, family)
     with env(**FAMILY_KNOBS[family]):
         x32, y = _run(op, x, order, levels, s, batch=2)
     for b in range(2):
@@ -90,16 +95,17 @@ def test_parity_3d_families(case, op, family):
         assert err <= TOL, f"instance {b}: rel L2 {err:.3e}"
 
 
-@pytest.mark.parametrize("op", [0, 1], ids=OP_NAMES[:2])
-def test_3d_families_bit_identical(op):
-    """Both 3-D kernel families filter the axes in the same order with the same arithmetic."""
-    shape, order, levels, s = (2, 48, 40, 64), 4, 3, 1.5
+@pytest.mark.parametrize("op,shape", [(0, (2, 48, 40, 64)), (1, (2, 48, 40, 64)), (2, (2, 96, 328)), (3, (2, 96, 328))],
+                         ids=["es_adjoint-3d", "es_apply-3d", "matern_cov_apply-2d", "matern_sample-2d"])
+def test_families_bit_identical(op, shape):
+    """Both kernel families filter the axes in the same order with the same arithmetic."""
+    order, levels, s = 4, 3, 1.5
     x = torch.from_numpy(np.random.default_rng(11).standard_normal(shape).astype(np.float32)).to(DEV)
-    say("3d-families-bits", OP_NAMES[op], shape)
+    say("families-bits", OP_NAMES[op], shape)
     outs = []
     for mode in ("0", "2"):
-        with env(ESWAVE_STREAM3D=mode, ESWAVE_TAIL_MAX=0):
-            outs.append(es.apply_op(op, x, 3, order, levels, s).cpu().numpy())
+        with env(ESWAVE_STREAMED=mode, ESWAVE_TAIL_MAX=0):
+            outs.append(es.apply_op(op, x, len(shape) - 1, order, levels, s).cpu().numpy())
     assert np.array_equal(outs[0], outs[1])
 
 
