@@ -149,6 +149,50 @@ def _time(fn, torch, reps, warmup=1):
     return (time.perf_counter() - t0) / reps
 
 
+FLUSH_BYTES = 512 << 20  # larger than the 256 MB Infinity Cache
+
+
+def _time_cold(fn, torch, reps, flush):
+    """Median duration of fn() with the Infinity Cache flushed before every call (a 512 MB
+    write outside the timed region), HIP events on the current stream around the call."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        flush.fill_(1.0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return statistics.median(ts)
+
+
+def _time_hot(fn, torch, reps):
+    """Median duration of back-to-back calls (caches warm)."""
+    fn()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    return statistics.median(ts)
+
+
+def copy_ceiling(torch, dev, nbytes):
+    """Practical bandwidth ceiling: device-to-device copy of nbytes (read + write), cold."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+    t = _time_cold(lambda: dst.copy_(src), torch, 5, flush)
+    del src, dst, flush
+    return round(2 * nbytes / t / 1e9, 1)
+
+
 def other_workloads(args, es, inputs, torch, np):
     """The other workloads: fused path vs the plain per-instance, per-axis launches."""
     from paper_2507_02401_amd import autograd as ag
@@ -160,9 +204,13 @@ def other_workloads(args, es, inputs, torch, np):
     print("[bench] 128^2 latency", file=sys.stderr, flush=True)
     d = inputs.small_image()
     x = torch.from_numpy(d["x"]).to(dev)
-    tf = _time(lambda: es.matern_cov_apply(x, 2, d["order"], d["levels"], d["s"]), torch, 50, 5)
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+    c1 = lambda: es.matern_cov_apply(x, 2, d["order"], d["levels"], d["s"])
+    tf = _time(c1, torch, 50, 5)
     tp = _time(lambda: es.plain_op(es.OP_COV, x, 2, d["order"], d["levels"], d["s"]), torch, 20, 2)
-    out["image_128_db4_m5_cov"] = {"fused_us": round(1e6 * tf, 2), "plain_us": round(1e6 * tp, 2)}
+    out["image_128_db4_m5_cov"] = {"fused_us": round(1e6 * tf, 2), "plain_us": round(1e6 * tp, 2),
+                                   "fused_us_median_hot": round(1e6 * _time_hot(c1, torch, 21), 2),
+                                   "fused_us_median_cold": round(1e6 * _time_cold(c1, torch, 11, flush), 2)}
 
     # 256^3, db4, 5 levels, s = 2: loss 0.5||E_s^* x - y||^2, forward + backward
     print("[bench] 256^3 autograd", file=sys.stderr, flush=True)
@@ -185,10 +233,14 @@ def other_workloads(args, es, inputs, torch, np):
 
     nv = xv.numel()
     tf, tp, to = _time(fwd_bwd, torch, reps), _time(plain_pair, torch, 2), _time(op_pair, torch, reps)
+    to_cold = _time_cold(op_pair, torch, 7, flush)
     out["volume_256_db4_m5_autograd"] = {
         "fwd_bwd_ms": round(1e3 * tf, 3), "voxels_per_s_fwd_bwd": round(nv / tf, 1),
         "adjoint_plus_apply_ms": round(1e3 * to, 3),
         "effective_GBps_adjoint_plus_apply": round(16 * nv / to / 1e9, 1),
+        "adjoint_plus_apply_ms_median_hot": round(1e3 * _time_hot(op_pair, torch, 7), 3),
+        "adjoint_plus_apply_ms_median_cold": round(1e3 * to_cold, 3),
+        "effective_GBps_cold": round(16 * nv / to_cold / 1e9, 1),
         "plain_pair_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tf, 2)}
     del xv, yv
 
@@ -314,6 +366,12 @@ def main():
     elapsed = time.perf_counter() - t0
     ms = 1e3 * elapsed / args.steps
     value = voxels / (elapsed / args.steps)
+    # the same call with the Infinity Cache flushed before each one (median), and the cold
+    # device-copy rate of the same byte count as the practical bandwidth ceiling
+    flush = torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device=dev)
+    t_cold = _time_cold(step, torch, max(3, min(args.steps, 11)), flush)
+    del flush
+    copy_gbps = copy_ceiling(torch, dev, 4 * voxels)
 
     if args.calibration_copy:
         cal_src = torch.ones(CAL_FLOATS, dtype=torch.float32, device=dev)
@@ -382,6 +440,10 @@ def main():
                    "images": IMAGES, "side": SIDE, "order": ORDER, "levels": LEVELS, "s": S, "op": "matern_cov_apply"},
         "hbm_GBps_effective": round(8.0 * value / 1e9, 1),
         "frac_of_hbm_peak_whole_op": round(8.0 * value / 1e9 / HBM_PEAK_GBPS, 4),
+        "cold": {"ms_median": round(1e3 * t_cold, 4), "value": round(voxels / t_cold, 1),
+                 "hbm_GBps_effective": round(8.0 * voxels / t_cold / 1e9, 1),
+                 "note": "Infinity Cache flushed (512 MB write) before each call, outside the timed region"},
+        "copy_ceiling_GBps": copy_gbps,
         "rel_l2_vs_fp64_oracle_image5": rel,
         "autotuned": not args.no_autotune,
         "roofline": roofline,

@@ -137,12 +137,14 @@ void es_plan_destroy(es_plan* plan);
 
 /* ---- autotuning ------------------------------------------------------------------------- */
 
-/* Times every tile variant of every launch of the operator's launch sequence for this
- * geometry and batch (reps launches each, HIP events on `stream`, synchronising), keeps the
- * fastest per launch in a process-wide cache used by later calls with the same geometry, and
- * leaves the correct result of the operator in `out`.  Arguments as for the operator entry
+/* Times every candidate of every launch of the operator's launch sequence for this geometry
+ * and batch -- the tile variants, and for levels with two kernel families (plain tiles / tiles
+ * streamed along the slowest axis) the variants of both -- in three round-robin rounds of
+ * `reps` launches each (HIP events on `stream`, synchronising), keeps the candidate with the
+ * fastest round per launch in a process-wide cache used by later calls with the same geometry,
+ * and leaves the correct result of the operator in `out`.  Arguments as for the operator entry
  * points.  With the environment variable ESWAVE_TUNE_CACHE naming a file, choices are appended
- * there and read back by later processes.  Tile variants change only the speed: results are
+ * there and read back by later processes.  Candidates change only the speed: results are
  * bit-identical. */
 es_status es_autotune(int op, int ndim, const int64_t* shape, int64_t batch, int order, int levels,
                       double s, const float* in, float* out, void* ws, size_t ws_bytes, int32_t reps,

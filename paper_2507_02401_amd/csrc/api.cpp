@@ -1401,27 +1401,35 @@ es_status es_autotune(int op, int ndim, const int64_t* shape, int64_t batch, int
   hipEvent_t e0, e1;
   ES_HIP(hipEventCreate(&e0), "hipEventCreate");
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(ES_EDEVICE, "hipEventCreate"); }
+  // candidates are timed round-robin over kTuneRounds rounds and each keeps its fastest round,
+  // so that a transient slowdown of the device does not decide the choice
+  constexpr int kTuneRounds = 3;
   std::vector<int> best(sc.launches.size(), -1);
   for (size_t j = 0; j < sc.launches.size() && st == ES_OK; ++j) {
     if (sc.launches[j].is_tail) continue;
-    float best_ms = 1e30f;
-    for (int v = 0; v < num_choices(sc.launches[j]) && st == ES_OK; ++v) {
-      Launch l = sc.launches[j];
-      apply_choice(l, g, v, batch);
-      const int total = (int)(l.task.tiles_per_inst * batch);
-      st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);  // warm
-      if (st != ES_OK) break;
-      if (hipEventRecord(e0, hs) != hipSuccess) { st = fail(ES_EDEVICE, "hipEventRecord"); break; }
-      for (int r = 0; r < reps && st == ES_OK; ++r) st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);
-      if (st != ES_OK) break;
-      float ms = 0.f;
-      if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-        st = fail(ES_EDEVICE, "event timing failed");
-        break;
+    const int nc = num_choices(sc.launches[j]);
+    std::vector<float> t_min(nc, 1e30f);
+    for (int round = 0; round < kTuneRounds && st == ES_OK; ++round) {
+      for (int v = 0; v < nc && st == ES_OK; ++v) {
+        Launch l = sc.launches[j];
+        apply_choice(l, g, v, batch);
+        const int total = (int)(l.task.tiles_per_inst * batch);
+        st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);  // warm
+        if (st != ES_OK) break;
+        if (hipEventRecord(e0, hs) != hipSuccess) { st = fail(ES_EDEVICE, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && st == ES_OK; ++r) st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);
+        if (st != ES_OK) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          st = fail(ES_EDEVICE, "event timing failed");
+          break;
+        }
+        t_min[v] = std::min(t_min[v], ms);
       }
-      if (ms < best_ms) { best_ms = ms; best[j] = v; }
     }
+    for (int v = 0; v < nc; ++v)
+      if (best[j] < 0 || t_min[v] < t_min[best[j]]) best[j] = v;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
