@@ -137,12 +137,13 @@ void es_plan_destroy(es_plan* plan);
 
 /* ---- autotuning ------------------------------------------------------------------------- */
 
-/* Times every candidate of every launch of the operator's launch sequence for this geometry
- * and batch -- the tile variants, and for levels with two kernel families (plain tiles / tiles
- * streamed along the slowest axis) the variants of both -- in three round-robin rounds of
- * `reps` launches each (HIP events on `stream`, synchronising), keeps the candidate with the
- * fastest round per launch in a process-wide cache used by later calls with the same geometry,
- * and leaves the correct result of the operator in `out`.  Arguments as for the operator entry
+/* Chooses, for every launch of the operator's launch sequence for this geometry and batch, among
+ * its candidates -- the tile variants, and for levels with two kernel families (plain tiles /
+ * tiles streamed along the slowest axis) the variants of both.  Each candidate is timed inside
+ * the whole sequence (HIP events on `stream`, synchronising; three round-robin rounds of `reps`
+ * sequences, fastest round kept), launch by launch in sequence order.  The choices go to a
+ * process-wide cache used by later calls with the same geometry, and the correct result of the
+ * operator is left in `out`.  Arguments as for the operator entry
  * points.  With the environment variable ESWAVE_TUNE_CACHE naming a file, choices are appended
  * there and read back by later processes.  Candidates change only the speed: results are
  * bit-identical. */

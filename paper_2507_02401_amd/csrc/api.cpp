@@ -1401,35 +1401,41 @@ es_status es_autotune(int op, int ndim, const int64_t* shape, int64_t batch, int
   hipEvent_t e0, e1;
   ES_HIP(hipEventCreate(&e0), "hipEventCreate");
   if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(ES_EDEVICE, "hipEventCreate"); }
-  // candidates are timed round-robin over kTuneRounds rounds and each keeps its fastest round,
-  // so that a transient slowdown of the device does not decide the choice
+  // Each launch's candidates are timed inside the whole launch sequence (the other launches
+  // keep their current choice), because a launch's speed depends on what the launches before
+  // it left in the caches.  Launches are settled in order (greedy descent); candidates are
+  // timed round-robin over kTuneRounds rounds of `reps` sequences and keep their fastest round.
   constexpr int kTuneRounds = 3;
   std::vector<int> best(sc.launches.size(), -1);
+  auto time_sequence = [&](float* ms) -> es_status {
+    es_status r = run_schedule(sc, g, batch, in, out, hs);  // warm
+    if (r != ES_OK) return r;
+    if (hipEventRecord(e0, hs) != hipSuccess) return fail(ES_EDEVICE, "hipEventRecord");
+    for (int k = 0; k < reps && r == ES_OK; ++k) r = run_schedule(sc, g, batch, in, out, hs);
+    if (r != ES_OK) return r;
+    if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+      return fail(ES_EDEVICE, "event timing failed");
+    return ES_OK;
+  };
   for (size_t j = 0; j < sc.launches.size() && st == ES_OK; ++j) {
     if (sc.launches[j].is_tail) continue;
-    const int nc = num_choices(sc.launches[j]);
+    const Launch keep = sc.launches[j];
+    const int nc = num_choices(keep);
     std::vector<float> t_min(nc, 1e30f);
     for (int round = 0; round < kTuneRounds && st == ES_OK; ++round) {
       for (int v = 0; v < nc && st == ES_OK; ++v) {
-        Launch l = sc.launches[j];
-        apply_choice(l, g, v, batch);
-        const int total = (int)(l.task.tiles_per_inst * batch);
-        st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);  // warm
-        if (st != ES_OK) break;
-        if (hipEventRecord(e0, hs) != hipSuccess) { st = fail(ES_EDEVICE, "hipEventRecord"); break; }
-        for (int r = 0; r < reps && st == ES_OK; ++r) st = run_launch(l, sc.f, hs, nullptr, 1, total, nullptr);
-        if (st != ES_OK) break;
+        sc.launches[j] = keep;
+        apply_choice(sc.launches[j], g, v, batch);
         float ms = 0.f;
-        if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-          st = fail(ES_EDEVICE, "event timing failed");
-          break;
-        }
-        t_min[v] = std::min(t_min[v], ms);
+        st = time_sequence(&ms);
+        if (st == ES_OK) t_min[v] = std::min(t_min[v], ms);
       }
     }
     for (int v = 0; v < nc; ++v)
       if (best[j] < 0 || t_min[v] < t_min[best[j]]) best[j] = v;
+    sc.launches[j] = keep;
+    apply_choice(sc.launches[j], g, best[j], batch);
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -1434,18 +1434,117 @@ DEVI void coarse_synthesis_w(float* sm, int src, int dst, int n0, int n1, int n2
   }
 }
 
-// Uniform dispatch on whether the filtered axis is shorter than the filter (periodic folding).
+// Register-window versions: a thread computes PO consecutive outputs along the filtered axis
+// from one window of inputs (each input read once per window, its wrap resolved once), with
+// the per-output arithmetic of the versions above.  Along the contiguous axis the window is
+// read as 16-byte vectors (start and length multiples of 4, so a vector never straddles the
+// wrap); along the strided axes lanes run along the contiguous axis (conflict-free LDS).
+// Preconditions (checked by the dispatchers): the axis is at least L long (analysis) or its
+// half at least L/2 (synthesis), the outputs per line are a multiple of PO, and for the
+// contiguous axis the block offset is a multiple of 4.
+template <int L>
+DEVI void coarse_analysis_v(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f) {
+  constexpr int PO = 4, WN = 2 * PO + L - 2, W4 = (WN + 3) / 4;
+  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
+  const int o0 = ax == 0 ? n0 >> 1 : n0, o1 = ax == 1 ? n1 >> 1 : n1, o2 = ax == 2 ? n2 >> 1 : n2;
+  // item space: the filtered axis counted in chunks of PO outputs
+  const int p0 = ax == 0 ? o0 / PO : o0, p1 = ax == 1 ? o1 / PO : o1, p2 = ax == 2 ? o2 / PO : o2;
+  const int l1 = ilog2_or_neg(p1), l2 = ilog2_or_neg(p2);
+  const int step = ax == 0 ? n1 * n2 : (ax == 1 ? n2 : 1);
+  const int ostep = ax == 0 ? o1 * o2 : (ax == 1 ? o2 : 1);
+  const int total = p0 * p1 * p2;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, p1, p2, l1, l2, c0, c1, c2);
+    const int k0 = PO * (ax == 0 ? c0 : (ax == 1 ? c1 : c2));
+    const int base = src + (ax == 0 ? 0 : c0 * n1 * n2) + (ax == 1 ? 0 : c1 * n2) + (ax == 2 ? 0 : c2);
+    float win[4 * W4];
+    if (ax == 2) {
+#pragma unroll
+      for (int v = 0; v < W4; ++v) {
+        int i = 2 * k0 + 4 * v;
+        i = i >= n ? i - n : i;
+        const float4 x = *reinterpret_cast<const float4*>(sm + base + i);
+        win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
+      }
+    } else {
+      const int a0 = base + 2 * k0 * step, a0w = a0 - n * step, wrap = n - 2 * k0;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) win[j] = sm[(j >= wrap ? a0w : a0) + j * step];
+    }
+    const int ob = dst + (ax == 0 ? k0 : c0) * o1 * o2 + (ax == 1 ? k0 : c1) * o2 + (ax == 2 ? k0 : c2);
+#pragma unroll
+    for (int q = 0; q < PO; ++q) {
+      float acc = 0.f;
+#pragma unroll
+      for (int t = 0; t < L; ++t) acc = fmaf(f.h[t], win[2 * q + t], acc);
+      sm[ob + q * ostep] = acc;
+    }
+  }
+}
+
+template <int L>
+DEVI void coarse_synthesis_v(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f, bool combine,
+                             float alpha) {
+  // PO = 8 full-res outputs (4 half-res positions q0 .. q0+3) per thread; the window holds the
+  // half-res samples q0 - A .. q0 + 3 with A = L/2 - 1 rounded up to a multiple of 4
+  constexpr int H = L / 2, PO = 8, A = (H - 1 + 3) & ~3, WN = A + 4, W4 = WN / 4;
+  const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2), half = n >> 1;
+  const int h1 = ax == 1 ? half : n1, h2 = ax == 2 ? half : n2;
+  const int p0 = ax == 0 ? n0 / PO : n0, p1 = ax == 1 ? n1 / PO : n1, p2 = ax == 2 ? n2 / PO : n2;
+  const int l1 = ilog2_or_neg(p1), l2 = ilog2_or_neg(p2);
+  const int step = ax == 0 ? h1 * h2 : (ax == 1 ? h2 : 1);
+  const int ostep = ax == 0 ? n1 * n2 : (ax == 1 ? n2 : 1);
+  const int total = p0 * p1 * p2;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, p1, p2, l1, l2, c0, c1, c2);
+    const int q0 = (PO / 2) * (ax == 0 ? c0 : (ax == 1 ? c1 : c2));
+    const int base = src + (ax == 0 ? 0 : c0 * h1 * h2) + (ax == 1 ? 0 : c1 * h2) + (ax == 2 ? 0 : c2);
+    float win[WN];
+    if (ax == 2) {
+#pragma unroll
+      for (int v = 0; v < W4; ++v) {
+        int k = q0 - A + 4 * v;
+        k = k < 0 ? k + half : k;
+        const float4 x = *reinterpret_cast<const float4*>(sm + base + k);
+        win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
+      }
+    } else {
+      const int a0 = base + (q0 - A) * step, a0w = a0 + half * step;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) win[j] = sm[(q0 - A + j < 0 ? a0w : a0) + j * step];
+    }
+    const int p00 = 2 * q0;
+    const int ob = dst + (ax == 0 ? p00 : c0) * n1 * n2 + (ax == 1 ? p00 : c1) * n2 + (ax == 2 ? p00 : c2);
+#pragma unroll
+    for (int r = 0; r < PO; ++r) {
+      const int par = r & 1, qq = r >> 1;  // output 2 (q0 + qq) + par
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < H; ++j) acc = fmaf(f.h[2 * j + par], win[A + qq - j], acc);
+      const int o = ob + r * ostep;
+      sm[o] = combine ? fmaf(alpha, sm[o], acc) : acc;
+    }
+  }
+}
+
+// Uniform dispatch: register-window version where its preconditions hold, else one output per
+// thread with single-wrap or modulo (axis shorter than the filter: periodic folding) indexing.
 template <int L>
 DEVI void coarse_analysis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f) {
   const int n = ax == 0 ? n0 : (ax == 1 ? n1 : n2);
-  if (n >= L) coarse_analysis_w<L, false>(sm, src, dst, n0, n1, n2, ax, f);
+  if (n >= L && (n >> 1) % 4 == 0 && (ax != 2 || src % 4 == 0)) coarse_analysis_v<L>(sm, src, dst, n0, n1, n2, ax, f);
+  else if (n >= L) coarse_analysis_w<L, false>(sm, src, dst, n0, n1, n2, ax, f);
   else coarse_analysis_w<L, true>(sm, src, dst, n0, n1, n2, ax, f);
 }
 template <int L>
 DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, int ax, const Filter& f, bool combine,
                            float alpha) {
   const int half = (ax == 0 ? n0 : (ax == 1 ? n1 : n2)) >> 1;
-  if (half >= L / 2) coarse_synthesis_w<L, false>(sm, src, dst, n0, n1, n2, ax, f, combine, alpha);
+  if (half >= L / 2 && half % 4 == 0 && (ax != 2 || src % 4 == 0))
+    coarse_synthesis_v<L>(sm, src, dst, n0, n1, n2, ax, f, combine, alpha);
+  else if (half >= L / 2) coarse_synthesis_w<L, false>(sm, src, dst, n0, n1, n2, ax, f, combine, alpha);
   else coarse_synthesis_w<L, true>(sm, src, dst, n0, n1, n2, ax, f, combine, alpha);
 }
 
@@ -1453,7 +1552,7 @@ constexpr int kCoarseThreads = 1024;
 
 template <int D, int L>
 __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Filter f) {
-  __shared__ float sm[kCoarseLds];
+  __shared__ __attribute__((aligned(16))) float sm[kCoarseLds];
   const int wg = logical_wg(args.total_wg);
   if (wg < 0) return;
   int ti = 0;
@@ -1607,16 +1706,110 @@ DEVI void fbc_synthesis_w(float* sm, int src, int dst, int S0, int S1, int b0, i
   }
 }
 
+// Register-window versions (as coarse_analysis_v / coarse_synthesis_v, for the strided packed
+// layout of the full bank: low half at k, high half at half + k along the axis).
+template <int L>
+DEVI void fbc_analysis_v(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+  constexpr int PO = 4, WN = 2 * PO + L - 2, W4 = (WN + 3) / 4;
+  const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2), half = n >> 1;
+  const int p0 = ax == 0 ? half / PO : b0, p1 = ax == 1 ? half / PO : b1, p2 = ax == 2 ? half / PO : b2;
+  const int l1 = ilog2_or_neg(p1), l2 = ilog2_or_neg(p2);
+  const int step = ax == 0 ? S0 : (ax == 1 ? S1 : 1);
+  const int total = p0 * p1 * p2;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, p1, p2, l1, l2, c0, c1, c2);
+    const int k0 = PO * (ax == 0 ? c0 : (ax == 1 ? c1 : c2));
+    const int other = (ax == 0 ? 0 : c0 * S0) + (ax == 1 ? 0 : c1 * S1) + (ax == 2 ? 0 : c2);
+    float win[4 * W4];
+    if (ax == 2) {
+#pragma unroll
+      for (int v = 0; v < W4; ++v) {
+        int i = 2 * k0 + 4 * v;
+        i = i >= n ? i - n : i;
+        const float4 x = *reinterpret_cast<const float4*>(sm + src + other + i);
+        win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
+      }
+    } else {
+      const int a0 = src + other + 2 * k0 * step, a0w = a0 - n * step, wrap = n - 2 * k0;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) win[j] = sm[(j >= wrap ? a0w : a0) + j * step];
+    }
+#pragma unroll
+    for (int q = 0; q < PO; ++q) {
+      float lo = 0.f, hi = 0.f;
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        lo = fmaf(f.h[t], win[2 * q + t], lo);
+        hi = fmaf(f.g[t], win[2 * q + t], hi);
+      }
+      sm[dst + other + (k0 + q) * step] = lo;
+      sm[dst + other + (half + k0 + q) * step] = hi;
+    }
+  }
+}
+
+template <int L>
+DEVI void fbc_synthesis_v(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
+  constexpr int H = L / 2, PO = 8, A = (H - 1 + 3) & ~3, WN = A + 4, W4 = WN / 4;
+  const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2), half = n >> 1;
+  const int p0 = ax == 0 ? b0 / PO : b0, p1 = ax == 1 ? b1 / PO : b1, p2 = ax == 2 ? b2 / PO : b2;
+  const int l1 = ilog2_or_neg(p1), l2 = ilog2_or_neg(p2);
+  const int step = ax == 0 ? S0 : (ax == 1 ? S1 : 1);
+  const int total = p0 * p1 * p2;
+  for (int e = threadIdx.x; e < total; e += blockDim.x) {
+    int c0, c1, c2;
+    split3(e, p1, p2, l1, l2, c0, c1, c2);
+    const int q0 = (PO / 2) * (ax == 0 ? c0 : (ax == 1 ? c1 : c2));
+    const int other = (ax == 0 ? 0 : c0 * S0) + (ax == 1 ? 0 : c1 * S1) + (ax == 2 ? 0 : c2);
+    float lo[WN], hi[WN];
+    if (ax == 2) {
+#pragma unroll
+      for (int v = 0; v < W4; ++v) {
+        int k = q0 - A + 4 * v;
+        k = k < 0 ? k + half : k;
+        const float4 x = *reinterpret_cast<const float4*>(sm + src + other + k);
+        const float4 y = *reinterpret_cast<const float4*>(sm + src + other + half + k);
+        lo[4 * v] = x.x; lo[4 * v + 1] = x.y; lo[4 * v + 2] = x.z; lo[4 * v + 3] = x.w;
+        hi[4 * v] = y.x; hi[4 * v + 1] = y.y; hi[4 * v + 2] = y.z; hi[4 * v + 3] = y.w;
+      }
+    } else {
+      const int a0 = src + other + (q0 - A) * step, a0w = a0 + half * step, hs = half * step;
+#pragma unroll
+      for (int j = 0; j < WN; ++j) {
+        const int a = (q0 - A + j < 0 ? a0w : a0) + j * step;
+        lo[j] = sm[a];
+        hi[j] = sm[a + hs];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < PO; ++r) {
+      const int par = r & 1, qq = r >> 1;  // output 2 (q0 + qq) + par
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < H; ++j) {
+        acc = fmaf(f.h[2 * j + par], lo[A + qq - j], acc);
+        acc = fmaf(f.g[2 * j + par], hi[A + qq - j], acc);
+      }
+      sm[dst + other + (2 * q0 + r) * step] = acc;
+    }
+  }
+}
+
 template <int L>
 DEVI void fbc_analysis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
   const int n = ax == 0 ? b0 : (ax == 1 ? b1 : b2);
-  if (n >= L) fbc_analysis_w<L, false>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
+  if (n >= L && (n >> 1) % 4 == 0 && (ax != 2 || (src % 4 == 0 && S1 % 4 == 0 && S0 % 4 == 0)))
+    fbc_analysis_v<L>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
+  else if (n >= L) fbc_analysis_w<L, false>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
   else fbc_analysis_w<L, true>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
 }
 template <int L>
 DEVI void fbc_synthesis(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
   const int half = (ax == 0 ? b0 : (ax == 1 ? b1 : b2)) >> 1;
-  if (half >= L / 2) fbc_synthesis_w<L, false>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
+  if (half >= L / 2 && half % 4 == 0 && (ax != 2 || (src % 4 == 0 && S1 % 4 == 0 && S0 % 4 == 0)))
+    fbc_synthesis_v<L>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
+  else if (half >= L / 2) fbc_synthesis_w<L, false>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
   else fbc_synthesis_w<L, true>(sm, src, dst, S0, S1, b0, b1, b2, ax, f);
 }
 
@@ -1635,7 +1828,7 @@ DEVI float fbc_weight(const float* coef, int nlev, int n0, int n1, int n2, int c
 
 template <int D, int L, bool SYN>
 __global__ void __launch_bounds__(kFbCoarseThreads) k_fb_coarse(TailArgs args, Filter f) {
-  __shared__ float sm[2 * kFbCoarseMax];
+  __shared__ __attribute__((aligned(16))) float sm[2 * kFbCoarseMax];
   const int wg = logical_wg(args.total_wg);
   if (wg < 0) return;
   int ti = 0;
