@@ -451,6 +451,18 @@ def main():
     }
 
     if not args.no_extras:
+        # squared H^s norm of the same batch: fused reduction vs coefficients + a torch reduction
+        print("[bench] H^s norm", file=sys.stderr, flush=True)
+        nws = torch.empty(max(1, lib.es_hs_norm_workspace_bytes(2, shp, IMAGES, ORDER, LEVELS)), dtype=torch.uint8,
+                          device=dev)
+        tn = _time(lambda: es.hs_norm_sq(x, 2, ORDER, LEVELS, S, workspace=nws), torch, reps)
+        tu = _time(lambda: (es.es_adjoint(x, 2, ORDER, LEVELS, -S, out=y, workspace=ws).double() ** 2).sum(dim=(1, 2)),
+                   torch, reps)
+        nv = es.hs_norm_sq(x, 2, ORDER, LEVELS, S, workspace=nws)[i_s].item()
+        nref = oracle.hs_norm_sq(data["x"][i_s].astype(np.float64), ORDER, LEVELS, S)
+        result["hs_norm_sq"] = {"ms": round(1e3 * tn, 4), "voxels_per_s": round(voxels / tn, 1),
+                                "effective_GBps": round(4.0 * voxels / tn / 1e9, 1),
+                                "unfused_ms": round(1e3 * tu, 4), "rel_err_vs_fp64_oracle_image5": abs(nv - nref) / nref}
         result["other_workloads"] = other_workloads(args, es, inputs, torch, np)
 
     if not args.no_plain:

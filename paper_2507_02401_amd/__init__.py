@@ -5,10 +5,10 @@ E_s^* X = W^{-1}(D (W X)) with W a periodic orthonormal Daubechies DWT and D the
 per-level weights, as hand-written HIP kernels behind a C ABI (include/eswave.h).
 """
 from ._lib import (OP_ADJOINT, OP_APPLY, OP_COV, OP_SAMPLE, EswaveError, load)
-from .ops import (RaggedPlan, apply_op, autotune, es_adjoint, es_apply, matern_cov_apply, matern_sample, matern_to_s,
-                  plain_op, workspace_bytes)
+from .ops import (RaggedPlan, apply_op, autotune, es_adjoint, es_apply, hs_norm_sq, matern_cov_apply, matern_sample,
+                  matern_to_s, plain_op, workspace_bytes)
 from . import autograd
 
 __all__ = ["autotune", "OP_ADJOINT", "OP_APPLY", "OP_COV", "OP_SAMPLE", "EswaveError", "load", "RaggedPlan", "apply_op",
-           "es_adjoint", "es_apply", "matern_cov_apply", "matern_sample", "matern_to_s", "plain_op",
+           "es_adjoint", "es_apply", "hs_norm_sq", "matern_cov_apply", "matern_sample", "matern_to_s", "plain_op",
            "workspace_bytes", "autograd"]

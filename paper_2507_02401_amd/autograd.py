@@ -1,4 +1,4 @@
-"""torch.autograd.Function forms of the four operators.
+"""torch.autograd.Function forms of the four operators and of the squared H^s norm.
 
 Every operator is linear, so the backward pass is the adjoint applied to the incoming
 gradient: es_adjoint^T = es_apply (synthesis instead of analysis, same level weights),
@@ -52,6 +52,29 @@ class MaternSampleFn(torch.autograd.Function):
     @staticmethod
     def backward(ctx, g):
         return ops.matern_sample(g.contiguous(), *ctx.args), None, None, None, None
+
+
+class HsNormSqFn(torch.autograd.Function):
+    """||x||^2_{H^s} per instance; its gradient is 2 W^T D_{-2s} W x, the covariance operator with
+    smoothness -s (the precision operator), scaled by the incoming gradient of each instance."""
+
+    @staticmethod
+    def forward(ctx, x, ndim, order, levels, s):
+        ctx.args = (ndim, order, levels, s)
+        ctx.save_for_backward(x)
+        return ops.hs_norm_sq(x, ndim, order, levels, s)
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        ndim, order, levels, s = ctx.args
+        p = ops.matern_cov_apply(x.contiguous(), ndim, order, levels, -s)
+        scale = (2.0 * g).to(p.dtype).reshape(g.shape + (1,) * ndim)
+        return scale * p, None, None, None, None
+
+
+def hs_norm_sq(x, ndim, order, levels, s):
+    return HsNormSqFn.apply(x, ndim, order, levels, s)
 
 
 def es_adjoint(x, ndim, order, levels, s):

@@ -1148,6 +1148,110 @@ size_t es_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int ord
   return (size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float);
 }
 
+// ------------------------------------------------------------------------------------------
+// Squared H^s norm: ||x||^2_{H^s} = ||D_{-s} W x||^2 = sum of 2^{2 s j} c^2 over the orthonormal
+// coefficients c = W x (detail level i: j = m - i; approximation: 1).  The analysis launch
+// sequence of es_adjoint with smoothness -s runs in squared-norm mode: coefficients are squared
+// and summed per work-group instead of stored, and one finalising launch adds the partials of
+// each instance in a fixed order.
+
+// Partial sums (doubles) the squared-norm mode needs per instance: for every level launch the
+// most tiles any of its candidates uses, plus one for the coarse-level kernel.
+int64_t norm_partials_per_instance(const Geo& g) {
+  Schedule sc;
+  if (build_schedule_raw(ES_OP_ADJOINT, g, 1, (const float*)(uintptr_t)256, (float*)(uintptr_t)512,
+                         (float*)(uintptr_t)1024, &sc) != ES_OK)
+    return -1;
+  int64_t n = 0;
+  for (const Launch& l : sc.launches) {
+    if (l.is_tail) { n += 1; continue; }
+    int64_t mx = 0;
+    for (int c = 0; c < num_choices(l); ++c) {
+      Launch k = l;
+      apply_choice(k, g, c, 1);
+      mx = std::max<int64_t>(mx, k.task.tiles_per_inst);
+    }
+    n += mx;
+  }
+  return n;
+}
+
+size_t norm_ws_bytes(const Geo& g, int64_t batch) {
+  if (g.m == 0 || batch <= 0) return 0;
+  const int64_t per = norm_partials_per_instance(g);
+  if (per < 0) return 0;
+  const size_t lv = ((size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float) + 255) & ~(size_t)255;
+  return lv + (size_t)batch * (size_t)per * sizeof(double);
+}
+
+size_t es_hs_norm_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels) {
+  Geo g;
+  if (make_geo(ndim, shape, order, levels, 0.0, &g) != ES_OK || batch < 0) return 0;
+  return norm_ws_bytes(g, batch);
+}
+
+es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                        const float* x, double* norms, void* ws, size_t ws_bytes, void* stream) {
+  Geo g;
+  es_status st = make_geo(ndim, shape, order, levels, -s, &g);  // weights 2^{+s j}
+  if (st != ES_OK) return st;
+  if (batch < 0) return fail(ES_EINVAL, "batch must be >= 0");
+  if (batch == 0) return ES_OK;
+  if (batch > 0x7fffffffll) return fail(ES_EINVAL, "batch too large");
+  if (!x || !norms) return fail(ES_EINVAL, "input and output pointers must be non-NULL");
+  if (((uintptr_t)x & 15) || ((uintptr_t)norms & 7))
+    return fail(ES_EINVAL, "input must be 16-byte and output 8-byte aligned");
+  const size_t xbytes = (size_t)(batch * g.N()) * sizeof(float);
+  if (overlap(x, xbytes, norms, (size_t)batch * sizeof(double))) return fail(ES_EINVAL, "input and output overlap");
+  const size_t need = norm_ws_bytes(g, batch);
+  if (need) {
+    if (!ws) return fail(ES_EWORKSPACE, "workspace of %zu bytes required, got NULL", need);
+    if (ws_bytes < need) return fail(ES_EWORKSPACE, "workspace of %zu bytes required, got %zu", need, ws_bytes);
+    if ((uintptr_t)ws & 255) return fail(ES_EINVAL, "workspace must be 256-byte aligned");
+    if (overlap(ws, need, x, xbytes) || overlap(ws, need, norms, (size_t)batch * sizeof(double)))
+      return fail(ES_EINVAL, "workspace overlaps input or output");
+  }
+  st = check_device();
+  if (st != ES_OK) return st;
+  const hipStream_t hs = (hipStream_t)stream;
+  if (g.m == 0) {  // W = I
+    ES_HIP(launch_sumsq(x, g.N(), batch, norms, hs), "sum-of-squares launch");
+    return ES_OK;
+  }
+  float* lv = (float*)ws;
+  double* partials = (double*)((char*)ws + (((size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float) + 255) &
+                                            ~(size_t)255));
+  Schedule sc;
+  // the coefficient array is never written in squared-norm mode: pass the partials as its address
+  st = build_schedule(ES_OP_ADJOINT, g, batch, x, (float*)partials, lv, &sc);
+  if (st != ES_OK) return st;
+  bool has_tail = false;
+  for (const Launch& l : sc.launches) has_tail |= l.is_tail != 0;
+  NormSegs segs{};
+  int64_t off = 0;
+  for (size_t j = 0; j < sc.launches.size(); ++j) {
+    Launch& l = sc.launches[j];
+    if (segs.count >= kMaxNormSegs) return fail(ES_EUNSUPPORTED, "too many levels for the squared-norm mode");
+    segs.off[segs.count] = off;
+    if (l.is_tail) {
+      l.tail.flags = kNormSq;
+      l.tail.out = (float*)(partials + off);
+      segs.per[segs.count++] = 1;
+      off += batch;
+    } else {
+      l.task.flags = kNormSq | ((!has_tail && j + 1 == sc.launches.size()) ? kNormLL : 0);
+      l.task.out0 = (float*)(partials + off);
+      l.task.bs_out0 = 0;
+      segs.per[segs.count++] = l.task.tiles_per_inst;
+      off += (int64_t)l.task.tiles_per_inst * batch;
+    }
+  }
+  st = run_schedule(sc, g, batch, x, (float*)partials, hs);
+  if (st != ES_OK) return st;
+  ES_HIP(launch_norm_finalize(partials, segs, norms, batch, hs), "norm finalize launch");
+  return ES_OK;
+}
+
 size_t es_workspace_bytes_plain(int ndim, const int64_t* shape, int64_t batch, int order, int levels, int op) {
   Geo g;
   (void)batch;

@@ -45,8 +45,13 @@ struct Task {
   int32_t ntile[3];
   int32_t tiles_per_inst;
   int32_t tile_begin;  // first work-group index of this task within the launch
-  int32_t pad_;
+  int32_t flags;       // kNorm*: squared-norm mode of the full-bank analysis kernels
 };
+// Squared-norm mode (FB_DOWN / FB_DOWN_S / full-bank coarse analysis): the weighted coefficients
+// are summed as squares instead of stored; each work-group writes its partial sum (double) to
+// ((double*)out0)[work-group index within the task] (tail: ((double*)out)[instance]).
+constexpr int32_t kNormSq = 1;   // detail bands are summed, not stored
+constexpr int32_t kNormLL = 2;   // the approximation output is final: summed, not stored
 
 // Launch arguments: tasks either inline (count == 1) or in a device table.
 struct TaskArgs {
@@ -69,7 +74,7 @@ struct TailTask {
   int32_t batch;
   int32_t b[3];      // block at the tail's first level T
   int32_t nlev;      // levels handled inside the tail
-  int32_t pad_;
+  int32_t flags;     // kNormSq: full-bank analysis sums squares (partial per instance to out)
   // LP:   coef[0] = alpha for the output (w_1 if T == 0 else c_T), coef[1 + j] = c_{T+1+j};
   //       the last level's z is c_{m-1} a_{m-1}.
   // FB:   coef[j] = weight of the detail bands of tail level j (j = 0 finest), coef[nlev] =
@@ -137,6 +142,19 @@ hipError_t launch_plain_pass(const PlainPass& p, int taps, const Filter& f, hipS
 hipError_t launch_block_copy(const float* src, float* dst, const int b[3], const int st_src[2],
                              const int st_dst[2], hipStream_t stream);
 hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t stream);
+
+// Squared-norm finalisation: out[b] = sum over segments k of partials[off_k + b*per_k + t],
+// t < per_k, in a fixed order (deterministic).  kMaxNormSegs segments at most.
+constexpr int kMaxNormSegs = 40;
+struct NormSegs {
+  int64_t off[kMaxNormSegs];
+  int32_t per[kMaxNormSegs];
+  int32_t count;
+};
+hipError_t launch_norm_finalize(const double* partials, const NormSegs& segs, double* out, int64_t batch,
+                                hipStream_t stream);
+// Sum of squares of each of `batch` contiguous instances of n floats (identity transform).
+hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, double* out, hipStream_t stream);
 
 // Host filter derivation (filters.cpp).
 bool daubechies_filter(int order, double* h_out);

@@ -69,6 +69,24 @@ DEVI void gather_to_lds(int n, Src src, Dst dst) {
   }
 }
 
+// Sum of one value per thread over the work-group, in a fixed order (wave reduction, then the
+// waves in index order); thread 0 stores it.  Every thread of the work-group must call it.
+template <int NT>
+DEVI void store_wg_sum(double v, double* dst) {
+  __shared__ double part[NT / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tsum = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) tsum += part[i];
+    *dst = tsum;
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Work-group -> task/tile mapping.
 //
@@ -826,6 +844,7 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
   for (int j = 0; j < H; ++j)
 #pragma unroll
     for (int u = 0; u < QT; ++u) alo[j][u] = ahi[j][u] = 0.f;
+  float nsq = 0.f;  // squared-norm mode: this thread's sum
 
   for (int p = 0; p < NP; ++p) {
     if constexpr (VEC) {
@@ -879,11 +898,15 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
           // band (e0, e1, e2) at half-res position (g0, g1, g2)
           const float lo = alo[H - 1][u], hi = ahi[H - 1][u];
           if ((e1 | e2) == 0) {
-            gst(ll + g0 * t.st_out1[0] + g1 * t.st_out1[1] + g2, beta * lo);
+            if (t.flags & kNormLL) nsq = fmaf(beta * lo, beta * lo, nsq);
+            else gst(ll + g0 * t.st_out1[0] + g1 * t.st_out1[1] + g2, beta * lo);
+          } else if (t.flags & kNormSq) {
+            nsq = fmaf(alpha * lo, alpha * lo, nsq);
           } else {
             gst(coef + g0 * t.st_out0[0] + (e1 * h1 + g1) * t.st_out0[1] + e2 * h2 + g2, alpha * lo);
           }
-          gst(coef + (h0 + g0) * t.st_out0[0] + (e1 * h1 + g1) * t.st_out0[1] + e2 * h2 + g2, alpha * hi);
+          if (t.flags & kNormSq) nsq = fmaf(alpha * hi, alpha * hi, nsq);
+          else gst(coef + (h0 + g0) * t.st_out0[0] + (e1 * h1 + g1) * t.st_out0[1] + e2 * h2 + g2, alpha * hi);
         }
       }
     }
@@ -897,6 +920,7 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
 #pragma unroll
     for (int u = 0; u < QT; ++u) alo[0][u] = ahi[0][u] = 0.f;
   }
+  if (t.flags & kNormSq) store_wg_sum<NT>(nsq, reinterpret_cast<double*>(t.out0) + (wg - t.tile_begin));
 }
 
 // FB_UP_S: full-res output tile U1 x U2 in-plane, R output slices (R even).  Output pair Q (full-
@@ -1118,11 +1142,15 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
 
   const int n0h = b0 >> 1, n1h = b1 >> 1, n2h = b2 >> 1;
   const float alpha = t.alpha, beta = t.beta;
+  float nsq = 0.f;  // squared-norm mode: this thread's sum
   // write one coefficient of band (e0,e1,e2) at half-res position (g0,g1,g2)
   auto emit = [&](int e0, int e1, int e2, int g0, int g1, int g2, float v) {
     if (g0 >= (D >= 3 ? n0h : 1) || g1 >= (D >= 2 ? n1h : 1) || g2 >= n2h) return;
     if ((e0 | e1 | e2) == 0) {
-      gst(ll + (D >= 3 ? g0 * t.st_out1[0] : 0) + (D >= 2 ? g1 * t.st_out1[1] : 0) + g2, beta * v);
+      if (t.flags & kNormLL) nsq = fmaf(beta * v, beta * v, nsq);
+      else gst(ll + (D >= 3 ? g0 * t.st_out1[0] : 0) + (D >= 2 ? g1 * t.st_out1[1] : 0) + g2, beta * v);
+    } else if (t.flags & kNormSq) {
+      nsq = fmaf(alpha * v, alpha * v, nsq);
     } else {
       const int r0 = e0 * n0h + g0, r1 = e1 * n1h + g1, r2 = e2 * n2h + g2;
       gst(coef + (D >= 3 ? r0 * t.st_out0[0] : 0) + (D >= 2 ? r1 * t.st_out0[1] : 0) + r2, alpha * v);
@@ -1176,6 +1204,7 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
           emit(1, e1, e2, g0, g1, g2, hi);
         });
   }
+  if (t.flags & kNormSq) store_wg_sum<NT>(nsq, reinterpret_cast<double*>(t.out0) + (wg - t.tile_begin));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1886,12 +1915,17 @@ __global__ void __launch_bounds__(kFbCoarseThreads) k_fb_coarse(TailArgs args, F
         __syncthreads();
       }
     }
+    const bool norm = (tp->flags & kNormSq) != 0;
+    float nsq = 0.f;
     for (int e = threadIdx.x; e < B; e += blockDim.x) {
       int c0, c1, c2;
       split3(e, n1, n2, l1, l2, c0, c1, c2);
       const float w = fbc_weight(tp->coef, nl, n0, n1, n2, c0, c1, c2, D);
-      gst(out + (D >= 3 ? c0 * out0 : 0) + (D >= 2 ? c1 * out1 : 0) + c2, w * sm[CUR + e]);
+      const float v = w * sm[CUR + e];
+      if (norm) nsq = fmaf(v, v, nsq);
+      else gst(out + (D >= 3 ? c0 * out0 : 0) + (D >= 2 ? c1 * out1 : 0) + c2, v);
     }
+    if (norm) store_wg_sum<kFbCoarseThreads>(nsq, reinterpret_cast<double*>(tp->out) + inst);
   } else {
     gather_to_lds<kFbCoarseThreads, U>(
         B,
@@ -2028,6 +2062,30 @@ namespace {
 
 // (kind, ndim, variant, taps) -> tile.  Variant 0 = wide, 1 = narrow (thin or small blocks).
 // Analysis kinds: half-res output tile per band; synthesis kinds: full-res output tile.
+// Squared-norm finalisation: one work-group per instance, segments in order, each segment's
+// partials strided over the threads, then the work-group sum (fixed order: deterministic).
+__global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict__ partials, NormSegs segs,
+                                                       double* __restrict__ out) {
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (int k = 0; k < segs.count; ++k) {
+    const double* p = partials + segs.off[k] + (int64_t)b * segs.per[k];
+    for (int i = threadIdx.x; i < segs.per[k]; i += 256) acc += p[i];
+  }
+  store_wg_sum<256>(acc, out + b);
+}
+
+// Sum of squares of each instance (levels = 0: the transform is the identity).
+__global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ out) {
+  const float* p = x + (int64_t)blockIdx.x * n;
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double v = gld(p + i);
+    acc += v * v;
+  }
+  store_wg_sum<256>(acc, out + blockIdx.x);
+}
+
 struct Shape3 {
   int a, b, c;
 };
@@ -2229,6 +2287,19 @@ hipError_t launch_block_copy(const float* src, float* dst, const int b[3], const
   const int64_t total = (int64_t)b[0] * b[1] * b[2];
   hipLaunchKernelGGL(k_block_copy, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, src, dst, b[0], b[1], b[2],
                      st_src[0], st_src[1], st_dst[0], st_dst[1]);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize(const double* partials, const NormSegs& segs, double* out, int64_t batch,
+                                hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_norm_finalize, dim3((unsigned)batch), dim3(256), 0, s, partials, segs, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, double* out, hipStream_t s) {
+  if (batch <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sumsq, dim3((unsigned)batch), dim3(256), 0, s, x, n, out);
   return hipGetLastError();
 }
 

@@ -81,6 +81,24 @@ def matern_sample(xi, ndim, order, levels, s, out=None, workspace=None):
     return apply_op(OP_SAMPLE, xi, ndim, order, levels, s, out, workspace)
 
 
+def hs_norm_sq(x, ndim, order, levels, s, workspace=None):
+    """||x||^2_{H^s} per instance (float64 tensor of the batch shape): sum of 2^{2sj} c^2 over
+    the orthonormal wavelet coefficients c = W x, summed on the GPU without storing c."""
+    grid, batch = _split(x, ndim)
+    x = x.contiguous()
+    lib = load()
+    shp = shape_arg(grid)
+    out = torch.empty(batch, dtype=torch.float64, device=x.device)
+    need = int(lib.es_hs_norm_workspace_bytes(ndim, shp, batch, int(order), int(levels)))
+    ws = _ws(need, x.device, workspace)
+    with torch.cuda.device(x.device):
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        st = lib.es_hs_norm_sq(ndim, shp, batch, int(order), int(levels), float(s), x.data_ptr(), out.data_ptr(),
+                               ws.data_ptr() if ws is not None else None, need, stream)
+    check(st)
+    return out.reshape(x.shape[:x.dim() - ndim])
+
+
 def plain_op(op, x, ndim, order, levels, s, out=None):
     """Reference variant: one launch per 1-D pass per level per instance."""
     grid, batch = _split(x, ndim)

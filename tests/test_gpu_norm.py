@@ -1,0 +1,89 @@
+"""GPU: the squared H^s norm (fused reduction) and its gradient vs the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2507_02401_amd as es
+from paper_2507_02401_amd import autograd as ag
+from tests.gpu_util import TOL, env, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+CASES = [
+    # shape, order, levels, s
+    ((4096,), 8, 5, 1.0),
+    ((104, 136), 4, 3, 1.5),
+    ((256, 384), 6, 5, 1.5),
+    ((16, 16), 8, 4, -0.5),
+    ((96, 32), 1, 5, 0.5),
+    ((24, 40, 56), 4, 3, 2.0),
+    ((32, 32, 32), 2, 5, 1.0),
+    ((64, 64), 3, 0, 1.0),
+]
+KNOBS = {"auto": {}, "notail": dict(ESWAVE_TAIL_MAX=0), "streamed": dict(ESWAVE_STREAMED=2),
+         "tiled": dict(ESWAVE_STREAMED=0), "narrow": dict(ESWAVE_FORCE_VARIANT=1)}
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-db{c[1]}-m{c[2]}-s{c[3]}")
+@pytest.mark.parametrize("mode", list(KNOBS))
+def test_norm_parity(case, mode):
+    shape, order, levels, s = case
+    x = np.random.default_rng(hash((shape, order, levels)) & 0xFFFF).standard_normal((2,) + shape).astype(np.float32)
+    say("hs_norm", shape, order, levels, s, mode)
+    with env(**KNOBS[mode]):
+        got = es.hs_norm_sq(torch.from_numpy(x).to(DEV), len(shape), order, levels, s).cpu().numpy()
+    assert got.dtype == np.float64 and got.shape == (2,)
+    for b in range(2):
+        ref = oracle.hs_norm_sq(x[b].astype(np.float64), order, levels, s)
+        assert abs(got[b] - ref) <= TOL * ref, (b, got[b], ref)
+
+
+def test_norm_equals_weighted_coefficients_and_is_deterministic():
+    """||x||^2_{H^s} = ||E_{-s}^* x||^2 (the coefficients with the inverse weights), bit-stable."""
+    shape, order, levels, s = (3, 128, 96), 5, 4, 1.25
+    x = torch.from_numpy(np.random.default_rng(5).standard_normal(shape).astype(np.float32)).to(DEV)
+    say("hs_norm vs adjoint", shape)
+    n1 = es.hs_norm_sq(x, 2, order, levels, s)
+    n2 = es.hs_norm_sq(x, 2, order, levels, s)
+    assert torch.equal(n1, n2)
+    c = es.es_adjoint(x, 2, order, levels, -s).double()
+    ref = (c * c).sum(dim=(1, 2))
+    assert torch.allclose(n1, ref, rtol=1e-6, atol=0)
+
+
+def test_norm_s0_is_parseval():
+    shape = (2, 64, 64, 32)
+    x = torch.from_numpy(np.random.default_rng(6).standard_normal(shape).astype(np.float32)).to(DEV)
+    say("hs_norm s=0", shape)
+    got = es.hs_norm_sq(x, 3, 4, 3, 0.0)
+    ref = (x.double() ** 2).sum(dim=(1, 2, 3))
+    assert torch.allclose(got, ref, rtol=1e-6, atol=0)
+
+
+@pytest.mark.parametrize("shape,ndim", [((2, 96, 64), 2), ((32, 16, 24), 3)])
+def test_norm_gradient(shape, ndim):
+    """d/dx ||x||^2_{H^s} = 2 W^T D_{-2s} W x, against the oracle's covariance with -s."""
+    order, levels, s = 4, 3, 1.5
+    x = np.random.default_rng(7).standard_normal(shape).astype(np.float32)
+    w = np.array([0.7, -1.3]) if ndim == 2 else np.array(0.9)
+    say("hs_norm grad", shape)
+    xt = torch.from_numpy(x).to(DEV).requires_grad_(True)
+    n = ag.hs_norm_sq(xt, ndim, order, levels, s)
+    (n * torch.from_numpy(w).to(DEV)).sum().backward()
+    g = xt.grad.cpu().numpy()
+    xs = x.reshape((-1,) + shape[-ndim:])
+    ws_ = np.atleast_1d(w)
+    for b in range(xs.shape[0]):
+        ref = 2 * ws_[b] * oracle.matern_cov_apply(xs[b].astype(np.float64), order, levels, -s)
+        assert rel_l2(g.reshape(xs.shape)[b], ref) <= TOL
+
+
+def test_norm_errors():
+    x = torch.zeros(2, 64, 64, device=DEV)
+    with pytest.raises(es.EswaveError):
+        es.hs_norm_sq(x, 2, 4, 7, 1.0)  # 64 not divisible by 2^7
+    with pytest.raises(es.EswaveError):
+        es.hs_norm_sq(x, 2, 9, 3, 1.0)  # order out of range
+    assert es.hs_norm_sq(x[:0], 2, 4, 3, 1.0).numel() == 0

@@ -111,6 +111,20 @@ def test_validation_before_any_device_call(lib, kw, status, name):
     assert len(lib.es_last_error()) > 0
 
 
+def test_norm_workspace_and_validation(lib):
+    shp = _lib.shape_arg((64, 96))
+    assert lib.es_hs_norm_workspace_bytes(2, shp, 3, 4, 0) == 0  # identity: no workspace
+    need = lib.es_hs_norm_workspace_bytes(2, shp, 3, 4, 3)
+    # level arrays (a_1 .. a_3 of 3 instances) plus at least one partial sum per launch and instance
+    assert need >= 3 * 4 * (32 * 48 + 16 * 24 + 8 * 12) + 3 * 8 * 2
+    x, o, w = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 32)
+    assert lib.es_hs_norm_sq(2, shp, 3, 4, 7, 1.0, x, o, w, need, None) == 1  # 64 not divisible by 2^7
+    assert lib.es_hs_norm_sq(2, shp, 3, 4, 3, 1.0, ctypes.c_void_p((1 << 20) + 4), o, w, need, None) == 1  # misaligned
+    assert lib.es_hs_norm_sq(2, shp, 3, 4, 3, 1.0, x, o, w, need - 1, None) == 2  # workspace too small
+    assert lib.es_hs_norm_sq(2, shp, 3, 4, 3, 1.0, x, o, None, 0, None) == 2
+    assert lib.es_hs_norm_sq(2, shp, 0, 4, 3, 1.0, None, None, None, 0, None) == 0  # empty batch
+
+
 def test_batch_zero_is_noop(lib):
     assert _call(lib, batch=0, x=0, y=0, ws=0, ws_bytes=0) == _lib.ES_OK
 

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import (daubechies_lowpass, dwt, es_adjoint, es_apply, level_weights, matern_cov_apply,
+from oracle import (daubechies_lowpass, dwt, es_adjoint, es_apply, idwt, level_weights, matern_cov_apply,
                     matern_sample, weight_map)
 from oracle.dense import operator_matrices
 
@@ -143,6 +143,22 @@ def test_hs_inner_product_defines_adjoint():
     # ||x||_{H^s}^2 = <x, Gamma^2 x>, and Gamma^2 inverts the covariance
     xc = matern_cov_apply(x, order, levels, s)
     assert abs(oracle.hs_norm_sq(xc, order, levels, s) - np.sum(xc * x)) < 1e-11 * np.sum(x * x)
+
+
+def test_hs_norm_parseval_and_levels():
+    """s = 0: the orthonormal W keeps the Euclidean norm (Parseval); a detail-only input of one
+    level scales as 2^{2 s j}; a constant lives in the approximation (weight 1)."""
+    shape, order, levels = (32, 16), 4, 3
+    x = _rand(shape, 11)
+    assert abs(oracle.hs_norm_sq(x, order, levels, 0.0) - np.sum(x * x)) < 1e-12 * np.sum(x * x)
+    h = daubechies_lowpass(order)
+    c = np.zeros(shape)
+    c[8:16, 0:4] = _rand((8, 4), 12)  # band (1, 0) of level 2: rows [n0/4, n0/2), cols [0, n1/4); j = m - 2 = 1
+    xi = idwt(c, h, levels)
+    for s in (0.5, 1.5, -1.0):
+        assert abs(oracle.hs_norm_sq(xi, order, levels, s) - 2.0 ** (2 * s * 1) * np.sum(c * c)) < 1e-11 * np.sum(c * c)
+    k = np.full(shape, 0.3)
+    assert abs(oracle.hs_norm_sq(k, order, levels, 2.0) - np.sum(k * k)) < 1e-12 * np.sum(k * k)
 
 
 def test_weight_map_layout():
