@@ -455,6 +455,8 @@ def main():
         print("[bench] H^s norm", file=sys.stderr, flush=True)
         nws = torch.empty(max(1, lib.es_hs_norm_workspace_bytes(2, shp, IMAGES, ORDER, LEVELS)), dtype=torch.uint8,
                           device=dev)
+        if not args.no_autotune:  # the norm runs the analysis sequence of es_adjoint: tune that geometry
+            es.autotune(es.OP_ADJOINT, x, 2, ORDER, LEVELS, -S, out=y)
         tn = _time(lambda: es.hs_norm_sq(x, 2, ORDER, LEVELS, S, workspace=nws), torch, reps)
         tu = _time(lambda: (es.es_adjoint(x, 2, ORDER, LEVELS, -S, out=y, workspace=ws).double() ** 2).sum(dim=(1, 2)),
                    torch, reps)
