@@ -465,6 +465,24 @@ def main():
         result["hs_norm_sq"] = {"ms": round(1e3 * tn, 4), "voxels_per_s": round(voxels / tn, 1),
                                 "effective_GBps": round(4.0 * voxels / tn / 1e9, 1),
                                 "unfused_ms": round(1e3 * tu, 4), "rel_err_vs_fp64_oracle_image5": abs(nv - nref) / nref}
+        # Tikhonov reconstruction with the H^s prior: mask Bernoulli(0.3), PCG to 1e-5
+        print("[bench] Tikhonov PCG", file=sys.stderr, flush=True)
+        from paper_2507_02401_amd.solver import tikhonov_pcg
+        gmask = torch.Generator(device=dev).manual_seed(1)
+        msk = (torch.rand(x.shape, generator=gmask, device=dev) < 0.3).float()
+        pdat = msk * x
+        tikhonov_pcg(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xr, info = tikhonov_pcg(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=200, rtol=1e-5)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        its = max(1, info["iterations"])
+        result["tikhonov_pcg"] = {"iterations": info["iterations"], "ms_total": round(1e3 * tt, 3),
+                                  "ms_per_iteration": round(1e3 * tt / its, 4),
+                                  "max_rel_residual": float(info["rel_residual"].max()),
+                                  "operator_applications_per_iteration": 2, "alpha": 0.05, "mask_density": 0.3}
+        del xr, msk, pdat
         result["other_workloads"] = other_workloads(args, es, inputs, torch, np)
 
     if not args.no_plain:

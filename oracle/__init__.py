@@ -23,7 +23,9 @@ Pinning status (see tests/test_oracle_*.py):
                     and the spectrum closed form;
   * operators    -- pinned by the identities s=0 / m=0, constants preserved,
                     brute-force adjointness, the semigroup and square-root
-                    identities.
+                    identities;
+  * Tikhonov solve -- pinned by a dense direct solve of the normal equations
+                    on tiny grids and by the first-order optimality condition.
   The absolute Matern scale constant of Cor. 4.3 is not part of the path and
   is not implemented (parity unpinned; the constant is dropped as Remark 3.3
   allows).
@@ -32,11 +34,12 @@ Pinning status (see tests/test_oracle_*.py):
 from .filters import daubechies_lowpass, quadrature_highpass
 from .dwt import analysis_axis, synthesis_axis, dwt, idwt, level_weights, weight_map
 from .ops import es_adjoint, es_apply, matern_cov_apply, matern_sample, hs_norm_sq
+from .solver import tikhonov_solve
 from . import dense
 
 __all__ = [
     "daubechies_lowpass", "quadrature_highpass",
     "analysis_axis", "synthesis_axis", "dwt", "idwt", "level_weights", "weight_map",
     "es_adjoint", "es_apply", "matern_cov_apply", "matern_sample", "hs_norm_sq",
-    "dense",
+    "tikhonov_solve", "dense",
 ]

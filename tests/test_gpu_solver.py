@@ -1,0 +1,37 @@
+"""GPU: matrix-free Tikhonov reconstruction with the H^s prior (preconditioned CG around the
+wavelet operators) vs the FP64 oracle solution of the normal equations."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2507_02401_amd.solver import tikhonov_pcg
+from tests.gpu_util import rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+# FP32 operator applications carry ~1e-6 relative error; the preconditioned system's condition
+# number is about 1 + 1/alpha (<= 21 here), and CG stops at a residual of 1e-6: 1e-4 covers both.
+SOLVE_TOL = 1e-4
+
+
+@pytest.mark.parametrize("shape,ndim,order,levels,s,alpha", [((2, 64, 96), 2, 4, 4, 1.5, 0.05),
+                                                             ((16, 32, 32), 3, 2, 3, 1.0, 0.1),
+                                                             ((3, 128, 128), 2, 8, 5, 1.0, 0.2)])
+def test_tikhonov_pcg_matches_oracle(shape, ndim, order, levels, s, alpha):
+    gen = np.random.default_rng(31)
+    truth = np.cumsum(np.cumsum(gen.standard_normal(shape), axis=-1), axis=-2) / 8.0
+    mask = (gen.random(shape) < 0.3).astype(np.float32)
+    p = (truth + 0.05 * gen.standard_normal(shape)).astype(np.float32)
+    say("tikhonov_pcg", shape, order, levels, s, alpha)
+    x, info = tikhonov_pcg(torch.from_numpy(p).cuda(), torch.from_numpy(mask).cuda(), ndim, order, levels, s, alpha,
+                           iters=200, rtol=1e-6)
+    x = x.cpu().numpy()
+    assert info["iterations"] < 200 and bool((info["rel_residual"] <= 1e-6).all())
+    xs = x.reshape((-1,) + shape[len(shape) - ndim:])
+    ps = p.reshape(xs.shape)
+    ms = mask.reshape(xs.shape)
+    for b in range(xs.shape[0]):
+        ref = oracle.tikhonov_solve(ps[b].astype(np.float64), ms[b].astype(np.float64), order, levels, s, alpha)
+        err = rel_l2(xs[b], ref)
+        assert err <= SOLVE_TOL, (b, err)

@@ -167,3 +167,27 @@ def test_weight_map_layout():
     assert np.all(w[:2, :2] == 1.0)          # approximation
     assert np.all(w[:4, 2:4] == 1.0) and np.all(w[2:4, :4] == 1.0)  # level 2 (coarsest) details
     assert np.all(w[4:, :] == 0.25) and np.all(w[:, 4:] == 0.25)    # level 1 details: 2^{-2}
+
+
+@pytest.mark.parametrize("shape,order,levels,s,alpha", [((16, 16), 4, 3, 1.5, 0.05), ((8, 8, 8), 2, 2, 1.0, 0.3),
+                                                        ((32,), 8, 3, 2.0, 0.01)])
+def test_tikhonov_solve_matches_dense_direct_solve(shape, order, levels, s, alpha):
+    """The oracle's CG solution of (M + alpha Gamma^2) x = M p equals a dense direct solve, with
+    Gamma^2 built from the dense Kronecker matrices (W^T D_{-2s} W), and is a stationary point
+    of J(x) = 1/2||Mx - p||^2 + alpha/2 ||x||^2_{H^s}."""
+    gen = np.random.default_rng(21)
+    p = gen.standard_normal(shape)
+    mask = (gen.random(shape) < 0.4).astype(np.float64)
+    x = oracle.tikhonov_solve(p, mask, order, levels, s, alpha)
+    G2 = operator_matrices(shape, order, levels, -s)[2]
+    A = np.diag(mask.ravel()) + alpha * G2
+    xd = np.linalg.solve(A, (mask * p).ravel()).reshape(shape)
+    assert np.linalg.norm(x - xd) <= 1e-10 * np.linalg.norm(xd)
+    # gradient of J: M(Mx - p) + alpha Gamma^2 x (the H^s norm's gradient is 2 Gamma^2 x)
+    grad = mask * (mask * x - p) + alpha * matern_cov_apply(x, order, levels, -s)
+    assert np.linalg.norm(grad) <= 1e-10 * np.linalg.norm(mask * p)
+    # and J(x) is below J at random perturbations
+    def J(v):
+        return 0.5 * np.sum((mask * v - p) ** 2) + 0.5 * alpha * oracle.hs_norm_sq(v, order, levels, s)
+    for k in range(3):
+        assert J(x) < J(x + 1e-3 * gen.standard_normal(shape))
