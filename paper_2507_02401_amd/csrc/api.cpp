@@ -1050,12 +1050,63 @@ es_status plan_fill_tables(es_plan* p, const float* const* in, float* const* out
   return ES_OK;
 }
 
+es_status plan_launch_group(es_plan* p, const PlanGroup& gr, hipStream_t s) {
+  const Filter& f = p->filt[gr.proto.L];
+  return run_launch(gr.proto, f, s, gr.proto.is_tail ? nullptr : p->d_tasks + gr.table_off, (int)gr.inst.size(),
+                    gr.total_wg, gr.proto.is_tail ? p->d_tails + gr.table_off : nullptr);
+}
+
+// All groups in order on one stream.
 es_status plan_launch_all(es_plan* p, hipStream_t s) {
   for (const PlanGroup& gr : p->groups) {
-    const Filter& f = p->filt[gr.proto.L];
-    es_status st = run_launch(gr.proto, f, s, gr.proto.is_tail ? nullptr : p->d_tasks + gr.table_off,
-                              (int)gr.inst.size(), gr.total_wg, gr.proto.is_tail ? p->d_tails + gr.table_off : nullptr);
+    es_status st = plan_launch_group(p, gr, s);
     if (st != ES_OK) return st;
+  }
+  return ES_OK;
+}
+
+// Graph capture with concurrent groups: the groups of one phase touch disjoint instances, so they
+// are forked onto `nside` side streams (joined back before the next phase); the captured graph
+// then holds them as parallel branches and the device overlaps their launches.  Events are
+// created here and destroyed by the caller after the capture ends.
+es_status plan_launch_all_forked(es_plan* p, hipStream_t s, hipStream_t* side, int nside,
+                                 std::vector<hipEvent_t>* events) {
+  auto new_event = [&](hipEvent_t* e) -> es_status {
+    ES_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming), "hipEventCreate");
+    events->push_back(*e);
+    return ES_OK;
+  };
+  const size_t n = p->groups.size();
+  for (size_t g = 0; g < n;) {
+    size_t e = g;
+    while (e < n && p->groups[e].phase == p->groups[g].phase) ++e;
+    const int width = (int)std::min<size_t>(e - g, (size_t)nside + 1);
+    if (width == 1) {
+      for (size_t q = g; q < e; ++q) {
+        es_status st = plan_launch_group(p, p->groups[q], s);
+        if (st != ES_OK) return st;
+      }
+      g = e;
+      continue;
+    }
+    hipEvent_t fork;
+    es_status st = new_event(&fork);
+    if (st != ES_OK) return st;
+    ES_HIP(hipEventRecord(fork, s), "hipEventRecord");
+    for (int k = 1; k < width; ++k) ES_HIP(hipStreamWaitEvent(side[k - 1], fork, 0), "hipStreamWaitEvent");
+    for (size_t q = g; q < e; ++q) {
+      const int k = (int)((q - g) % width);
+      st = plan_launch_group(p, p->groups[q], k == 0 ? s : side[k - 1]);
+      if (st != ES_OK) return st;
+    }
+    for (int k = 1; k < width; ++k) {
+      hipEvent_t join;
+      st = new_event(&join);
+      if (st != ES_OK) return st;
+      ES_HIP(hipEventRecord(join, side[k - 1]), "hipEventRecord");
+      ES_HIP(hipStreamWaitEvent(s, join, 0), "hipStreamWaitEvent");
+    }
+    g = e;
   }
   return ES_OK;
 }
@@ -1379,14 +1430,29 @@ es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out,
   if (!p->exec) {
     // kernels read everything through the device tables, so the captured graph stays valid
     // when the caller's pointers change (only the tables are refreshed, above)
-    hipStream_t cap = nullptr;
+    // groups of a phase run as parallel branches, ESWAVE_PLAN_BRANCHES of them at most
+    // (default 4; 1: one chain)
+    constexpr int kSide = 15;
+    hipStream_t cap = nullptr, side[kSide] = {};
     ES_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) { (void)hipStreamDestroy(cap); return dev_fail(e, "hipStreamBeginCapture"); }
-    st = plan_launch_all(p, cap);
+    const char* br = getenv("ESWAVE_PLAN_BRANCHES");
+    const int nside = std::max(0, std::min(kSide, (br && *br ? atoi(br) : 4) - 1));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nside && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
+    std::vector<hipEvent_t> events;
+    auto cleanup = [&]() {
+      for (hipEvent_t ev : events) (void)hipEventDestroy(ev);
+      for (int k = 0; k < kSide; ++k)
+        if (side[k]) (void)hipStreamDestroy(side[k]);
+      (void)hipStreamDestroy(cap);
+    };
+    if (e != hipSuccess) { cleanup(); return dev_fail(e, "hipStreamCreate"); }
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) { cleanup(); return dev_fail(e, "hipStreamBeginCapture"); }
+    st = nside ? plan_launch_all_forked(p, cap, side, nside, &events) : plan_launch_all(p, cap);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cap, &graph);
-    (void)hipStreamDestroy(cap);
+    cleanup();
     if (st != ES_OK) { if (graph) (void)hipGraphDestroy(graph); return st; }
     if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
     hipGraphExec_t exec = nullptr;
