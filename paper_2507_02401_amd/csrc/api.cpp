@@ -271,6 +271,17 @@ double tile_waste(int kind, const Geo& g, int level, int variant) {
 // that a level shared by many instances is tiled for the whole launch, not for one instance.
 thread_local int64_t g_variant_batch = 0;
 
+// Largest block the low-pass coarse kernel takes.  An instance that fits the large LDS class as a
+// whole runs entirely in one work-group (one launch instead of a down level, the coarse kernel and
+// an up level); larger instances hand over at the small class.  The choice depends on the
+// geometry only, never on the batch, so an instance gives the same bits in any batch.
+// ESWAVE_TAIL_MAX overrides (capped at the large class).
+int64_t lp_tail_limit(const Geo& g) {
+  const char* e = getenv("ESWAVE_TAIL_MAX");
+  if (e && *e) return std::min<int64_t>(atoll(e), kCoarseMaxBlockBig);
+  return g.N() <= kCoarseMaxBlockBig ? kCoarseMaxBlockBig : std::min<int64_t>(kTailMax[g.D], kCoarseMaxBlock);
+}
+
 int pick_variant(int kind, const Geo& g, int level, int64_t batch) {
   const int fv = forced_variant();
   if (fv >= 0) return fv;
@@ -482,8 +493,9 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
     // (tail kind 3).  The first low-pass tail kernel (kind 0) stays switched off: a 1-D run of
     // it ended in a GPU memory-aperture fault whose cause has not been found.
     int T = -1;
+    const int64_t limit = lp_tail_limit(g);
     for (int i = 0; i <= m - 2; ++i)
-      if (g.level_size(i) <= std::min<int64_t>(tail_max(D), kCoarseMaxBlock)) { T = i; break; }
+      if (g.level_size(i) <= limit) { T = i; break; }
     const bool tail = T >= 0;
     const int down_to = tail ? T : m - 1;
     for (int i = 1; i <= down_to; ++i) {
@@ -517,7 +529,17 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
       t.batch = (int32_t)batch;
       t.coef[0] = (float)(T == 0 ? w[1] : c[T]);
       for (int j = 1; j <= K; ++j) t.coef[j] = (float)c[T + j];
-      l.lds = 0;  // static LDS
+      l.lds = tail_lds_bytes(3, D, t.b, K);  // selects the kernel's LDS size class
+      // the kernel's LDS layout: pyramid A_0 .. A_K, then the temporaries (2-D: B/2; 3-D: B/2 + B/2)
+      {
+        const int64_t B = g.level_size(T);
+        int64_t need = 0;
+        for (int j = 0; j <= K; ++j) need += B >> (D * j);
+        need += D == 2 ? B / 2 : (D == 3 ? B : 0);
+        const int64_t cap = B <= kCoarseMaxBlock ? kCoarseMaxBlock / 4 * 9 : kCoarseMaxBlockBig / 4 * 9;
+        if (B > kCoarseMaxBlockBig || need > cap)
+          return fail(ES_EUNSUPPORTED, "coarse block of %lld floats needs %lld floats of LDS", (long long)B, (long long)need);
+      }
       sc->launches.push_back(l);
     }
     const int up_from = tail ? T - 1 : m - 2;

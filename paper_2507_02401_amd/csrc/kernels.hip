@@ -1373,7 +1373,7 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
 
 // ---------------------------------------------------------------------------------------
 // LP_COARSE: the coarse levels of the projection form for one instance in one work-group.
-// Input a_T (a contiguous block of at most kCoarseMax floats), output z_T in place (or y when
+// Input a_T (a contiguous block of at most CMAX floats), output z_T in place (or y when
 // T = 0).  Everything between the load and the store stays in a static LDS array addressed by
 // integer offsets: A_0 = a_T, A_1 = a_{T+1}, ..., A_K, then two half-size temporaries.
 //   down:  A_{j+1} = A A_j                       (separable, contiguous axis first)
@@ -1381,8 +1381,10 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
 //   up:    A_j = coef_j A_j + A^T A_{j+1}        (j = K-1 .. 0; coef_0 is the output weight)
 // Axes at least L long wrap with one compare; shorter ones use the modulo (periodic folding).
 
-constexpr int kCoarseMax = kCoarseMaxBlock;
-constexpr int kCoarseLds = kCoarseMax * 2 + kCoarseMax;  // pyramid (<= 2B in 1-D) + temporaries
+// LDS of a block of at most CMAX floats: the pyramid (< 2B in 1-D, < 4B/3 in 2-D, < 8B/7 in 3-D)
+// plus the temporaries (1-D: none; 2-D: B/2; 3-D: B/2 + B/2, the second synthesis pass writes a
+// half block) stay below 9B/4.
+constexpr int coarse_lds_floats(int cmax) { return cmax / 4 * 9; }
 
 // Index decomposition of a flat element index over (o0, o1, o2); shifts when o1, o2 are
 // powers of two (the common case), divisions otherwise.
@@ -1579,9 +1581,9 @@ DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, 
 
 constexpr int kCoarseThreads = 1024;
 
-template <int D, int L>
+template <int D, int L, int CMAX>
 __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Filter f) {
-  __shared__ __attribute__((aligned(16))) float sm[kCoarseLds];
+  __shared__ __attribute__((aligned(16))) float sm[coarse_lds_floats(CMAX)];
   const int wg = logical_wg(args.total_wg);
   if (wg < 0) return;
   int ti = 0;
@@ -1605,7 +1607,7 @@ __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Fil
   int tmpA = 0;
   for (int j = 0; j <= K; ++j) tmpA += B >> (D * j);
   const int tmpB = tmpA + (B >> 1);
-  gather_to_lds<kCoarseThreads, kCoarseMax / kCoarseThreads>(
+  gather_to_lds<kCoarseThreads, CMAX / kCoarseThreads>(
       B, [&](int e) { return gld(in + e); }, [&](int e, float v) { sm[e] = v; });
   __syncthreads();
   int off = 0;
@@ -2181,11 +2183,16 @@ hipError_t launch_k(int ndim, int taps, int variant, bool vec, const TaskArgs& a
 }
 
 template <int D, int L>
-hipError_t launch_tail_dl(int kind, const TailArgs& a, int grid, size_t, const Filter& f, hipStream_t s) {
+hipError_t launch_tail_dl(int kind, const TailArgs& a, int grid, size_t lds, const Filter& f, hipStream_t s) {
   switch (kind) {
     case 1: hipLaunchKernelGGL((k_fb_coarse<D, L, false>), dim3(grid), dim3(kFbCoarseThreads), 0, s, a, f); break;
     case 2: hipLaunchKernelGGL((k_fb_coarse<D, L, true>), dim3(grid), dim3(kFbCoarseThreads), 0, s, a, f); break;
-    case 3: hipLaunchKernelGGL((k_lp_coarse<D, L>), dim3(grid), dim3(kCoarseThreads), 0, s, a, f); break;
+    case 3:
+      if (lds > sizeof(float) * (size_t)coarse_lds_floats(kCoarseMaxBlock))
+        hipLaunchKernelGGL((k_lp_coarse<D, L, kCoarseMaxBlockBig>), dim3(grid), dim3(kCoarseThreads), 0, s, a, f);
+      else
+        hipLaunchKernelGGL((k_lp_coarse<D, L, kCoarseMaxBlock>), dim3(grid), dim3(kCoarseThreads), 0, s, a, f);
+      break;
     default: return hipErrorInvalidValue;  // kind 0 (first low-pass tail) was removed
   }
   return hipGetLastError();
@@ -2266,7 +2273,12 @@ hipError_t launch_tail(int kind, int ndim, int taps, const TailArgs& args, int g
   return hipErrorInvalidValue;
 }
 
-size_t tail_lds_bytes(int, int, const int[3], int) { return 0; }  // the coarse kernels use static LDS
+// LDS the coarse kernels need for a block (static arrays; the low-pass kernel has two sizes, chosen
+// at launch from this value).
+size_t tail_lds_bytes(int kind, int, const int b[3], int) {
+  if (kind != 3) return 0;
+  return sizeof(float) * (size_t)coarse_lds_floats(b[0] * b[1] * b[2]);
+}
 
 hipError_t launch_plain_pass(const PlainPass& p, int taps, const Filter& f, hipStream_t s) {
   switch (taps) {

@@ -111,6 +111,23 @@ def test_validation_before_any_device_call(lib, kw, status, name):
     assert len(lib.es_last_error()) > 0
 
 
+def test_every_schedule_fits_the_coarse_kernels(lib):
+    """Schedules for many geometries build (the host checks each coarse block against the LDS
+    the coarse kernels hold, including the 3-D synthesis temporaries)."""
+    sides = [8, 16, 32, 64, 128, 256, 512]
+    for ndim in (1, 2, 3):
+        for n in sides:
+            shape = (n * (8 if ndim == 1 else 1),) * ndim if ndim > 1 else (n * n,)
+            N = int(np.prod(shape))
+            for levels in range(0, 8):
+                if min(shape) % (1 << levels):
+                    continue
+                for order in (1, 4, 8):
+                    for op in range(4):
+                        r = lib.es_schedule_length(op, ndim, _lib.shape_arg(shape), 2, order, levels)
+                        assert r >= 0, (op, shape, order, levels, lib.es_last_error())
+
+
 def test_norm_workspace_and_validation(lib):
     shp = _lib.shape_arg((64, 96))
     assert lib.es_hs_norm_workspace_bytes(2, shp, 3, 4, 0) == 0  # identity: no workspace
