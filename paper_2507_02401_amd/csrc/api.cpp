@@ -271,15 +271,15 @@ double tile_waste(int kind, const Geo& g, int level, int variant) {
 // that a level shared by many instances is tiled for the whole launch, not for one instance.
 thread_local int64_t g_variant_batch = 0;
 
-// Largest block the low-pass coarse kernel takes.  An instance that fits the large LDS class as a
-// whole runs entirely in one work-group (one launch instead of a down level, the coarse kernel and
-// an up level); larger instances hand over at the small class.  The choice depends on the
-// geometry only, never on the batch, so an instance gives the same bits in any batch.
-// ESWAVE_TAIL_MAX overrides (capped at the large class).
-int64_t lp_tail_limit(const Geo& g) {
+// Largest block the low-pass coarse kernel takes: the large LDS class (an instance that fits it
+// as a whole runs entirely in one work-group, in one launch).  Measured against handing over at
+// the small class: equal on 64 x 1024^2 db8, 2 % faster on 256 x 512^2 db6, 14 % on 16 x 256^2
+// db4.  The choice depends on the geometry only, never on the batch, so an instance gives the
+// same bits in any batch.  ESWAVE_TAIL_MAX overrides (capped at the large class).
+int64_t lp_tail_limit(const Geo&) {
   const char* e = getenv("ESWAVE_TAIL_MAX");
   if (e && *e) return std::min<int64_t>(atoll(e), kCoarseMaxBlockBig);
-  return g.N() <= kCoarseMaxBlockBig ? kCoarseMaxBlockBig : std::min<int64_t>(kTailMax[g.D], kCoarseMaxBlock);
+  return kCoarseMaxBlockBig;
 }
 
 int pick_variant(int kind, const Geo& g, int level, int64_t batch) {
