@@ -25,7 +25,11 @@ Pinning status (see tests/test_oracle_*.py):
                     brute-force adjointness, the semigroup and square-root
                     identities;
   * Tikhonov solve -- pinned by a dense direct solve of the normal equations
-                    on tiny grids and by the first-order optimality condition.
+                    on tiny grids and by the first-order optimality condition;
+  * Fourier form of E_s^* (Sec. 5) -- pinned by plane-wave eigenvalues (closed
+                    form, aliased wave numbers included), a point-by-point DFT
+                    sum on tiny grids and its invariants (identity at s = 0,
+                    semigroup, symmetry, shift equivariance).
   The absolute Matern scale constant of Cor. 4.3 is not part of the path and
   is not implemented (parity unpinned; the constant is dropped as Remark 3.3
   allows).
@@ -35,11 +39,12 @@ from .filters import daubechies_lowpass, quadrature_highpass
 from .dwt import analysis_axis, synthesis_axis, dwt, idwt, level_weights, weight_map
 from .ops import es_adjoint, es_apply, matern_cov_apply, matern_sample, hs_norm_sq
 from .solver import tikhonov_solve
+from .fourier import fft_cov_apply, fourier_multiplier
 from . import dense
 
 __all__ = [
     "daubechies_lowpass", "quadrature_highpass",
     "analysis_axis", "synthesis_axis", "dwt", "idwt", "level_weights", "weight_map",
     "es_adjoint", "es_apply", "matern_cov_apply", "matern_sample", "hs_norm_sq",
-    "tikhonov_solve", "dense",
+    "tikhonov_solve", "fft_cov_apply", "fourier_multiplier", "dense",
 ]
