@@ -117,6 +117,40 @@ es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order
                         const float* x, double* norms, void* ws, size_t ws_bytes, void* stream);
 size_t es_hs_norm_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
 
+/* ---- Fourier form of E_s^* (Sec. 5) ---------------------------------------------------- */
+
+/* y_b = ifft(B . fft(x_b)) for each of `batch` instances: the paper's second realisation of the
+ * adjoint embedding, multiplication of the spectrum by the Bessel potential
+ * B[k] = (1 + 4 pi^2 sum_a (k_a / period)^2)^(-s) (proof of Prop. 3.2; Sec. 5), where the grid samples
+ * a periodic box of side `period` on every axis and k_a in -n_a/2 .. n_a/2 - 1 is the integer
+ * frequency of axis a.  It is a different operator from matern_cov_apply (diagonal in the Fourier
+ * basis, shift-invariant; the two are norm-equivalent on the detail scales), with the same role.
+ * The transforms are hipFFT's (real-to-complex and complex-to-real); the multiplication by B and
+ * the 1/N of the inverse transform are one pass of this library over the half spectrum.
+ *   ndim, shape  1..3 axes, every side in 2..2^30 (any length, not only powers of two); at most
+ *                2^31-1 elements per instance.
+ *   s            finite, any sign (s < 0 multiplies by the inverse potential; |s| must keep
+ *                B within FP32 range).  period: finite, > 0 (1 = unit box).
+ *   x, y         device, batch * prod(shape) floats, 16-byte aligned.  y == x (in place) is
+ *                allowed; other overlaps are not.  When y != x, x is copied into y first (the
+ *                FFT library may overwrite the input of an out-of-place transform): x is never
+ *                written.
+ *   ws           device workspace of es_fft_workspace_bytes(...) bytes, 256-byte aligned, not
+ *                overlapping x or y: the half spectrum (batch * prod(shape[:-1]) * (n_last/2+1)
+ *                complex FP32) followed by hipFFT's work area.
+ * The first call for a geometry and batch (or its workspace query) creates a pair of hipFFT plans
+ * on the current device and caches them; plan creation allocates the library's own device tables,
+ * held until es_fft_release_plans().  Calls are serialised by a lock (plans hold their stream and
+ * work area), so concurrent calls from several threads are safe but do not overlap on the host.
+ * Errors: ES_EINVAL, ES_EWORKSPACE, ES_EUNSUPPORTED (not gfx950), ES_ENOMEM (plan allocation),
+ * ES_EDEVICE (HIP or hipFFT error, named in es_last_error()). */
+es_status es_fft_cov_apply(int ndim, const int64_t* shape, int64_t batch, double s, double period, const float* x,
+                           float* y, void* ws, size_t ws_bytes, void* stream);
+/* Workspace bytes of es_fft_cov_apply for this geometry and batch (creates the plans if needed). */
+es_status es_fft_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, size_t* bytes);
+/* Waits for every device that holds cached plans and destroys them. */
+es_status es_fft_release_plans(void);
+
 /* ---- ragged batches: many geometries in one captured launch sequence ------------------ */
 
 typedef struct {

@@ -33,6 +33,10 @@ SIGNATURES = [
     ("es_workspace_bytes_plain", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("es_hs_norm_sq", ctypes.c_int, _OP_ARGS),
     ("es_hs_norm_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    ("es_fft_cov_apply", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                        _fp, _fp, _fp, ctypes.c_size_t, _fp]),
+    ("es_fft_workspace_bytes", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    ("es_fft_release_plans", ctypes.c_int, []),
     ("es_plan_create", ctypes.c_int, [ctypes.POINTER(EsDesc), ctypes.c_int32, ctypes.c_int, _fp, ctypes.POINTER(ctypes.c_void_p)]),
     ("es_plan_execute", ctypes.c_int, [_fp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _fp, ctypes.c_size_t, _fp]),
     ("es_plan_execute_eager", ctypes.c_int, [_fp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _fp, ctypes.c_size_t, _fp]),

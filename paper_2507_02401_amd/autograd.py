@@ -1,4 +1,4 @@
-"""torch.autograd.Function forms of the four operators and of the squared H^s norm.
+"""torch.autograd.Function forms of the four operators, the squared H^s norm and the Fourier form.
 
 Every operator is linear, so the backward pass is the adjoint applied to the incoming
 gradient: es_adjoint^T = es_apply (synthesis instead of analysis, same level weights),
@@ -71,6 +71,23 @@ class HsNormSqFn(torch.autograd.Function):
         p = ops.matern_cov_apply(x.contiguous(), ndim, order, levels, -s)
         scale = (2.0 * g).to(p.dtype).reshape(g.shape + (1,) * ndim)
         return scale * p, None, None, None, None
+
+
+class FftCovFn(torch.autograd.Function):
+    """Fourier form of E_s^*: real, symmetric (B is real and even), so its backward is itself."""
+
+    @staticmethod
+    def forward(ctx, x, ndim, s, period):
+        ctx.args = (ndim, s, period)
+        return ops.fft_cov_apply(x, ndim, s, period)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ops.fft_cov_apply(g.contiguous(), *ctx.args), None, None, None
+
+
+def fft_cov(x, ndim, s, period=1.0):
+    return FftCovFn.apply(x, ndim, s, period)
 
 
 def hs_norm_sq(x, ndim, order, levels, s):

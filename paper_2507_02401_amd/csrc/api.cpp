@@ -1188,6 +1188,14 @@ es_status plan_prepare(es_plan* p, const float* const* in, float* const* out, vo
 
 }  // namespace
 
+namespace es {
+es_status report_error(es_status st, const char* msg) {
+  g_last_error = msg;
+  return st;
+}
+es_status device_check() { return check_device(); }
+}  // namespace es
+
 // ------------------------------------------------------------------------------------------
 // Exports.
 

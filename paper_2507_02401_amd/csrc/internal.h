@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/eswave.h"
+
 namespace es {
 
 constexpr int kMaxTaps = 16;  // db8
@@ -161,5 +163,10 @@ hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, double* out, h
 
 // Host filter derivation (filters.cpp).
 bool daubechies_filter(int order, double* h_out);
+
+// Host error reporting shared by the exported entry points (api.cpp): sets the thread-local
+// message returned by es_last_error() and returns st; the gfx950 check of the current device.
+es_status report_error(es_status st, const char* msg);
+es_status device_check();
 
 }  // namespace es

@@ -99,6 +99,34 @@ def hs_norm_sq(x, ndim, order, levels, s, workspace=None):
     return out.reshape(x.shape[:x.dim() - ndim])
 
 
+def fft_workspace_bytes(grid, batch):
+    lib = load()
+    n = ctypes.c_size_t(0)
+    check(lib.es_fft_workspace_bytes(len(grid), shape_arg(grid), int(batch), ctypes.byref(n)))
+    return int(n.value)
+
+
+def fft_cov_apply(x, ndim, s, period=1.0, out=None, workspace=None):
+    """y = ifft(B fft(x)) over the last ndim axes, B = (1 + 4 pi^2 |k/period|^2)^(-s): the Fourier form
+    of E_s^* (Sec. 5).  out may be x itself (in place)."""
+    grid, batch = _split(x, ndim)
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of the input's shape")
+    lib = load()
+    shp = shape_arg(grid)
+    with torch.cuda.device(x.device):
+        need = fft_workspace_bytes(grid, batch)
+        ws = _ws(need, x.device, workspace)
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        st = lib.es_fft_cov_apply(ndim, shp, batch, float(s), float(period), x.data_ptr(), out.data_ptr(),
+                                  ws.data_ptr() if ws is not None else None, need, stream)
+    check(st)
+    return out
+
+
 def plain_op(op, x, ndim, order, levels, s, out=None):
     """Reference variant: one launch per 1-D pass per level per instance."""
     grid, batch = _split(x, ndim)
