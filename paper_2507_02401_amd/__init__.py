@@ -7,9 +7,10 @@ Fourier realisation (Sec. 5), ifft(B fft(X)), with hipFFT transforms.
 """
 from ._lib import (OP_ADJOINT, OP_APPLY, OP_COV, OP_SAMPLE, EswaveError, load)
 from .ops import (RaggedPlan, apply_op, autotune, es_adjoint, es_apply, fft_cov_apply, hs_norm_sq, matern_cov_apply,
-                  matern_sample, matern_to_s, plain_op, workspace_bytes)
+                  matern_depth, matern_parameters, matern_sample, matern_to_s, plain_op, workspace_bytes)
 from . import autograd
 
 __all__ = ["autotune", "OP_ADJOINT", "OP_APPLY", "OP_COV", "OP_SAMPLE", "EswaveError", "load", "RaggedPlan", "apply_op",
-           "es_adjoint", "es_apply", "fft_cov_apply", "hs_norm_sq", "matern_cov_apply", "matern_sample", "matern_to_s",
+           "es_adjoint", "es_apply", "fft_cov_apply", "hs_norm_sq", "matern_cov_apply", "matern_depth", "matern_parameters",
+           "matern_sample", "matern_to_s",
            "plain_op", "workspace_bytes", "autograd"]

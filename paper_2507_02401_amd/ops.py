@@ -167,6 +167,28 @@ def matern_to_s(nu, d):
     return nu + d / 2.0
 
 
+def matern_depth(nu, rho, spacing):
+    """Depth m of the wavelet form of the Matern covariance Gamma_{nu, rho} on a grid of the given
+    spacing (Cor. 4.3).  The unweighted (approximation) scale of the wavelet form sits at the
+    correlation scale rho / sqrt(2 nu); detail level i (1 = finest, scale 2^i spacing) is weighted
+    2^{-2s(m-i)}, so the coarsest level m is the one whose scale 2^m * spacing equals it.  The
+    corollary requires rho / sqrt(2 nu) = 2^m on the level scale: a non-integer m raises
+    ValueError.  The overall Matern constant is not applied (Remark 3.3)."""
+    if not (nu > 0 and rho > 0 and spacing > 0):
+        raise ValueError("nu, rho and spacing must be positive")
+    m = math.log2(rho / (math.sqrt(2.0 * nu) * spacing))
+    k = round(m)
+    if abs(m - k) > 1e-9 or k < 0:
+        raise ValueError(f"rho / (sqrt(2 nu) * spacing) = 2^{m:.6g} is not a non-negative power of two")
+    return int(k)
+
+
+def matern_parameters(nu, rho, d, spacing):
+    """(s, levels) of matern_cov_apply / matern_sample for Gamma_{nu, rho} in d dimensions on a grid
+    of the given spacing: s = nu + d/2 (Prop. 3.2), levels from matern_depth (Cor. 4.3)."""
+    return matern_to_s(nu, d), matern_depth(nu, rho, spacing)
+
+
 class RaggedPlan:
     """Many instances of different geometry in one captured launch sequence (es_plan_*).
 
