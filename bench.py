@@ -249,6 +249,36 @@ def other_workloads(args, es, inputs, torch, np):
     # the GPU faulted; the cause was not found, so the case is not run until one is shown.
     out["ragged_200_cov"] = {"skipped": "GPU fault in one run, cause not found; see the ragged-plan notes"}
 
+    # ten mixed geometries (1-, 2- and 3-D, db1..db8, depth 0..7): one captured plan vs the same
+    # plan launched eagerly vs one fused call per instance vs the plain path
+    print("[bench] ragged 10 mixed", file=sys.stderr, flush=True)
+    descs = [((128, 256), 2, 4, 0.5), ((64, 64, 64), 4, 3, 1.0), ((512,), 8, 5, 2.0), ((256, 128), 8, 4, 1.5),
+             ((96, 160), 3, 3, 1.0), ((32, 32, 16), 6, 2, 0.5), ((1024,), 1, 7, 1.0), ((64, 64), 4, 1, 1.0),
+             ((16, 16), 8, 4, 1.0), ((128, 128), 2, 0, 1.0)]
+    gen = np.random.default_rng(2)
+    ins = [torch.from_numpy(gen.standard_normal(sh).astype(np.float32)).to(dev) for sh, _, _, _ in descs]
+    outs = [torch.empty_like(a) for a in ins]
+    plan = es.RaggedPlan(descs, es.OP_COV)
+    nvr = sum(a.numel() for a in ins)
+    tg = _time(lambda: plan(ins, outs, graph=True), torch, reps)
+    te = _time(lambda: plan(ins, outs, graph=False), torch, reps)
+
+    def plain_all():
+        for a, b, (sh, o, m, s_) in zip(ins, outs, descs):
+            es.plain_op(es.OP_COV, a, len(sh), o, m, s_, out=b)
+
+    def single_calls():
+        for a, b, (sh, o, m, s_) in zip(ins, outs, descs):
+            es.matern_cov_apply(a, len(sh), o, m, s_, out=b)
+    tp = _time(plain_all, torch, 3, 1)
+    ts = _time(single_calls, torch, reps)
+    out["ragged_mixed_10_cov"] = {
+        "voxels": nvr, "launches_per_call": plan.num_launches, "graph_us": round(1e6 * tg, 2),
+        "eager_plan_us": round(1e6 * te, 2), "per_instance_fused_calls_us": round(1e6 * ts, 2),
+        "plain_per_instance_us": round(1e6 * tp, 2), "speedup_vs_plain": round(tp / tg, 2)}
+    plan.close()
+    del ins, outs
+
     # 256 x 512^2, db6, 6 levels, s = 1.5: prior sample and its gradient through a masked loss
     print("[bench] 256 x 512^2 sampler", file=sys.stderr, flush=True)
     d = inputs.map_gradient_batch(count=256, side=512)
