@@ -1461,12 +1461,17 @@ es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out,
     // kernels read everything through the device tables, so the captured graph stays valid
     // when the caller's pointers change (only the tables are refreshed, above)
     // groups of a phase run as parallel branches, ESWAVE_PLAN_BRANCHES of them at most
-    // (default 4; 1: one chain)
+    // (default: 4, or 1 -- one chain -- for plans under 2^22 voxels, where the cross-queue
+    // synchronisation of the branches costs more than their overlap gains)
     constexpr int kSide = 15;
+    constexpr int64_t kBranchMinVoxels = 1 << 22;
     hipStream_t cap = nullptr, side[kSide] = {};
     ES_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking), "hipStreamCreate");
     const char* br = getenv("ESWAVE_PLAN_BRANCHES");
-    const int nside = std::max(0, std::min(kSide, (br && *br ? atoi(br) : 4) - 1));
+    int64_t voxels = 0;
+    for (const Geo& g : p->geos) voxels += g.N();
+    const int def_br = voxels < kBranchMinVoxels ? 1 : 4;
+    const int nside = std::max(0, std::min(kSide, (br && *br ? atoi(br) : def_br) - 1));
     hipError_t e = hipSuccess;
     for (int k = 0; k < nside && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
     std::vector<hipEvent_t> events;

@@ -6,7 +6,7 @@ import torch
 import inputs
 import oracle
 import paper_2507_02401_amd as es
-from tests.gpu_util import ORACLE_OPS, OP_NAMES, TOL, rel_l2, say
+from tests.gpu_util import ORACLE_OPS, OP_NAMES, TOL, env, rel_l2, say
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -43,6 +43,32 @@ def test_plan_mixed_vs_oracle(op):
     for k in range(len(MIXED)):
         assert np.array_equal(outs2[k].cpu().numpy(), eager[k])
     plan.close()
+
+
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_plan_branches_equal_chain(op):
+    """The same plan captured as one chain and with each phase's groups forked over four graph
+    branches gives the same bits, replay after replay."""
+    gen = np.random.default_rng(10 + op)
+    ins = [torch.from_numpy(gen.standard_normal(d[0]).astype(np.float32)).to(DEV) for d in MIXED]
+    res = {}
+    for br in ("1", "4"):
+        say("plan branches", OP_NAMES[op], br)
+        with env(ESWAVE_PLAN_BRANCHES=br):
+            plan = es.RaggedPlan(MIXED, op)
+            outs = [torch.empty_like(x) for x in ins]
+            for rep in range(3):
+                plan(ins, outs, graph=True)
+                torch.cuda.synchronize()
+                cur = [y.cpu().numpy() for y in outs]
+                if br in res:
+                    for k in range(len(MIXED)):
+                        assert np.array_equal(cur[k], res[br][k]), (br, rep, k)
+                res[br] = cur
+                _ = (ins[0] * 2).sum().item()
+            plan.close()
+    for k in range(len(MIXED)):
+        assert np.array_equal(res["1"][k], res["4"][k]), k
 
 
 def test_plan_equals_single_calls():
