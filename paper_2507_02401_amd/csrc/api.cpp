@@ -1004,6 +1004,9 @@ struct es_plan {
   bool tables_valid = false;
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
+  // the streams and events used to capture the graph, kept until the graph is destroyed
+  std::vector<hipStream_t> cap_streams;
+  std::vector<hipEvent_t> cap_events;
   std::vector<int> identity_inst;  // instances whose op is the identity (plain copy)
 };
 
@@ -1487,14 +1490,18 @@ es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out,
     st = nside ? plan_launch_all_forked(p, cap, side, nside, &events) : plan_launch_all(p, cap);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cap, &graph);
-    cleanup();
-    if (st != ES_OK) { if (graph) (void)hipGraphDestroy(graph); return st; }
-    if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
+    if (st != ES_OK) { cleanup(); if (graph) (void)hipGraphDestroy(graph); return st; }
+    if (e != hipSuccess) { cleanup(); return dev_fail(e, "hipStreamEndCapture"); }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) { (void)hipGraphDestroy(graph); return dev_fail(e, "hipGraphInstantiate"); }
+    if (e != hipSuccess) { cleanup(); (void)hipGraphDestroy(graph); return dev_fail(e, "hipGraphInstantiate"); }
     p->graph = graph;
     p->exec = exec;
+    // the capture streams and events are released with the graph (es_plan_destroy), not before
+    p->cap_events = events;
+    p->cap_streams.push_back(cap);
+    for (int k = 0; k < kSide; ++k)
+      if (side[k]) p->cap_streams.push_back(side[k]);
   }
   ES_HIP(hipGraphLaunch(p->exec, s), "hipGraphLaunch");
   return ES_OK;
@@ -1510,6 +1517,8 @@ void es_plan_destroy(es_plan* p) {
   if (!p) return;
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
+  for (hipEvent_t ev : p->cap_events) (void)hipEventDestroy(ev);
+  for (hipStream_t s : p->cap_streams) (void)hipStreamDestroy(s);
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   if (p->d_tails) (void)hipFree(p->d_tails);
   delete p;
