@@ -331,6 +331,9 @@ def main():
                     help="also run one 1 GiB device copy (known bytes) for counter calibration")
     ap.add_argument("--fourier-only", action="store_true",
                     help="time only the Fourier form (fft_cov_apply) on the same batch (for profiling) and exit")
+    ap.add_argument("--ragged-seed", type=int, default=None,
+                    help="time only a 200-instance ragged plan drawn with this seed (graph vs eager) and exit; "
+                         "seed 0 is not accepted (that case is kept off the GPU)")
     args = ap.parse_args()
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
@@ -365,6 +368,32 @@ def main():
 
     def step():
         es.matern_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=ws)
+
+    if args.ragged_seed is not None:
+        if args.ragged_seed == 0:
+            print("the seed-0 ragged case is kept off the GPU (a GPU fault with an unknown cause)", file=sys.stderr)
+            sys.exit(2)
+        d = inputs.ragged_batch(count=200, seed=args.ragged_seed)
+        descs = list(d["descs"])
+        ins = [torch.from_numpy(a).to(dev) for a in d["xs"]]
+        outs = [torch.empty_like(a) for a in ins]
+        plan = es.RaggedPlan(descs, es.OP_COV)
+        plan(ins, outs, graph=False)
+        torch.cuda.synchronize()
+        eager = [o.clone() for o in outs]
+        plan(ins, outs, graph=True)
+        torch.cuda.synchronize()
+        same = all(torch.equal(a, b) for a, b in zip(outs, eager))
+        del eager
+        nvr = sum(a.numel() for a in ins)
+        tg = _time(lambda: plan(ins, outs, graph=True), torch, max(3, args.steps))
+        te = _time(lambda: plan(ins, outs, graph=False), torch, max(3, args.steps))
+        print(json.dumps({"workload": f"matern_cov_apply ragged plan: 200 instances, seed {args.ragged_seed}",
+                          "voxels": nvr, "launches_per_call": plan.num_launches, "graph_ms": round(1e3 * tg, 3),
+                          "eager_ms": round(1e3 * te, 3), "voxels_per_s_graph": round(nvr / tg, 1),
+                          "graph_equals_eager": same}), flush=True)
+        plan.close()
+        return
 
     if args.fourier_only:
         from paper_2507_02401_amd.ops import fft_workspace_bytes
