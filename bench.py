@@ -248,10 +248,31 @@ def other_workloads(args, es, inputs, torch, np):
         "plain_pair_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tf, 2)}
     del xv, yv
 
-    # 200 ragged instances: kept off the GPU.  One run of this workload (as a test, on a build
-    # whose tile kernels had a different staging loop and tile decode, since taken out) ended with
-    # the GPU faulted; the cause was not found, so the case is not run until one is shown.
-    out["ragged_200_cov"] = {"skipped": "GPU fault in one run, cause not found; see the ragged-plan notes"}
+    # 200 ragged instances.  The seed-0 draw is kept off the GPU: one run of it (as a test, on a
+    # build whose tile kernels had a different staging loop and tile decode, since taken out) ended
+    # with the GPU faulted and the cause was not found.  The same recipe with seed 1 is timed.
+    out["ragged_200_cov"] = {"skipped": "seed 0: GPU fault in one run, cause not found"}
+    print("[bench] ragged 200 (seed 1)", file=sys.stderr, flush=True)
+    d = inputs.ragged_batch(count=200, seed=1)
+    descs = list(d["descs"])
+    ins = [torch.from_numpy(a).to(dev) for a in d["xs"]]
+    outs = [torch.empty_like(a) for a in ins]
+    plan = es.RaggedPlan(descs, es.OP_COV)
+    nvr = sum(a.numel() for a in ins)
+    tg = _time(lambda: plan(ins, outs, graph=True), torch, reps)
+    te = _time(lambda: plan(ins, outs, graph=False), torch, reps)
+
+    def plain_all200():
+        for a, b, (sh, o, m, s_) in zip(ins, outs, descs):
+            es.plain_op(es.OP_COV, a, len(sh), o, m, s_, out=b)
+    tp = _time(plain_all200, torch, 1, 1)
+    out["ragged_200_seed1_cov"] = {
+        "voxels": nvr, "launches_per_call": plan.num_launches, "graph_ms": round(1e3 * tg, 3),
+        "voxels_per_s_graph": round(nvr / tg, 1), "effective_GBps_graph": round(8 * nvr / tg / 1e9, 1),
+        "eager_plan_ms": round(1e3 * te, 3), "plain_per_instance_ms": round(1e3 * tp, 3),
+        "speedup_vs_plain": round(tp / tg, 2)}
+    plan.close()
+    del ins, outs
 
     # ten mixed geometries (1-, 2- and 3-D, db1..db8, depth 0..7): one captured plan vs the same
     # plan launched eagerly vs one fused call per instance vs the plain path
