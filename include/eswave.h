@@ -184,6 +184,21 @@ size_t es_plan_workspace_bytes(const es_plan* plan);
 int32_t es_plan_num_launches(const es_plan* plan);
 void es_plan_destroy(es_plan* plan);
 
+/* Host-only plan checks (instrumentation; no device call, usable without a GPU).
+ * A plan freezes every instance's launch sequence (kernels, tile variants, tile counts, vector
+ * path, coarse-kernel LDS class) at creation; executions only move the frozen launches' pointers
+ * onto the caller's buffers, and every launch's memory footprint (the block each array is
+ * addressed with, per instance) is checked against those buffers before anything is enqueued.
+ * es_plan_create_host builds the same host-side plan as es_plan_create without device
+ * resources (such a plan cannot be executed; destroy it with es_plan_destroy).
+ * es_plan_fill_host runs the checks and table fill of an execution for the given addresses
+ * (plain integers, never dereferenced): in[i] / out[i] of instance i, ws of ws_bytes bytes.
+ * Returns ES_OK, or ES_EINVAL / ES_EWORKSPACE with the offending instance and step in
+ * es_last_error().  es_plan_work_groups: work-groups one execution launches (after a fill). */
+es_status es_plan_create_host(const es_desc* descs, int32_t count, int op, es_plan** out);
+es_status es_plan_fill_host(es_plan* plan, const uint64_t* in, const uint64_t* out, uint64_t ws, size_t ws_bytes);
+int64_t es_plan_work_groups(const es_plan* plan);
+
 /* ---- autotuning ------------------------------------------------------------------------- */
 
 /* Chooses, for every launch of the operator's launch sequence for this geometry and batch, among

@@ -43,6 +43,10 @@ SIGNATURES = [
     ("es_plan_workspace_bytes", ctypes.c_size_t, [_fp]),
     ("es_plan_num_launches", ctypes.c_int32, [_fp]),
     ("es_plan_destroy", None, [_fp]),
+    ("es_plan_create_host", ctypes.c_int, [ctypes.POINTER(EsDesc), ctypes.c_int32, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)]),
+    ("es_plan_fill_host", ctypes.c_int, [_fp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                         ctypes.c_uint64, ctypes.c_size_t]),
+    ("es_plan_work_groups", ctypes.c_int64, [_fp]),
     ("es_autotune", ctypes.c_int, [ctypes.c_int] + _OP_ARGS[:-1] + [ctypes.c_int32, _fp]),
     ("es_schedule_length", ctypes.c_int32, [ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
     ("es_schedule_describe", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,

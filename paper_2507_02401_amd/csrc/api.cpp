@@ -36,6 +36,7 @@
 
 #include "../../include/eswave.h"
 #include "internal.h"
+#include "tiles.h"
 
 using namespace es;
 
@@ -721,6 +722,148 @@ es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, f
   return st;
 }
 
+// ------------------------------------------------------------------------------------------
+// Footprint check.  Every level kernel reduces its tile indices modulo the level block or
+// guards them against it, and every coarse kernel walks exactly its block, so the memory one
+// launch may touch is, per array, the block that array is addressed with (its own dims and
+// strides) for each instance of the task.  Before anything is enqueued the host checks these
+// ranges against the caller's buffers: a launch that would read outside every buffer, or write
+// outside the writable ones, is rejected with ES_EINVAL instead of reaching the device.
+
+struct Region {
+  uintptr_t lo, hi;  // [lo, hi) bytes
+  bool writable;
+};
+
+struct Access {
+  const void* base;
+  int64_t per_inst;  // bytes between instances
+  int64_t span;      // bytes one instance may touch from base
+  bool write;
+};
+
+// Largest element offset + 1 of a (d0, d1, d2) block addressed with strides (s0, s1, 1).
+int64_t block_span(const int d[3], int64_t s0, int64_t s1) {
+  if (d[0] <= 0 || d[1] <= 0 || d[2] <= 0) return 0;
+  return (int64_t)(d[0] - 1) * s0 + (int64_t)(d[1] - 1) * s1 + d[2];
+}
+int64_t dense_span(const int d[3]) { return (int64_t)d[0] * d[1] * d[2]; }
+void half_of(const int b[3], int D, int h[3]) {
+  for (int k = 0; k < 3; ++k) h[k] = k >= 3 - D ? b[k] / 2 : 1;
+}
+
+void launch_accesses(const Launch& l, std::vector<Access>* acc) {
+  acc->clear();
+  auto add = [&](const void* p, int64_t bs, int64_t span_floats, bool w) {
+    acc->push_back(Access{p, bs * (int64_t)sizeof(float), span_floats * (int64_t)sizeof(float), w});
+  };
+  if (l.is_tail) {
+    const TailTask& t = l.tail;
+    const int64_t B = dense_span(t.b);
+    if (l.kind == 3) {  // low-pass coarse: contiguous block in, contiguous block out
+      add(t.in, t.bs_in, B, false);
+      add(t.out, t.bs_out, B, true);
+    } else if (l.kind == 1) {  // full-bank analysis: contiguous in, strided packed block out
+      add(t.in, t.bs_in, B, false);
+      if (t.flags & kNormSq) acc->push_back(Access{t.out, 0, (int64_t)t.batch * 8, true});
+      else add(t.out, t.bs_out, block_span(t.b, t.st_out[0], t.st_out[1]), true);
+    } else {  // full-bank synthesis: strided packed block in, strided block out
+      add(t.in, t.bs_in, block_span(t.b, t.st_in[0], t.st_in[1]), false);
+      add(t.out, t.bs_out, block_span(t.b, t.st_out[0], t.st_out[1]), true);
+    }
+    return;
+  }
+  const Task& t = l.task;
+  int h[3];
+  half_of(t.b, l.D, h);
+  switch (l.kind) {
+    case K_LP_DOWN:
+    case K_LP_DOWN_S:
+      add(t.in0, t.bs_in0, block_span(t.b, t.st_in0[0], t.st_in0[1]), false);
+      add(t.out0, t.bs_out0, dense_span(h), true);
+      break;
+    case K_LP_UP:
+      add(t.in0, t.bs_in0, dense_span(h), false);
+      add(t.in1, t.bs_in1, dense_span(t.b), false);
+      add(t.out0, t.bs_out0, dense_span(t.b), true);
+      break;
+    case K_LP_UP2: {
+      int q[3];
+      half_of(h, l.D, q);
+      add(t.in0, t.bs_in0, dense_span(q), false);
+      add(t.in1, t.bs_in1, dense_span(h), false);
+      add(t.in2, t.bs_in2, dense_span(t.b), false);
+      add(t.out0, t.bs_out0, dense_span(t.b), true);
+      break;
+    }
+    case K_FB_DOWN:
+    case K_FB_DOWN_S:
+      add(t.in0, t.bs_in0, block_span(t.b, t.st_in0[0], t.st_in0[1]), false);
+      if (t.flags & kNormSq) {  // per-work-group partial sums (doubles) in place of the bands
+        acc->push_back(Access{t.out0, 0, (int64_t)t.tiles_per_inst * t.batch * 8, true});
+        if (!(t.flags & kNormLL)) add(t.out1, t.bs_out1, block_span(h, t.st_out1[0], t.st_out1[1]), true);
+      } else {
+        add(t.out0, t.bs_out0, block_span(t.b, t.st_out0[0], t.st_out0[1]), true);
+        add(t.out1, t.bs_out1, block_span(h, t.st_out1[0], t.st_out1[1]), true);
+      }
+      break;
+    default:  // K_FB_UP, K_FB_UP_S
+      add(t.in0, t.bs_in0, block_span(h, t.st_in0[0], t.st_in0[1]), false);
+      add(t.in1, t.bs_in1, block_span(t.b, t.st_in1[0], t.st_in1[1]), false);
+      add(t.out0, t.bs_out0, block_span(t.b, t.st_out0[0], t.st_out0[1]), true);
+      break;
+  }
+}
+
+// Tile bookkeeping of a level launch: the counts the kernel decodes work-group indices with.
+bool tiles_consistent(const Launch& l) {
+  if (l.is_tail) return l.tail.batch >= 1 && l.tail.nlev >= 1;
+  const Task& t = l.task;
+  for (int k = 0; k < 3; ++k)
+    if (t.ntile[k] < 1 || t.b[k] < 1) return false;
+  return t.batch >= 1 && (int64_t)t.tiles_per_inst == (int64_t)t.ntile[0] * t.ntile[1] * t.ntile[2];
+}
+
+// Checks every access of every instance of one launch against the regions.
+es_status check_launch(const Launch& l, const Region* regions, int nreg, const char* what) {
+  if (!tiles_consistent(l)) return fail(ES_EINVAL, "%s: inconsistent tile counts", what);
+  std::vector<Access> acc;
+  launch_accesses(l, &acc);
+  const int64_t batch = l.is_tail ? l.tail.batch : l.task.batch;
+  for (const Access& a : acc) {
+    if (a.span <= 0) continue;
+    const uintptr_t lo = (uintptr_t)a.base;
+    const uintptr_t hi = lo + (uintptr_t)((batch - 1) * a.per_inst + a.span);
+    bool ok = false;
+    for (int r = 0; r < nreg && !ok; ++r)
+      ok = lo >= regions[r].lo && hi <= regions[r].hi && (!a.write || regions[r].writable);
+    if (!ok)
+      return fail(ES_EINVAL, "%s: a %s of %lld bytes at %p lies outside the caller's %sbuffers", what,
+                  a.write ? "write" : "read", (long long)(hi - lo), a.base, a.write ? "writable " : "");
+  }
+  return ES_OK;
+}
+
+es_status check_schedule(const Schedule& sc, const Region* regions, int nreg) {
+  if (sc.identity) return ES_OK;
+  char what[64];
+  for (size_t j = 0; j < sc.launches.size(); ++j) {
+    snprintf(what, sizeof what, "launch %zu of the schedule", j);
+    es_status st = check_launch(sc.launches[j], regions, nreg, what);
+    if (st != ES_OK) return st;
+  }
+  return ES_OK;
+}
+
+// The regions of a uniform-batch call: input (read), output and workspace (read and write).
+int call_regions(const void* in, const void* out, int64_t bytes, const void* ws, size_t ws_bytes, Region r[3]) {
+  int n = 0;
+  r[n++] = Region{(uintptr_t)in, (uintptr_t)in + (uintptr_t)bytes, false};
+  r[n++] = Region{(uintptr_t)out, (uintptr_t)out + (uintptr_t)bytes, true};
+  if (ws && ws_bytes) r[n++] = Region{(uintptr_t)ws, (uintptr_t)ws + ws_bytes, true};
+  return n;
+}
+
 int64_t round8(int64_t v) { return (v + 7) & ~(int64_t)7; }
 
 es_status run_launch(const Launch& l, const Filter& f, hipStream_t stream, const Task* table, int count,
@@ -832,6 +975,10 @@ es_status run_split(int op, const Geo& g, int64_t batch, int S, const float* in,
     hipStream_t st = k == 0 ? user : ss.s[k];
     Schedule sc;
     es_status r = build_schedule(op, g, nb, in + b0 * N, out + b0 * N, ws ? ws + b0 * wsi : nullptr, &sc);
+    Region reg[3];
+    const int nreg = call_regions(in + b0 * N, out + b0 * N, nb * N * (int64_t)sizeof(float), ws ? ws + b0 * wsi : nullptr,
+                                  (size_t)(nb * wsi) * sizeof(float), reg);
+    if (r == ES_OK) r = check_schedule(sc, reg, nreg);
     if (r == ES_OK) r = run_schedule(sc, g, nb, in + b0 * N, out + b0 * N, st);
     if (r != ES_OK) return r;
   }
@@ -859,6 +1006,10 @@ es_status run_op(int op, int ndim, const int64_t* shape, int64_t batch, int orde
   if (S > 1) return run_split(op, g, batch, S, in, out, (float*)ws, (hipStream_t)stream);
   Schedule sc;
   st = build_schedule(op, g, batch, in, out, (float*)ws, &sc);
+  if (st != ES_OK) return st;
+  Region reg[3];
+  const int nreg = call_regions(in, out, batch * g.N() * (int64_t)sizeof(float), ws, need, reg);
+  st = check_schedule(sc, reg, nreg);
   if (st != ES_OK) return st;
   return run_schedule(sc, g, batch, in, out, (hipStream_t)stream);
 }
@@ -1008,19 +1159,45 @@ struct es_plan {
   std::vector<hipStream_t> cap_streams;
   std::vector<hipEvent_t> cap_events;
   std::vector<int> identity_inst;  // instances whose op is the identity (plain copy)
+  std::vector<std::vector<Launch>> frozen;  // per instance: its schedule at creation (sentinel pointers)
+  bool host_only = false;                   // es_plan_create_host: tables only, no device resources
 };
 
 namespace {
 
-// Schedule of instance `k` with the plan's current pointers.
-es_status instance_schedule(const es_plan* p, int k, const float* in, float* out, void* ws, Schedule* sc) {
+// Plans freeze every instance schedule when they are created: kernel, tile variant, tile
+// counts, vector path and coarse-kernel LDS class are decided once, from the knobs and the
+// tune cache as they are at es_plan_create.  The schedules are built against sentinel base
+// addresses (one range each for the input, the output and the workspace, far apart and never
+// dereferenced); when the caller's pointers change, each table entry is the frozen launch with
+// its pointers moved from the sentinel ranges to the caller's buffers, nothing else.
+constexpr uintptr_t kSentinelIn = (uintptr_t)1 << 44;
+constexpr uintptr_t kSentinelOut = (uintptr_t)2 << 44;
+constexpr uintptr_t kSentinelWs = (uintptr_t)3 << 44;
+constexpr uintptr_t kSentinelSpan = (uintptr_t)1 << 44;
+
+es_status instance_schedule_frozen(const es_plan* p, int k, Schedule* sc) {
   const Geo& g = p->geos[k];
-  float* wsk = ws ? (float*)ws + p->ws_off[k] : (float*)(uintptr_t)256;
   g_variant_batch = (int64_t)p->geos.size();
-  const es_status st = build_schedule(p->op, g, 1, in ? in : (const float*)(uintptr_t)256,
-                                      out ? out : (float*)(uintptr_t)512, wsk, sc);
+  const es_status st = build_schedule(p->op, g, 1, (const float*)kSentinelIn, (float*)kSentinelOut,
+                                      (float*)kSentinelWs + p->ws_off[k], sc);
   g_variant_batch = 0;
   return st;
+}
+
+// Moves one pointer from its sentinel range to the caller's buffer; false if it lies in none.
+template <class T>
+bool rebase(T*& ptr, const float* in, float* out, void* ws) {
+  if (!ptr) return true;
+  const uintptr_t v = (uintptr_t)ptr;
+  const uintptr_t bases[3] = {kSentinelIn, kSentinelOut, kSentinelWs};
+  const uintptr_t real[3] = {(uintptr_t)in, (uintptr_t)out, (uintptr_t)ws};
+  for (int i = 0; i < 3; ++i)
+    if (v >= bases[i] && v < bases[i] + kSentinelSpan) {
+      ptr = (T*)(real[i] + (v - bases[i]));
+      return true;
+    }
+  return false;
 }
 
 // Phase of step j of an instance schedule: down steps get their level index, the tail 1000,
@@ -1042,33 +1219,61 @@ void step_phases(int op, const Geo& g, const Schedule& sc, std::vector<int>* ph)
   }
 }
 
+// A member launch may share a group's kernel only if it is the same instantiation.
+bool same_kernel(const Launch& a, const Launch& proto) {
+  return a.is_tail == proto.is_tail && a.kind == proto.kind && a.D == proto.D && a.L == proto.L &&
+         a.variant == proto.variant && a.vec == proto.vec && (!a.is_tail || a.lds <= proto.lds);
+}
+
 es_status plan_fill_tables(es_plan* p, const float* const* in, float* const* out, void* ws) {
   const int n = (int)p->geos.size();
-  std::vector<Schedule> scs(n);
-  for (int k = 0; k < n; ++k) {
-    es_status st = instance_schedule(p, k, in ? in[k] : nullptr, out ? out[k] : nullptr, ws, &scs[k]);
-    if (st != ES_OK) return st;
-  }
+  Region reg[3];
   for (PlanGroup& gr : p->groups) {
     int64_t wg = 0;
     for (size_t q = 0; q < gr.inst.size(); ++q) {
-      const Launch& l = scs[gr.inst[q]].launches[gr.step[q]];
-      if (gr.proto.is_tail) {
+      const int k = gr.inst[q];
+      if (k < 0 || k >= n || gr.step[q] < 0 || gr.step[q] >= (int)p->frozen[k].size())
+        return fail(ES_EINVAL, "plan table: instance %d step %d is not in its frozen schedule", k, gr.step[q]);
+      Launch l = p->frozen[k][gr.step[q]];
+      if (!same_kernel(l, gr.proto))
+        return fail(ES_EINVAL, "plan table: instance %d step %d does not match its launch group's kernel", k, gr.step[q]);
+      const float* ik = in ? in[k] : nullptr;
+      float* ok = out ? out[k] : nullptr;
+      bool moved = true;
+      if (l.is_tail) {
+        moved = rebase(l.tail.in, ik, ok, ws) && rebase(l.tail.out, ik, ok, ws);
+      } else {
+        moved = rebase(l.task.in0, ik, ok, ws) && rebase(l.task.in1, ik, ok, ws) && rebase(l.task.in2, ik, ok, ws) &&
+                rebase(l.task.out0, ik, ok, ws) && rebase(l.task.out1, ik, ok, ws);
+      }
+      if (!moved) return fail(ES_EINVAL, "plan table: instance %d step %d has a pointer outside its buffers", k, gr.step[q]);
+      if (!l.is_tail) {
+        // the launch's vector path was chosen when the plan was built; every instance must allow it
+        if (l.vec && !vec_ok(l.task, l.kind, p->geos[k]))
+          return fail(ES_EINVAL, "instance %d: pointers not aligned as the plan's vector path requires", k);
+      }
+      // instance k may touch its input, its output and its own slice of the workspace only
+      const int64_t nbytes = p->geos[k].N() * (int64_t)sizeof(float);
+      const int nreg = call_regions(ik, ok, nbytes, ws ? (float*)ws + p->ws_off[k] : nullptr,
+                                    (size_t)ws_floats_per_instance(p->geos[k]) * sizeof(float), reg);
+      char what[64];
+      snprintf(what, sizeof what, "plan instance %d step %d", k, gr.step[q]);
+      es_status st = check_launch(l, reg, nreg, what);
+      if (st != ES_OK) return st;
+      if (l.is_tail) {
         TailTask t = l.tail;
         t.tile_begin = (int32_t)wg;
         t.batch = 1;
         p->h_tails[gr.table_off + q] = t;
         wg += 1;
       } else {
-        // the launch's vector path was chosen when the plan was built; every instance must allow it
-        if (l.vec < gr.proto.vec)
-          return fail(ES_EINVAL, "instance %d: pointers not aligned as the plan's vector path requires", gr.inst[q]);
         Task t = l.task;
         t.tile_begin = (int32_t)wg;
         t.batch = 1;
         p->h_tasks[gr.table_off + q] = t;
         wg += t.tiles_per_inst;
       }
+      if (wg > 0x7fffffffll) return fail(ES_EINVAL, "plan launch group has too many work-groups");
     }
     gr.total_wg = (int)wg;
   }
@@ -1148,8 +1353,69 @@ es_status plan_identity_copies(es_plan* p, const float* const* in, float* const*
   return ES_OK;
 }
 
-es_status plan_prepare(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
-                       hipStream_t s, bool* changed) {
+// Host part of plan creation: geometries, workspace offsets, frozen schedules, launch groups and
+// host tables (no device call).
+es_status plan_build(const es_desc* descs, int32_t count, int op, es_plan** out) {
+  *out = nullptr;
+  if (count < 0 || (count > 0 && !descs)) return fail(ES_EINVAL, "descs must hold count >= 0 entries");
+  if (op < 0 || op > 3) return fail(ES_EINVAL, "unknown op %d", op);
+  es_plan* p = new (std::nothrow) es_plan();
+  if (!p) return fail(ES_ENOMEM, "plan allocation failed");
+  p->op = op;
+  for (int o = 1; o <= 8; ++o)
+    if (!get_filter(2 * o, &p->filt[2 * o])) { delete p; return fail(ES_EUNSUPPORTED, "filter derivation failed"); }
+  p->geos.resize(count);
+  p->ws_off.resize(count);
+  es_status st = ES_OK;
+  for (int k = 0; k < count; ++k) {
+    const es_desc& d = descs[k];
+    st = make_geo(d.ndim, d.shape, d.order, d.levels, d.s, &p->geos[k]);
+    if (st != ES_OK) { delete p; return fail(st, "desc %d: %s", k, g_last_error.c_str()); }
+    p->ws_off[k] = p->ws_total;
+    p->ws_total += ws_floats_per_instance(p->geos[k]);
+  }
+  // freeze every instance schedule, then group steps
+  std::vector<Schedule> scs(count);
+  p->frozen.resize(count);
+  for (int k = 0; k < count; ++k) {
+    st = instance_schedule_frozen(p, k, &scs[k]);
+    if (st != ES_OK) { delete p; return st; }
+    if (scs[k].identity) { p->identity_inst.push_back(k); continue; }
+    p->frozen[k] = scs[k].launches;
+    std::vector<int> ph;
+    step_phases(op, p->geos[k], scs[k], &ph);
+    for (size_t j = 0; j < scs[k].launches.size(); ++j) {
+      const Launch& l = scs[k].launches[j];
+      PlanGroup* gr = nullptr;
+      for (PlanGroup& c : p->groups)
+        if (c.phase == ph[j] && c.proto.is_tail == l.is_tail && c.proto.kind == l.kind && c.proto.D == l.D &&
+            c.proto.L == l.L && c.proto.variant == l.variant && c.proto.vec == l.vec) { gr = &c; break; }
+      if (!gr) {
+        p->groups.push_back(PlanGroup{});
+        gr = &p->groups.back();
+        gr->phase = ph[j];
+        gr->proto = l;
+        gr->proto.lds = 0;
+      }
+      gr->inst.push_back(k);
+      gr->step.push_back((int)j);
+      if (l.is_tail) gr->proto.lds = std::max(gr->proto.lds, l.lds);
+    }
+  }
+  std::stable_sort(p->groups.begin(), p->groups.end(), [](const PlanGroup& a, const PlanGroup& b) { return a.phase < b.phase; });
+  int64_t nt = 0, ntail = 0;
+  for (PlanGroup& gr : p->groups) {
+    if (gr.proto.is_tail) { gr.table_off = ntail; ntail += gr.inst.size(); }
+    else { gr.table_off = nt; nt += gr.inst.size(); }
+  }
+  p->h_tasks.resize(nt);
+  p->h_tails.resize(ntail);
+  *out = p;
+  return ES_OK;
+}
+
+// Host checks of the caller's pointers for one execution (no device call).
+es_status plan_check_io(const es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes) {
   if (!in || !out) return fail(ES_EINVAL, "in and out must be non-NULL host arrays");
   const int n = (int)p->geos.size();
   if (p->ws_total > 0) {
@@ -1165,6 +1431,15 @@ es_status plan_prepare(es_plan* p, const float* const* in, float* const* out, vo
                               overlap(ws, p->ws_total * sizeof(float), out[k], bytes)))
       return fail(ES_EINVAL, "instance %d overlaps the workspace", k);
   }
+  return ES_OK;
+}
+
+es_status plan_prepare(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
+                       hipStream_t s, bool* changed) {
+  if (p->host_only) return fail(ES_EINVAL, "plan was created by es_plan_create_host (no device resources)");
+  es_status st0 = plan_check_io(p, in, out, ws, ws_bytes);
+  if (st0 != ES_OK) return st0;
+  const int n = (int)p->geos.size();
   int dev = 0;
   ES_HIP(hipGetDevice(&dev), "hipGetDevice");
   if (dev != p->device) return fail(ES_EINVAL, "plan was created on device %d, current device is %d", p->device, dev);
@@ -1330,6 +1605,11 @@ es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order
       off += (int64_t)l.task.tiles_per_inst * batch;
     }
   }
+  {
+    const Region reg[2] = {{(uintptr_t)x, (uintptr_t)x + xbytes, false}, {(uintptr_t)ws, (uintptr_t)ws + need, true}};
+    st = check_schedule(sc, reg, 2);
+    if (st != ES_OK) return st;
+  }
   st = run_schedule(sc, g, batch, x, (float*)partials, hs);
   if (st != ES_OK) return st;
   ES_HIP(launch_norm_finalize(partials, segs, norms, batch, hs), "norm finalize launch");
@@ -1380,59 +1660,49 @@ es_status es_plan_create(const es_desc* descs, int32_t count, int op, void* stre
   es_status st = check_device();
   if (st != ES_OK) return st;
   (void)stream;
-  es_plan* p = new (std::nothrow) es_plan();
-  if (!p) return fail(ES_ENOMEM, "plan allocation failed");
-  p->op = op;
-  if (hipGetDevice(&p->device) != hipSuccess) { delete p; return fail(ES_EDEVICE, "hipGetDevice failed"); }
-  for (int o = 1; o <= 8; ++o)
-    if (!get_filter(2 * o, &p->filt[2 * o])) { delete p; return fail(ES_EUNSUPPORTED, "filter derivation failed"); }
-  p->geos.resize(count);
-  p->ws_off.resize(count);
-  for (int k = 0; k < count; ++k) {
-    const es_desc& d = descs[k];
-    st = make_geo(d.ndim, d.shape, d.order, d.levels, d.s, &p->geos[k]);
-    if (st != ES_OK) { delete p; return fail(st, "desc %d: %s", k, g_last_error.c_str()); }
-    p->ws_off[k] = p->ws_total;
-    p->ws_total += ws_floats_per_instance(p->geos[k]);
-  }
-  // group steps
-  std::vector<Schedule> scs(count);
-  for (int k = 0; k < count; ++k) {
-    st = instance_schedule(p, k, nullptr, nullptr, nullptr, &scs[k]);
-    if (st != ES_OK) { delete p; return st; }
-    if (scs[k].identity) { p->identity_inst.push_back(k); continue; }
-    std::vector<int> ph;
-    step_phases(op, p->geos[k], scs[k], &ph);
-    for (size_t j = 0; j < scs[k].launches.size(); ++j) {
-      const Launch& l = scs[k].launches[j];
-      PlanGroup* gr = nullptr;
-      for (PlanGroup& c : p->groups)
-        if (c.phase == ph[j] && c.proto.is_tail == l.is_tail && c.proto.kind == l.kind && c.proto.D == l.D &&
-            c.proto.L == l.L && c.proto.variant == l.variant && c.proto.vec == l.vec) { gr = &c; break; }
-      if (!gr) {
-        p->groups.push_back(PlanGroup{});
-        gr = &p->groups.back();
-        gr->phase = ph[j];
-        gr->proto = l;
-        gr->proto.lds = 0;
-      }
-      gr->inst.push_back(k);
-      gr->step.push_back((int)j);
-      if (l.is_tail) gr->proto.lds = std::max(gr->proto.lds, l.lds);
-    }
-  }
-  std::stable_sort(p->groups.begin(), p->groups.end(), [](const PlanGroup& a, const PlanGroup& b) { return a.phase < b.phase; });
-  int64_t nt = 0, ntail = 0;
-  for (PlanGroup& gr : p->groups) {
-    if (gr.proto.is_tail) { gr.table_off = ntail; ntail += gr.inst.size(); }
-    else { gr.table_off = nt; nt += gr.inst.size(); }
-  }
-  p->h_tasks.resize(nt);
-  p->h_tails.resize(ntail);
+  es_plan* p = nullptr;
+  st = plan_build(descs, count, op, &p);
+  if (st != ES_OK) return st;
+  if (hipGetDevice(&p->device) != hipSuccess) { es_plan_destroy(p); return fail(ES_EDEVICE, "hipGetDevice failed"); }
+  const size_t nt = p->h_tasks.size(), ntail = p->h_tails.size();
   if (nt && hipMalloc(&p->d_tasks, nt * sizeof(Task)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "task table allocation failed"); }
   if (ntail && hipMalloc(&p->d_tails, ntail * sizeof(TailTask)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "tail table allocation failed"); }
   *out = p;
   return ES_OK;
+}
+
+es_status es_plan_create_host(const es_desc* descs, int32_t count, int op, es_plan** out) {
+  if (!out) return fail(ES_EINVAL, "out is NULL");
+  *out = nullptr;
+  es_plan* p = nullptr;
+  es_status st = plan_build(descs, count, op, &p);
+  if (st != ES_OK) return st;
+  p->host_only = true;
+  *out = p;
+  return ES_OK;
+}
+
+es_status es_plan_fill_host(es_plan* p, const uint64_t* in, const uint64_t* out, uint64_t ws, size_t ws_bytes) {
+  if (!p) return fail(ES_EINVAL, "plan is NULL");
+  if (p->geos.empty()) return ES_OK;
+  if (!in || !out) return fail(ES_EINVAL, "in and out must be non-NULL host arrays");
+  const int n = (int)p->geos.size();
+  std::vector<const float*> ip(n);
+  std::vector<float*> op(n);
+  for (int k = 0; k < n; ++k) {
+    ip[k] = (const float*)(uintptr_t)in[k];
+    op[k] = (float*)(uintptr_t)out[k];
+  }
+  es_status st = plan_check_io(p, ip.data(), op.data(), (void*)(uintptr_t)ws, ws_bytes);
+  if (st != ES_OK) return st;
+  return plan_fill_tables(p, ip.data(), op.data(), (void*)(uintptr_t)ws);
+}
+
+int64_t es_plan_work_groups(const es_plan* p) {
+  if (!p) return -1;
+  int64_t n = 0;
+  for (const PlanGroup& gr : p->groups) n += gr.total_wg;
+  return n;
 }
 
 es_status es_plan_execute_eager(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
@@ -1583,6 +1853,10 @@ es_status es_schedule_run_step(int op, int ndim, const int64_t* shape, int64_t b
   st = build_schedule(op, g, batch, in, out, (float*)ws, &sc);
   if (st != ES_OK) return st;
   if (sc.identity || index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
+  Region reg[3];
+  const int nreg = call_regions(in, out, batch * g.N() * (int64_t)sizeof(float), ws, need, reg);
+  st = check_launch(sc.launches[index], reg, nreg, "launch");
+  if (st != ES_OK) return st;
   const Launch& l = sc.launches[index];
   const int64_t total = (l.is_tail ? 1 : l.task.tiles_per_inst) * batch;
   return run_launch(l, sc.f, (hipStream_t)stream, nullptr, 1, (int)total, nullptr);
@@ -1608,6 +1882,13 @@ es_status es_autotune(int op, int ndim, const int64_t* shape, int64_t batch, int
   Schedule sc;
   st = build_schedule_raw(op, g, batch, in, out, (float*)ws, &sc);
   if (st != ES_OK) return st;
+  {
+    // candidates change tiles only, never the blocks a launch addresses
+    Region reg[3];
+    const int nreg = call_regions(in, out, batch * g.N() * (int64_t)sizeof(float), ws, need, reg);
+    st = check_schedule(sc, reg, nreg);
+    if (st != ES_OK) return st;
+  }
   const hipStream_t hs = (hipStream_t)stream;
   // one full pass so that every launch finds valid inputs in the workspace
   st = run_schedule(sc, g, batch, in, out, hs);

@@ -113,15 +113,12 @@ struct TileShape {
   int t[3];  // output tile in the kernel's tiling space (half-res for analysis kinds,
              // full-res for synthesis kinds); padded dims are 1
 };
-TileShape tile_shape(int kind, int ndim, int variant, int taps);
-int tile_threads(int kind, int ndim, int variant);
 
 // Launchers (kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArgs& args, int grid,
                         const Filter& f, hipStream_t stream);
 hipError_t launch_tail(int kind, int ndim, int taps, const TailArgs& args, int grid, size_t lds_bytes,
                        const Filter& f, hipStream_t stream);
-size_t tail_lds_bytes(int kind, int ndim, const int b[3], int nlev);
 // Largest block (floats) the low-pass coarse-level kernel (tail kind 3) holds in LDS: the small
 // instantiation (32 KB of LDS) and the large one (128 KB: one work-group per CU), used when a call
 // has so few instances that its level kernels could not fill the chip anyway.
@@ -129,7 +126,6 @@ constexpr int kCoarseMaxBlock = 4096;
 constexpr int kCoarseMaxBlockBig = 16384;
 // Largest block (floats) the full-bank coarse-level kernels (tail kinds 1, 2) hold in LDS.
 constexpr int kFbCoarseMaxBlock = 8192;
-int tail_threads();
 
 // Plain reference path: one launch per 1-D pass.
 struct PlainPass {

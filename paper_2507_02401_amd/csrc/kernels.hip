@@ -21,6 +21,7 @@
 //
 // Plain kernels: one launch per 1-D pass over the whole level block, for comparison.
 #include "internal.h"
+#include "tiles.h"
 
 namespace es {
 
@@ -1381,10 +1382,6 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
 //   up:    A_j = coef_j A_j + A^T A_{j+1}        (j = K-1 .. 0; coef_0 is the output weight)
 // Axes at least L long wrap with one compare; shorter ones use the modulo (periodic folding).
 
-// LDS of a block of at most CMAX floats: the pyramid (< 2B in 1-D, < 4B/3 in 2-D, < 8B/7 in 3-D)
-// plus the temporaries (1-D: none; 2-D: B/2; 3-D: B/2 + B/2, the second synthesis pass writes a
-// half block) stay below 9B/4.
-constexpr int coarse_lds_floats(int cmax) { return cmax / 4 * 9; }
 
 // Index decomposition of a flat element index over (o0, o1, o2); shifts when o1, o2 are
 // powers of two (the common case), divisions otherwise.
@@ -1579,7 +1576,6 @@ DEVI void coarse_synthesis(float* sm, int src, int dst, int n0, int n1, int n2, 
   else coarse_synthesis_w<L, true>(sm, src, dst, n0, n1, n2, ax, f, combine, alpha);
 }
 
-constexpr int kCoarseThreads = 1024;
 
 template <int D, int L, int CMAX>
 __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Filter f) {
@@ -1669,7 +1665,6 @@ __global__ void __launch_bounds__(kCoarseThreads) k_lp_coarse(TailArgs args, Fil
 // SYN = true: synthesis from the packed block (strided input, weighted) down to a_T.
 
 constexpr int kFbCoarseMax = kFbCoarseMaxBlock;
-constexpr int kFbCoarseThreads = 1024;
 
 template <int L, bool SHORT>
 DEVI void fbc_analysis_w(float* sm, int src, int dst, int S0, int S1, int b0, int b1, int b2, int ax, const Filter& f) {
@@ -2088,41 +2083,6 @@ __global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ x, int6
   store_wg_sum<256>(acc, out + blockIdx.x);
 }
 
-struct Shape3 {
-  int a, b, c;
-};
-constexpr Shape3 shape_of(int K, int D, int V, int L) {
-  // V: 0 wide, 1 narrow, 2 medium
-  if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 32, 64} : Shape3{1, 32, 128});
-  if (K == K_LP_DOWN_S) return V == 0 ? Shape3{1, 64, 256} : (V == 1 ? Shape3{1, 16, 128} : Shape3{1, 32, 256});
-  if (K == K_FB_DOWN_S) return V == 0 ? Shape3{16, 8, 32} : (V == 1 ? Shape3{8, 8, 16} : Shape3{8, 8, 32});
-  if (K == K_FB_UP_S) return V == 0 ? Shape3{16, 16, 32} : (V == 1 ? Shape3{8, 8, 32} : Shape3{8, 16, 32});
-  if (D == 1) {
-    const bool an = (K == K_LP_DOWN || K == K_FB_DOWN);
-    return an ? (V == 0 ? Shape3{1, 1, 256} : (V == 1 ? Shape3{1, 1, 64} : Shape3{1, 1, 128}))
-              : (V == 0 ? Shape3{1, 1, 512} : (V == 1 ? Shape3{1, 1, 128} : Shape3{1, 1, 256}));
-  }
-  if (D == 2) {
-    switch (K) {
-      case K_LP_DOWN: return V == 0 ? Shape3{1, 32, 64} : (V == 1 ? Shape3{1, 8, 16} : Shape3{1, 16, 64});
-      case K_LP_UP: return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 16, 32} : Shape3{1, 32, 128});
-      case K_FB_DOWN: return V == 0 ? Shape3{1, 16, 32} : (V == 1 ? Shape3{1, 8, 16} : Shape3{1, 16, 64});
-      default: return V == 0 ? Shape3{1, 32, 64} : (V == 1 ? Shape3{1, 16, 32} : Shape3{1, 32, 128});
-    }
-  }
-  switch (K) {
-    case K_LP_DOWN:
-      return V == 0 ? (L <= 8 ? Shape3{4, 8, 16} : Shape3{2, 4, 16})
-                    : (V == 1 ? Shape3{2, 4, 8} : (L <= 8 ? Shape3{2, 8, 16} : Shape3{2, 4, 8}));
-    case K_LP_UP: return V == 0 ? Shape3{4, 16, 32} : (V == 1 ? Shape3{4, 8, 16} : Shape3{4, 8, 32});
-    case K_FB_DOWN:
-      return V == 0 ? (L <= 8 ? Shape3{2, 8, 16} : Shape3{2, 4, 8}) : (V == 1 ? Shape3{2, 4, 8} : Shape3{2, 4, 16});
-    default:
-      return V == 0 ? (L <= 8 ? Shape3{4, 16, 16} : Shape3{4, 8, 16})
-                    : (V == 1 ? Shape3{4, 8, 16} : (L <= 8 ? Shape3{4, 8, 32} : Shape3{4, 8, 16}));
-  }
-}
-constexpr int kThreads = 256;
 
 #define ES_TILE(K, D, V, L) shape_of(K, D, V, L).a, shape_of(K, D, V, L).b, shape_of(K, D, V, L).c
 
@@ -2226,18 +2186,6 @@ hipError_t launch_plain_l(const PlainPass& p, const Filter& f, hipStream_t s) {
 
 }  // namespace
 
-TileShape tile_shape(int kind, int ndim, int variant, int taps) {
-  const Shape3 sh = shape_of(kind, ndim, variant, taps);
-  TileShape t;
-  t.t[0] = sh.a;
-  t.t[1] = sh.b;
-  t.t[2] = sh.c;
-  return t;
-}
-
-int tile_threads(int, int, int) { return kThreads; }
-int tail_threads() { return kFbCoarseThreads; }
-
 hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArgs& args, int grid, const Filter& f,
                         hipStream_t stream) {
   // the vector path needs 16-byte rows; the host decides per launch (all tasks agree)
@@ -2271,13 +2219,6 @@ hipError_t launch_tail(int kind, int ndim, int taps, const TailArgs& args, int g
     case 3: return launch_tail_d<3>(kind, taps, args, grid, lds_bytes, f, stream);
   }
   return hipErrorInvalidValue;
-}
-
-// LDS the coarse kernels need for a block (static arrays; the low-pass kernel has two sizes, chosen
-// at launch from this value).
-size_t tail_lds_bytes(int kind, int, const int b[3], int) {
-  if (kind != 3) return 0;
-  return sizeof(float) * (size_t)coarse_lds_floats(b[0] * b[1] * b[2]);
 }
 
 hipError_t launch_plain_pass(const PlainPass& p, int taps, const Filter& f, hipStream_t s) {
