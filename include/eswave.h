@@ -90,6 +90,21 @@ es_status matern_cov_apply(int ndim, const int64_t* shape, int64_t batch, int or
 es_status matern_sample(int ndim, const int64_t* shape, int64_t batch, int order, int levels,
                         double s, const float* xi, float* x, void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of matern_cov_apply, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid allocation): the same
+ * operator, kernels and results, with the workspace taken from a fixed scratch array the library
+ * holds on each device (es_noalloc_scratch_bytes() bytes, 64 MiB, allocated with the library's code
+ * object on that device and kept until the process ends).  Calls no hipMalloc/hipFree and
+ * allocates no device memory.  The caller passes x and y as for matern_cov_apply.
+ * Errors: ES_EWORKSPACE when es_workspace_bytes(ndim, shape, batch, order, levels, ES_OP_COV)
+ * exceeds the scratch size (no work is enqueued); otherwise as matern_cov_apply.
+ * All calls on one device share that device's scratch and leave their level arrays in it: calls
+ * that overlap in time on one device (two streams, two threads) race and give undefined results;
+ * calls ordered on one stream do not. */
+es_status matern_cov_apply_noalloc(int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                                   double s, const float* x, float* y, void* stream);
+size_t es_noalloc_scratch_bytes(void);
+
 /* Workspace bytes the four entry points above need for this geometry and op (es_op). */
 size_t es_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels, int op);
 

@@ -28,6 +28,9 @@ SIGNATURES = [
     ("es_apply", ctypes.c_int, _OP_ARGS),
     ("matern_cov_apply", ctypes.c_int, _OP_ARGS),
     ("matern_sample", ctypes.c_int, _OP_ARGS),
+    ("matern_cov_apply_noalloc", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                                ctypes.c_double, _fp, _fp, _fp]),
+    ("es_noalloc_scratch_bytes", ctypes.c_size_t, []),
     ("es_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     ("es_plain_apply_op", ctypes.c_int, [ctypes.c_int] + _OP_ARGS),
     ("es_workspace_bytes_plain", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int]),

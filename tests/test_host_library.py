@@ -160,3 +160,13 @@ def test_plain_and_plan_validation(lib):
     assert lib.es_plan_create(None, 0, 7, None, ctypes.byref(p)) == _lib.ES_EINVAL
     assert lib.es_plan_workspace_bytes(None) == 0
     lib.es_plan_destroy(None)
+
+
+def test_noalloc_refuses_oversize_on_host(lib):
+    """The allocation-free covariance refuses, before any device call, a geometry whose level
+    arrays exceed the library's scratch (64 x 1024^2 db8, 7 levels: 89 MB > 64 MiB)."""
+    shp = _lib.shape_arg((1024, 1024))
+    need = lib.es_workspace_bytes(2, shp, 64, 8, 7, _lib.OP_COV)
+    assert need > lib.es_noalloc_scratch_bytes() == 64 << 20
+    assert lib.matern_cov_apply_noalloc(2, shp, 64, 8, 7, 1.5, 1 << 20, 1 << 30, None) == _lib.ES_EWORKSPACE
+    assert b"scratch" in lib.es_last_error()
