@@ -132,11 +132,11 @@ es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order
                         const float* x, double* norms, void* ws, size_t ws_bytes, void* stream);
 size_t es_hs_norm_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
 
-/* ---- Fourier form of E_s^* (Sec. 5) ---------------------------------------------------- */
+/* ---- Fourier form of E_s^* (Sec. 4, Implementation) ------------------------------------ */
 
 /* y_b = ifft(B . fft(x_b)) for each of `batch` instances: the paper's second realisation of the
  * adjoint embedding, multiplication of the spectrum by the Bessel potential
- * B[k] = (1 + 4 pi^2 sum_a (k_a / period)^2)^(-s) (proof of Prop. 3.2; Sec. 5), where the grid samples
+ * B[k] = (1 + 4 pi^2 sum_a (k_a / period)^2)^(-s) (proof of Prop. 3.2; Sec. 4, Implementation), where the grid samples
  * a periodic box of side `period` on every axis and k_a in -n_a/2 .. n_a/2 - 1 is the integer
  * frequency of axis a.  It is a different operator from matern_cov_apply (diagonal in the Fourier
  * basis, shift-invariant; the two are norm-equivalent on the detail scales), with the same role.

@@ -26,7 +26,7 @@ Pinning status (see tests/test_oracle_*.py):
                     identities;
   * Tikhonov solve -- pinned by a dense direct solve of the normal equations
                     on tiny grids and by the first-order optimality condition;
-  * Fourier form of E_s^* (Sec. 5) -- pinned by plane-wave eigenvalues (closed
+  * Fourier form of E_s^* (Sec. 4, Implementation) -- pinned by plane-wave eigenvalues (closed
                     form, aliased wave numbers included), a point-by-point DFT
                     sum on tiny grids and its invariants (identity at s = 0,
                     semigroup, symmetry, shift equivariance).

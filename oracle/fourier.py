@@ -1,9 +1,9 @@
-"""FP64 oracle of the Fourier realisation of E_s^* (Sec. 5, the FFT formula).
+"""FP64 oracle of the Fourier realisation of E_s^* (Sec. 4, Implementation: the FFT formula).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The paper characterises E_s^* in the Fourier domain as multiplication by the Bessel potential
-(1 + 4 pi^2 |xi|^2)^(-s) (proof of Prop. 3.2, and Sec. 5 where the discrete operator is written as
+(1 + 4 pi^2 |xi|^2)^(-s) (proof of Prop. 3.2, and Sec. 4 (Implementation) where the discrete operator is written as
 an inverse FFT of B times the FFT of X).  Reading taken here: the grid samples a periodic box of
 side `period` (the same on every axis) at n_k points per axis, the discrete Fourier basis of axis
 k has the integer frequencies k_k = -n_k/2 .. n_k/2 - 1 (numpy's fftfreq order), so the sampled

@@ -3,7 +3,7 @@
 The wavelet realisation of the adjoint Sobolev embedding of arXiv 2507.02401 (Sec. 4):
 E_s^* X = W^{-1}(D (W X)) with W a periodic orthonormal Daubechies DWT and D the
 per-level weights, as hand-written HIP kernels behind a C ABI (include/eswave.h); and its
-Fourier realisation (Sec. 5), ifft(B fft(X)), with hipFFT transforms.
+Fourier realisation (Sec. 4, Implementation), ifft(B fft(X)), with hipFFT transforms.
 """
 from ._lib import (OP_ADJOINT, OP_APPLY, OP_COV, OP_SAMPLE, EswaveError, load)
 from .ops import (RaggedPlan, apply_op, autotune, es_adjoint, es_apply, fft_cov_apply, hs_norm_sq, matern_cov_apply,

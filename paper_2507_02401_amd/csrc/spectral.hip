@@ -1,4 +1,4 @@
-// Fourier realisation of the adjoint embedding (Sec. 5): y = ifft(B . fft(x)) with B the Bessel
+// Fourier realisation of the adjoint embedding (Sec. 4, Implementation): y = ifft(B . fft(x)) with B the Bessel
 // potential (1 + 4 pi^2 |xi|^2)^(-s) sampled on the FFT grid of a periodic box of side `period`.
 //
 // The transforms are hipFFT's (real-to-complex forward, complex-to-real inverse, one plan pair per

@@ -108,7 +108,7 @@ def fft_workspace_bytes(grid, batch):
 
 def fft_cov_apply(x, ndim, s, period=1.0, out=None, workspace=None):
     """y = ifft(B fft(x)) over the last ndim axes, B = (1 + 4 pi^2 |k/period|^2)^(-s): the Fourier form
-    of E_s^* (Sec. 5).  out may be x itself (in place)."""
+    of E_s^* (Sec. 4, Implementation).  out may be x itself (in place)."""
     grid, batch = _split(x, ndim)
     x = x.contiguous()
     if out is None:

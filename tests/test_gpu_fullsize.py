@@ -35,9 +35,14 @@ def test_image_batch_64x1024():
     for b in (0, 37, 63):
         ref = oracle.matern_cov_apply(d["x"][b].astype(np.float64), d["order"], d["levels"], d["s"])
         assert rel_l2(y[b].cpu().numpy(), ref) <= TOL
-    # constant images stay constant; results do not depend on the neighbours in the batch
+    # results do not depend on the neighbours in the batch
     y1 = es.matern_cov_apply(x[37:38].contiguous(), 2, d["order"], d["levels"], d["s"])
     assert torch.equal(y1[0], y[37])
+    # constant images stay constant (a constant lives in the approximation band, weight 1)
+    c = torch.full((2, 1024, 1024), 0.75, dtype=torch.float32, device=DEV)
+    c[1] = -2.5
+    yc = es.matern_cov_apply(c, 2, d["order"], d["levels"], d["s"])
+    assert float((yc - c).abs().max()) <= 1e-5 * 2.5
 
 
 def test_volume_256_autograd():

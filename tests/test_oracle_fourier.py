@@ -1,4 +1,4 @@
-"""Pins of the FP64 Fourier-multiplier oracle (the FFT form of E_s^*, Sec. 5) against closed forms,
+"""Pins of the FP64 Fourier-multiplier oracle (the FFT form of E_s^*, Sec. 4, Implementation) against closed forms,
 brute-force DFT sums and the operator's invariants, and a comparison of its spectrum with the
 wavelet form's (norm equivalence, Sec. 4)."""
 import itertools
