@@ -181,7 +181,20 @@ typedef struct es_plan es_plan;
 
 /* Builds a plan for `count` instances (descs is a host array) of one op.  The plan owns its
  * device descriptor tables and a hipGraph of the whole launch sequence; the graph is
- * instantiated on the first es_plan_execute.  Returns ES_ENOMEM if allocation fails. */
+ * instantiated on the first es_plan_execute.  Returns ES_ENOMEM if allocation fails.
+ *
+ * By default a plan runs phase-merged launches: one launch per level phase and kernel, every
+ * instance of the phase in it.  With the environment variable ESWAVE_PLAN_PERSISTENT=1 at
+ * creation, plans of matern_cov_apply / matern_sample run persistently instead: one kernel
+ * launch per (dimensionality, filter length) present in the plan, the launches running
+ * concurrently as branches of the plan's graph, runs every level tile and coarse block of every
+ * instance (identity instances: copies), each work-group
+ * taking the next work item from a queue in device memory and waiting, with a bounded poll, until
+ * the previous step of the same instance has finished.  The item order interleaves instances so
+ * that coarse levels of one overlap fine levels of others; its pipeline lag and the largest block
+ * the coarse step takes in LDS (coarse fusion depth) are chosen by es_plan_autotune.  Plans whose
+ * level arrays cannot take the vector staging path, and plans of es_adjoint / es_apply, run
+ * phase-merged.  Persistent plans use twice the workspace (every level array written once). */
 es_status es_plan_create(const es_desc* descs, int32_t count, int op, void* stream, es_plan** out);
 
 /* Runs the plan: in[i] / out[i] (host arrays of device pointers) are instance i's input and
@@ -199,6 +212,29 @@ size_t es_plan_workspace_bytes(const es_plan* plan);
 int32_t es_plan_num_launches(const es_plan* plan);
 void es_plan_destroy(es_plan* plan);
 
+/* 1 when the plan runs persistently (see es_plan_create), else 0. */
+int32_t es_plan_is_persistent(const es_plan* plan);
+
+/* After an execution: synchronises `stream` and reads the persistent launches' error words.
+ * ES_EDEVICE when a dependency wait gave up after its poll limit (the results of that execution
+ * are invalid; the kernels still ran to completion); ES_OK otherwise, and for plans that do not
+ * run persistently. */
+es_status es_plan_errors(es_plan* plan, void* stream);
+
+/* Chooses a persistent plan's coarse fusion depth (largest block its coarse step takes: 2048 or
+ * 512 floats) and the pipeline lag of its item order by timing each candidate (eager launches,
+ * HIP events on `stream`, synchronising; fastest of three rounds of `reps` executions) on the
+ * caller's buffers, then rebuilds the plan with the fastest (the captured graph is rebuilt on
+ * the next es_plan_execute).  Leaves a correct result of the last candidate in `out`; a no-op
+ * for plans that do not run persistently.  The coarse fusion depth changes the summation order,
+ * so results of different choices agree to rounding only. */
+es_status es_plan_autotune(es_plan* plan, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
+                           int32_t reps, void* stream);
+
+/* The persistent configuration in use: coarse limit (floats), pipeline lag, work items per
+ * execution (-1 / -1.0 / 0 for plans that do not run persistently). */
+es_status es_plan_config(const es_plan* plan, int64_t* coarse_limit, double* lag, int64_t* items);
+
 /* Host-only plan checks (instrumentation; no device call, usable without a GPU).
  * A plan freezes every instance's launch sequence (kernels, tile variants, tile counts, vector
  * path, coarse-kernel LDS class) at creation; executions only move the frozen launches' pointers
@@ -209,7 +245,8 @@ void es_plan_destroy(es_plan* plan);
  * es_plan_fill_host runs the checks and table fill of an execution for the given addresses
  * (plain integers, never dereferenced): in[i] / out[i] of instance i, ws of ws_bytes bytes.
  * Returns ES_OK, or ES_EINVAL / ES_EWORKSPACE with the offending instance and step in
- * es_last_error().  es_plan_work_groups: work-groups one execution launches (after a fill). */
+ * es_last_error().  es_plan_work_groups: work-groups (phase-merged plans) or work items
+ * (persistent plans) of one execution, after a fill. */
 es_status es_plan_create_host(const es_desc* descs, int32_t count, int op, es_plan** out);
 es_status es_plan_fill_host(es_plan* plan, const uint64_t* in, const uint64_t* out, uint64_t ws, size_t ws_bytes);
 int64_t es_plan_work_groups(const es_plan* plan);

@@ -50,6 +50,12 @@ SIGNATURES = [
     ("es_plan_fill_host", ctypes.c_int, [_fp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
                                          ctypes.c_uint64, ctypes.c_size_t]),
     ("es_plan_work_groups", ctypes.c_int64, [_fp]),
+    ("es_plan_is_persistent", ctypes.c_int32, [_fp]),
+    ("es_plan_errors", ctypes.c_int, [_fp, _fp]),
+    ("es_plan_autotune", ctypes.c_int, [_fp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _fp,
+                                        ctypes.c_size_t, ctypes.c_int32, _fp]),
+    ("es_plan_config", ctypes.c_int, [_fp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(ctypes.c_int64)]),
     ("es_autotune", ctypes.c_int, [ctypes.c_int] + _OP_ARGS[:-1] + [ctypes.c_int32, _fp]),
     ("es_schedule_length", ctypes.c_int32, [ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
     ("es_schedule_describe", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,

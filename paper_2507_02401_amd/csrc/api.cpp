@@ -170,12 +170,24 @@ double wdet(const Geo& g, double tau, int i) { return std::exp2(-tau * g.s * (do
 
 int64_t align64(int64_t v) { return (v + 63) & ~(int64_t)63; }
 
-// Workspace: level arrays a_1 .. a_m of one instance, each 256-byte aligned.
-int64_t ws_floats_per_instance(const Geo& g) {
+// Schedule mode of persistent plans (set around their schedule builds): every level launch uses
+// the persistent kernel's tile variant and plain tiles, the coarse blocks fit the small LDS class
+// of the coarse body, and every level array is written once (z_i gets its own array instead of
+// overwriting a_i), so that no cache can hold a line of it from before it was written.
+struct SchedMode {
+  bool persist = false;
+  int64_t coarse_limit = kCoarseMaxBlock;
+};
+thread_local SchedMode g_mode;
+
+// Workspace: level arrays a_1 .. a_m of one instance, each 256-byte aligned (persistent plans:
+// then z_1 .. z_m in a second region of the same size).
+int64_t ws_floats_levels(const Geo& g) {
   int64_t tot = 0;
   for (int i = 1; i <= g.m; ++i) tot += align64(g.level_size(i));
   return tot;
 }
+int64_t ws_floats_per_instance(const Geo& g) { return (g_mode.persist ? 2 : 1) * ws_floats_levels(g); }
 int64_t ws_level_offset(const Geo& g, int i) {  // offset of a_i (i >= 1)
   int64_t off = 0;
   for (int j = 1; j < i; ++j) off += align64(g.level_size(j));
@@ -198,6 +210,7 @@ int64_t tail_max(int D) {
   return kTailMax[D];
 }
 bool fuse_up2() {  // measured slower than two launches on 64 x 1024^2 db8: opt-in
+  if (g_mode.persist) return false;
   const char* e = getenv("ESWAVE_FUSE_UP2");
   return e && *e == '1';
 }
@@ -278,12 +291,14 @@ thread_local int64_t g_variant_batch = 0;
 // db4.  The choice depends on the geometry only, never on the batch, so an instance gives the
 // same bits in any batch.  ESWAVE_TAIL_MAX overrides (capped at the large class).
 int64_t lp_tail_limit(const Geo&) {
+  if (g_mode.persist) return std::min<int64_t>(g_mode.coarse_limit, kPCoarseMax);
   const char* e = getenv("ESWAVE_TAIL_MAX");
   if (e && *e) return std::min<int64_t>(atoll(e), kCoarseMaxBlockBig);
   return kCoarseMaxBlockBig;
 }
 
 int pick_variant(int kind, const Geo& g, int level, int64_t batch) {
+  if (g_mode.persist) return kPVariant;
   const int fv = forced_variant();
   if (fv >= 0) return fv;
   if (g_variant_batch > batch) batch = g_variant_batch;
@@ -337,7 +352,7 @@ int tiled_kind(int kind) {
 
 Launch level_launch(int kind, const Geo& g, int level, int64_t batch) {
   const int mode = streamed_mode();
-  if (has_family(kind, g.D) && mode != 0) {
+  if (has_family(kind, g.D) && mode != 0 && !g_mode.persist) {
     const int sk = streamed_kind(kind);
     Task t{};
     set_tiles(t, sk, g, level, pick_variant(sk, g, level, batch), batch);
@@ -479,6 +494,8 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
   int32_t st_full[2];
   strides_of(full, st_full);
   auto lvl_ptr = [&](int i) -> float* { return ws + ws_level_offset(g, i); };
+  // z_i: in place of a_i, or (persistent plans) in the second region
+  auto zlvl_ptr = [&](int i) -> float* { return (g_mode.persist ? ws + ws_floats_levels(g) : ws) + ws_level_offset(g, i); };
   auto lvl_dims = [&](int i, int d[3]) { g.level_dims(i, d); };
 
   if (op == ES_OP_COV || op == ES_OP_SAMPLE) {
@@ -523,7 +540,7 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
       const int K = m - 1 - T;
       t.in = T == 0 ? in : lvl_ptr(T);
       t.bs_in = T == 0 ? N : wsi;
-      t.out = T == 0 ? out : lvl_ptr(T);
+      t.out = T == 0 ? out : zlvl_ptr(T);
       t.bs_out = T == 0 ? N : wsi;
       lvl_dims(T, t.b);
       t.nlev = K;
@@ -552,12 +569,13 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
       int d_z[3], d_o[3];
       lvl_dims(i + 1, d_z);
       lvl_dims(i, d_o);
-      l.task.in0 = lvl_ptr(i + 1);
+      // without a coarse step the first up level reads a_{m-1} itself (beta = c_{m-1})
+      l.task.in0 = (!tail && i + 1 == m - 1) ? lvl_ptr(i + 1) : zlvl_ptr(i + 1);
       l.task.bs_in0 = wsi;
       strides_of(d_z, l.task.st_in0);
       l.task.in1 = i == 0 ? in : lvl_ptr(i);
       l.task.bs_in1 = i == 0 ? N : wsi;
-      l.task.out0 = i == 0 ? out : lvl_ptr(i);
+      l.task.out0 = i == 0 ? out : zlvl_ptr(i);
       l.task.bs_out0 = i == 0 ? N : wsi;
       strides_of(d_o, l.task.st_in1);
       strides_of(d_o, l.task.st_out0);
@@ -718,7 +736,7 @@ es_status build_schedule_raw(int op, const Geo& g, int64_t batch, const float* i
 es_status build_schedule(int op, const Geo& g, int64_t batch, const float* in, float* out, float* ws,
                          Schedule* sc) {
   es_status st = build_schedule_raw(op, g, batch, in, out, ws, sc);
-  if (st == ES_OK && !sc->identity) apply_tuned(sc, op, g, batch);
+  if (st == ES_OK && !sc->identity && !g_mode.persist) apply_tuned(sc, op, g, batch);
   return st;
 }
 
@@ -1141,6 +1159,7 @@ struct es_plan {
   int device = 0;
   std::vector<Geo> geos;
   std::vector<int64_t> ws_off;
+  std::vector<int64_t> ws_len;  // floats of each instance's workspace slice
   int64_t ws_total = 0;
   std::vector<std::vector<int>> phase_of;  // per instance: phase of each schedule step
   std::vector<PlanGroup> groups;
@@ -1161,6 +1180,26 @@ struct es_plan {
   std::vector<int> identity_inst;  // instances whose op is the identity (plain copy)
   std::vector<std::vector<Launch>> frozen;  // per instance: its schedule at creation (sentinel pointers)
   bool host_only = false;                   // es_plan_create_host: tables only, no device resources
+  // persistent execution (cov / sample): one launch per dimensionality over a work-item queue
+  bool persistent = false;
+  double lag = 1.0;                 // pipeline lag scale of the item order
+  int64_t coarse_limit = kPCoarseMax;
+  int spin_limit = 1 << 16;  // polls of one dependency wait (of the order of 0.1 s)
+  int nq = kPMaxQueues;      // queues of a persistent launch: the device's XCDs
+  int chunk = 4;             // tiles per work item of large steps
+  struct PGroup {  // one persistent launch: the instances of one (dimensionality, taps)
+    int D = 0;
+    int L = 0;
+    std::vector<PStep> h_steps;     // frozen steps (sentinel pointers)
+    std::vector<PStep> cur_steps;   // steps with the caller's pointers
+    std::vector<PItem> h_items;     // execution order, queue after queue
+    std::vector<int32_t> qbegin;    // queue q: items [qbegin[q], qbegin[q + 1])
+    PStep* d_steps = nullptr;
+    PItem* d_items = nullptr;
+    int32_t* d_ctr = nullptr;
+    int grid = 0;
+  };
+  std::vector<PGroup> pgroups;
 };
 
 namespace {
@@ -1255,7 +1294,7 @@ es_status plan_fill_tables(es_plan* p, const float* const* in, float* const* out
       // instance k may touch its input, its output and its own slice of the workspace only
       const int64_t nbytes = p->geos[k].N() * (int64_t)sizeof(float);
       const int nreg = call_regions(ik, ok, nbytes, ws ? (float*)ws + p->ws_off[k] : nullptr,
-                                    (size_t)ws_floats_per_instance(p->geos[k]) * sizeof(float), reg);
+                                    (size_t)p->ws_len[k] * sizeof(float), reg);
       char what[64];
       snprintf(what, sizeof what, "plan instance %d step %d", k, gr.step[q]);
       es_status st = check_launch(l, reg, nreg, what);
@@ -1353,6 +1392,227 @@ es_status plan_identity_copies(es_plan* p, const float* const* in, float* const*
   return ES_OK;
 }
 
+// ---- persistent plans -------------------------------------------------------------------
+
+// Persistent execution (ESWAVE_PLAN_PERSISTENT=1 at plan creation) is available for plans of the
+// projection-form operators whose level launches all take the vector staging path.  It is not
+// the default: measured on 64 x 1024^2 db8 (0.54 ms against 0.35 ms phase-merged and 0.27 ms
+// for one uniform call) and on 200 ragged instances (1.51 against 0.98 ms), its work-groups run
+// at 4 per CU (the union of tile bodies holds 128 registers) where the level kernels run 6 to 8,
+// and every work item pays a queue pop and a dependency poll.
+bool persistent_wanted(int op) {
+  if (op != ES_OP_COV && op != ES_OP_SAMPLE) return false;
+  const char* e = getenv("ESWAVE_PLAN_PERSISTENT");
+  return e && *e == '1';
+}
+
+// Cost model of the item order: the bytes a step moves (its footprint) and the latency between
+// its last item being taken and its completion (a tile's duration; a coarse block's serial work).
+double step_bytes(const Launch& l) {
+  std::vector<Access> acc;
+  launch_accesses(l, &acc);
+  double b = 0;
+  for (const Access& a : acc) b += (double)a.span;
+  return b;
+}
+double step_latency_us(const Launch& l) {
+  if (!l.is_tail) return 6.0;
+  const double B = (double)dense_span(l.tail.b);
+  return 4.0 + B * l.L / 8000.0;
+}
+
+// Builds the persistent step tables of a plan from its frozen schedules, and the item order:
+// a list-scheduling simulation of the device (throughput kRate bytes/us) in which an instance's
+// next step becomes ready `lag` x its predecessor's latency after that predecessor was issued;
+// at each point the oldest started instance with a ready step is issued, else a new instance is
+// started.  lag -> 0 gives instance after instance, a large lag gives level after level.
+// Every instance's steps appear in order, so each step's dependency precedes it in the list.
+void persistent_tables(es_plan* p) {
+  constexpr double kRate = 5000.0;  // bytes per microsecond
+  p->pgroups.clear();
+  const int n = (int)p->geos.size();
+  for (int D = 1; D <= 3; ++D)
+  for (int L = 2; L <= kMaxTaps; L += 2) {
+    es_plan::PGroup G;
+    G.D = D;
+    G.L = L;
+    std::vector<int> inst;
+    for (int k = 0; k < n; ++k)
+      if (p->geos[k].D == D && p->geos[k].L == L) inst.push_back(k);
+    if (inst.empty()) continue;
+    // steps, instance by instance
+    std::vector<int> first(inst.size()), count(inst.size());
+    std::vector<double> bytes, lat;
+    for (size_t q = 0; q < inst.size(); ++q) {
+      const int k = inst[q];
+      first[q] = (int)G.h_steps.size();
+      const Geo& g = p->geos[k];
+      if (p->frozen[k].empty()) {  // identity: a copy of the input
+        PStep st{};
+        st.kind = P_COPY;
+        st.L = g.L;
+        st.wait = -1;
+        st.inst = k;
+        st.task.in0 = (const float*)kSentinelIn;
+        st.task.out0 = (float*)kSentinelOut;
+        st.task.bs_in0 = g.N();
+        st.ntiles = (int)((g.N() + kPCopyChunk - 1) / kPCopyChunk);
+        G.h_steps.push_back(st);
+        bytes.push_back(8.0 * (double)g.N());
+        lat.push_back(2.0);
+      } else {
+        for (const Launch& l : p->frozen[k]) {
+          PStep st{};
+          st.inst = k;
+          st.L = l.L;
+          if (l.is_tail) {
+            st.kind = P_COARSE;
+            st.tail = l.tail;
+            st.tail.batch = 1;
+            st.tail.tile_begin = 0;
+            st.ntiles = 1;
+          } else {
+            st.kind = kind_is_analysis(l.kind) ? P_LP_DOWN : P_LP_UP;
+            st.task = l.task;
+            st.task.batch = 1;
+            st.task.tile_begin = 0;
+            st.ntiles = l.task.tiles_per_inst;
+          }
+          const int idx = (int)G.h_steps.size();
+          st.wait = idx > first[q] ? idx - 1 : -1;
+          st.wait_count = st.wait >= 0 ? G.h_steps[st.wait].ntiles : 0;
+          G.h_steps.push_back(st);
+          bytes.push_back(step_bytes(l));
+          lat.push_back(step_latency_us(l));
+        }
+      }
+      count[q] = (int)G.h_steps.size() - first[q];
+    }
+    // instances to queues (one per XCD): longest first onto the least loaded queue
+    const int ni = (int)inst.size();
+    const int nq = std::max(1, std::min(p->nq, kPMaxQueues));
+    std::vector<double> work(ni, 0.0), load(nq, 0.0);
+    for (int q = 0; q < ni; ++q)
+      for (int j = first[q]; j < first[q] + count[q]; ++j) work[q] += bytes[j];
+    std::vector<int> by_work(ni), queue_of(ni);
+    for (int q = 0; q < ni; ++q) by_work[q] = q;
+    std::stable_sort(by_work.begin(), by_work.end(), [&](int a, int b) { return work[a] > work[b]; });
+    for (int q : by_work) {
+      const int best = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      queue_of[q] = best;
+      load[best] += work[q];
+    }
+    // item order of each queue: the queue's XCD (throughput kRate / nq) simulated as above
+    G.qbegin.assign(nq + 1, 0);
+    for (int Q = 0; Q < nq; ++Q) {
+      G.qbegin[Q] = (int32_t)G.h_items.size();
+      std::vector<int> mine;
+      for (int q = 0; q < ni; ++q)
+        if (queue_of[q] == Q) mine.push_back(q);
+      const int nm = (int)mine.size();
+      std::vector<int> next(nm, 0);
+      std::vector<double> ready(nm, 0.0);
+      int started = 0, finished = 0;
+      double t = 0;
+      while (finished < nm) {
+        int pick = -1;
+        for (int r = 0; r < started; ++r)
+          if (next[r] < count[mine[r]] && ready[r] <= t) { pick = r; break; }
+        if (pick < 0) {
+          if (started < nm) {
+            pick = started++;
+          } else {
+            double tmin = 1e300;
+            for (int r = 0; r < started; ++r)
+              if (next[r] < count[mine[r]]) tmin = std::min(tmin, ready[r]);
+            t = tmin;
+            continue;
+          }
+        }
+        const int q = mine[pick];
+        const int j = first[q] + next[pick];
+        // consecutive tiles share filter halos: larger steps hand out a few per item
+        const int nt = G.h_steps[j].ntiles;
+        const int chunk = G.h_steps[j].kind == P_COPY ? 1 : (nt >= 64 ? p->chunk : (nt >= 16 ? std::min(2, p->chunk) : 1));
+        for (int tile = 0; tile < nt; tile += chunk) G.h_items.push_back(PItem{j, tile, std::min(chunk, nt - tile), 0});
+        t += bytes[j] / (kRate / nq);
+        ready[pick] = t + p->lag * lat[j];
+        if (++next[pick] == count[q]) ++finished;
+      }
+    }
+    G.qbegin[nq] = (int32_t)G.h_items.size();
+    G.cur_steps = G.h_steps;
+    p->pgroups.push_back(std::move(G));
+  }
+}
+
+// Fills the persistent step tables for the caller's pointers, checking every step's footprint
+// against the instance's buffers.
+es_status persistent_fill(es_plan* p, const float* const* in, float* const* out, void* ws) {
+  Region reg[3];
+  for (es_plan::PGroup& G : p->pgroups) {
+    for (size_t j = 0; j < G.h_steps.size(); ++j) {
+      PStep st = G.h_steps[j];
+      const int k = st.inst;
+      const float* ik = in ? in[k] : nullptr;
+      float* ok = out ? out[k] : nullptr;
+      bool moved = true;
+      if (st.kind == P_COARSE) {
+        moved = rebase(st.tail.in, ik, ok, ws) && rebase(st.tail.out, ik, ok, ws);
+      } else {
+        moved = rebase(st.task.in0, ik, ok, ws) && rebase(st.task.in1, ik, ok, ws) &&
+                rebase(st.task.in2, ik, ok, ws) && rebase(st.task.out0, ik, ok, ws) &&
+                rebase(st.task.out1, ik, ok, ws);
+      }
+      if (!moved) return fail(ES_EINVAL, "plan instance %d: a step has a pointer outside its buffers", k);
+      const int64_t nbytes = p->geos[k].N() * (int64_t)sizeof(float);
+      const int nreg = call_regions(ik, ok, nbytes, ws ? (float*)ws + p->ws_off[k] : nullptr,
+                                    (size_t)p->ws_len[k] * sizeof(float), reg);
+      char what[64];
+      snprintf(what, sizeof what, "plan instance %d step %zu", k, j);
+      if (st.kind == P_COPY) {
+        const Access a{st.task.in0, 0, st.task.bs_in0 * 4, false}, b{st.task.out0, 0, st.task.bs_in0 * 4, true};
+        for (const Access& x : {a, b}) {
+          bool fits = false;
+          for (int r = 0; r < nreg && !fits; ++r)
+            fits = (uintptr_t)x.base >= reg[r].lo && (uintptr_t)x.base + x.span <= reg[r].hi && (!x.write || reg[r].writable);
+          if (!fits) return fail(ES_EINVAL, "%s: copy outside the caller's buffers", what);
+        }
+      } else {
+        Launch l{};
+        l.is_tail = st.kind == P_COARSE;
+        l.kind = l.is_tail ? 3 : (st.kind == P_LP_DOWN ? K_LP_DOWN : K_LP_UP);
+        l.D = G.D;
+        l.L = st.L;
+        l.task = st.task;
+        l.tail = st.tail;
+        if (!l.is_tail && !vec_ok(l.task, l.kind, p->geos[k]))
+          return fail(ES_EINVAL, "instance %d: pointers not aligned as the plan's vector path requires", k);
+        es_status e = check_launch(l, reg, nreg, what);
+        if (e != ES_OK) return e;
+      }
+      G.cur_steps[j] = st;
+    }
+  }
+  return ES_OK;
+}
+
+// Workspace slice of every instance (persistent plans: write-once level arrays, twice the size).
+void plan_layout(es_plan* p, bool persist) {
+  const int n = (int)p->geos.size();
+  p->ws_off.assign(n, 0);
+  p->ws_len.assign(n, 0);
+  p->ws_total = 0;
+  const SchedMode keep = g_mode;
+  g_mode.persist = persist;
+  for (int k = 0; k < n; ++k) {
+    p->ws_off[k] = p->ws_total;
+    p->ws_len[k] = ws_floats_per_instance(p->geos[k]);
+    p->ws_total += p->ws_len[k];
+  }
+  g_mode = keep;
+}
+
 // Host part of plan creation: geometries, workspace offsets, frozen schedules, launch groups and
 // host tables (no device call).
 es_status plan_build(const es_desc* descs, int32_t count, int op, es_plan** out) {
@@ -1365,18 +1625,46 @@ es_status plan_build(const es_desc* descs, int32_t count, int op, es_plan** out)
   for (int o = 1; o <= 8; ++o)
     if (!get_filter(2 * o, &p->filt[2 * o])) { delete p; return fail(ES_EUNSUPPORTED, "filter derivation failed"); }
   p->geos.resize(count);
-  p->ws_off.resize(count);
   es_status st = ES_OK;
   for (int k = 0; k < count; ++k) {
     const es_desc& d = descs[k];
     st = make_geo(d.ndim, d.shape, d.order, d.levels, d.s, &p->geos[k]);
     if (st != ES_OK) { delete p; return fail(st, "desc %d: %s", k, g_last_error.c_str()); }
-    p->ws_off[k] = p->ws_total;
-    p->ws_total += ws_floats_per_instance(p->geos[k]);
   }
-  // freeze every instance schedule, then group steps
+  plan_layout(p, persistent_wanted(op));
+  // freeze every instance schedule: for persistent execution when every level launch can take
+  // the persistent kernel's (vector) path, else for phase-merged launches
   std::vector<Schedule> scs(count);
   p->frozen.resize(count);
+  p->persistent = persistent_wanted(op);
+  if (p->persistent) {
+    const char* e = getenv("ESWAVE_PLAN_COARSE_MAX");
+    if (e && *e) p->coarse_limit = std::max<int64_t>(0, std::min<int64_t>(atoll(e), kPCoarseMax));
+    const char* lg = getenv("ESWAVE_PLAN_LAG");
+    if (lg && *lg) p->lag = std::max(0.0, atof(lg));
+    const char* sp = getenv("ESWAVE_PERSIST_SPIN");
+    if (sp && *sp) p->spin_limit = atoi(sp);
+    const char* ch = getenv("ESWAVE_PLAN_CHUNK");
+    if (ch && *ch) p->chunk = std::max(1, std::min(64, atoi(ch)));
+    g_mode.persist = true;
+    g_mode.coarse_limit = p->coarse_limit;
+    for (int k = 0; k < count && p->persistent; ++k) {
+      st = instance_schedule_frozen(p, k, &scs[k]);
+      if (st != ES_OK) break;
+      for (const Launch& l : scs[k].launches)
+        if (!l.is_tail && !l.vec) p->persistent = false;
+    }
+    g_mode = SchedMode{};
+    if (st != ES_OK) { delete p; return st; }
+    if (p->persistent) {
+      for (int k = 0; k < count; ++k)
+        if (!scs[k].identity) p->frozen[k] = scs[k].launches;
+      persistent_tables(p);
+      *out = p;
+      return ES_OK;
+    }
+    plan_layout(p, false);  // phase-merged after all: in-place level arrays
+  }
   for (int k = 0; k < count; ++k) {
     st = instance_schedule_frozen(p, k, &scs[k]);
     if (st != ES_OK) { delete p; return st; }
@@ -1446,6 +1734,18 @@ es_status plan_prepare(es_plan* p, const float* const* in, float* const* out, vo
   bool same = p->tables_valid && ws == p->last_ws;
   for (int k = 0; same && k < n; ++k) same = in[k] == p->last_in[k] && out[k] == p->last_out[k];
   *changed = !same;
+  if (!same && p->persistent) {
+    es_status st = persistent_fill(p, in, out, ws);
+    if (st != ES_OK) return st;
+    for (es_plan::PGroup& G : p->pgroups)
+      ES_HIP(hipMemcpyAsync(G.d_steps, G.cur_steps.data(), G.cur_steps.size() * sizeof(PStep), hipMemcpyHostToDevice, s),
+             "step table upload");
+    p->last_in.assign(in, in + n);
+    p->last_out.assign(out, out + n);
+    p->last_ws = ws;
+    p->tables_valid = true;
+    return ES_OK;
+  }
   if (!same) {
     es_status st = plan_fill_tables(p, in, out, ws);
     if (st != ES_OK) return st;
@@ -1462,6 +1762,122 @@ es_status plan_prepare(es_plan* p, const float* const* in, float* const* out, vo
     p->tables_valid = true;
   }
   return ES_OK;
+}
+
+// Device tables of a persistent plan (items are fixed at creation; steps are uploaded at fill).
+void persistent_free(es_plan* p) {
+  for (es_plan::PGroup& G : p->pgroups) {
+    if (G.d_steps) (void)hipFree(G.d_steps);
+    if (G.d_items) (void)hipFree(G.d_items);
+    if (G.d_ctr) (void)hipFree(G.d_ctr);
+    G.d_steps = nullptr;
+    G.d_items = nullptr;
+    G.d_ctr = nullptr;
+  }
+}
+
+es_status persistent_alloc(es_plan* p) {
+  for (es_plan::PGroup& G : p->pgroups) {
+    if (hipMalloc(&G.d_steps, G.h_steps.size() * sizeof(PStep)) != hipSuccess ||
+        hipMalloc(&G.d_items, std::max<size_t>(1, G.h_items.size()) * sizeof(PItem)) != hipSuccess ||
+        hipMalloc(&G.d_ctr, (kPDone + G.h_steps.size()) * sizeof(int32_t)) != hipSuccess)
+      return fail(ES_ENOMEM, "persistent plan table allocation failed");
+    if (!G.h_items.empty())
+      ES_HIP(hipMemcpy(G.d_items, G.h_items.data(), G.h_items.size() * sizeof(PItem), hipMemcpyHostToDevice),
+             "item table upload");
+    ES_HIP(hipMemset(G.d_ctr, 0, (kPDone + G.h_steps.size()) * sizeof(int32_t)), "counter clear");
+    const int resident = persist_resident_groups(G.D, G.L);
+    if (resident <= 0) return fail(ES_EDEVICE, "occupancy query of the persistent kernel failed");
+    // every XCD must receive work-groups (they are handed out round-robin): at least one per
+    // queue, in multiples of the queue count
+    const int nq = (int)G.qbegin.size() - 1;
+    int64_t grid = std::min<int64_t>((int64_t)G.h_items.size(), resident);
+    grid = (grid + nq - 1) / nq * nq;
+    G.grid = (int)std::max<int64_t>(grid, nq);
+  }
+  return ES_OK;
+}
+
+// One persistent group: clear its counters (a fill kernel, also inside captured graphs), run it.
+es_status persistent_launch_group(es_plan* p, const es_plan::PGroup& G, hipStream_t s) {
+  ES_HIP(launch_zero_ints(G.d_ctr, kPDone + (int64_t)G.h_steps.size(), s), "counter reset launch");
+  PArgs a{};
+  a.items = G.d_items;
+  a.steps = G.d_steps;
+  a.counters = G.d_ctr;
+  a.nq = (int32_t)G.qbegin.size() - 1;
+  for (int q = 0; q <= a.nq; ++q) a.qbegin[q] = G.qbegin[q];
+  a.spin_limit = p->spin_limit;
+  a.f = p->filt[G.L];
+  ES_HIP(launch_persist(G.D, G.L, a, G.grid, s), "persistent kernel launch");
+  return ES_OK;
+}
+
+// Every group; groups after the first run on side streams forked from and joined back to `s`
+// (their instances are disjoint), when side streams are given.
+es_status persistent_launch_all(es_plan* p, hipStream_t s, hipStream_t* side, int nside,
+                                std::vector<hipEvent_t>* events) {
+  const int ng = (int)p->pgroups.size();
+  if (ng <= 1 || nside <= 0 || !events) {
+    for (const es_plan::PGroup& G : p->pgroups) {
+      es_status st = persistent_launch_group(p, G, s);
+      if (st != ES_OK) return st;
+    }
+    return ES_OK;
+  }
+  hipEvent_t fork;
+  ES_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "hipEventCreate");
+  events->push_back(fork);
+  ES_HIP(hipEventRecord(fork, s), "hipEventRecord");
+  const int width = std::min(ng, nside + 1);
+  for (int k = 1; k < width; ++k) ES_HIP(hipStreamWaitEvent(side[k - 1], fork, 0), "hipStreamWaitEvent");
+  for (int g = 0; g < ng; ++g) {
+    const int k = g % width;
+    es_status st = persistent_launch_group(p, p->pgroups[g], k == 0 ? s : side[k - 1]);
+    if (st != ES_OK) return st;
+  }
+  for (int k = 1; k < width; ++k) {
+    hipEvent_t join;
+    ES_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming), "hipEventCreate");
+    events->push_back(join);
+    ES_HIP(hipEventRecord(join, side[k - 1]), "hipEventRecord");
+    ES_HIP(hipStreamWaitEvent(s, join, 0), "hipStreamWaitEvent");
+  }
+  return ES_OK;
+}
+
+void plan_drop_graph(es_plan* p) {
+  if (p->exec) (void)hipGraphExecDestroy(p->exec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  p->exec = nullptr;
+  p->graph = nullptr;
+  for (hipEvent_t ev : p->cap_events) (void)hipEventDestroy(ev);
+  for (hipStream_t st : p->cap_streams) (void)hipStreamDestroy(st);
+  p->cap_events.clear();
+  p->cap_streams.clear();
+}
+
+// Rebuilds a persistent plan's frozen schedules, step tables and item order for its current
+// lag and coarse limit (used by the plan autotuner), with fresh device tables.
+es_status persistent_rebuild(es_plan* p) {
+  plan_drop_graph(p);
+  persistent_free(p);
+  const int n = (int)p->geos.size();
+  std::vector<Schedule> scs(n);
+  g_mode.persist = true;
+  g_mode.coarse_limit = p->coarse_limit;
+  es_status st = ES_OK;
+  for (int k = 0; k < n && st == ES_OK; ++k) {
+    st = instance_schedule_frozen(p, k, &scs[k]);
+    for (const Launch& l : scs[k].launches)
+      if (st == ES_OK && !l.is_tail && !l.vec) st = fail(ES_EUNSUPPORTED, "instance %d needs the scalar staging path", k);
+  }
+  g_mode = SchedMode{};
+  if (st != ES_OK) return st;
+  for (int k = 0; k < n; ++k) p->frozen[k] = scs[k].identity ? std::vector<Launch>() : scs[k].launches;
+  persistent_tables(p);
+  p->tables_valid = false;
+  return persistent_alloc(p);
 }
 
 }  // namespace
@@ -1664,6 +2080,18 @@ es_status es_plan_create(const es_desc* descs, int32_t count, int op, void* stre
   st = plan_build(descs, count, op, &p);
   if (st != ES_OK) return st;
   if (hipGetDevice(&p->device) != hipSuccess) { es_plan_destroy(p); return fail(ES_EDEVICE, "hipGetDevice failed"); }
+  if (p->persistent) {
+    int nxcc = 0;
+    if (hipDeviceGetAttribute(&nxcc, hipDeviceAttributeNumberOfXccs, p->device) != hipSuccess || nxcc < 1) nxcc = 1;
+    if (nxcc != p->nq) {  // the item lists were built for kPMaxQueues XCDs
+      p->nq = std::min(nxcc, kPMaxQueues);
+      persistent_tables(p);
+    }
+    st = persistent_alloc(p);
+    if (st != ES_OK) { es_plan_destroy(p); return st; }
+    *out = p;
+    return ES_OK;
+  }
   const size_t nt = p->h_tasks.size(), ntail = p->h_tails.size();
   if (nt && hipMalloc(&p->d_tasks, nt * sizeof(Task)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "task table allocation failed"); }
   if (ntail && hipMalloc(&p->d_tails, ntail * sizeof(TailTask)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "tail table allocation failed"); }
@@ -1695,12 +2123,18 @@ es_status es_plan_fill_host(es_plan* p, const uint64_t* in, const uint64_t* out,
   }
   es_status st = plan_check_io(p, ip.data(), op.data(), (void*)(uintptr_t)ws, ws_bytes);
   if (st != ES_OK) return st;
+  if (p->persistent) return persistent_fill(p, ip.data(), op.data(), (void*)(uintptr_t)ws);
   return plan_fill_tables(p, ip.data(), op.data(), (void*)(uintptr_t)ws);
 }
 
 int64_t es_plan_work_groups(const es_plan* p) {
   if (!p) return -1;
   int64_t n = 0;
+  if (p->persistent) {
+    for (const es_plan::PGroup& G : p->pgroups)
+      for (const PItem& it : G.h_items) n += it.ntile;
+    return n;
+  }
   for (const PlanGroup& gr : p->groups) n += gr.total_wg;
   return n;
 }
@@ -1713,6 +2147,7 @@ es_status es_plan_execute_eager(es_plan* p, const float* const* in, float* const
   bool changed = false;
   es_status st = plan_prepare(p, in, out, ws, ws_bytes, s, &changed);
   if (st != ES_OK) return st;
+  if (p->persistent) return persistent_launch_all(p, s, nullptr, 0, nullptr);
   st = plan_identity_copies(p, in, out, s);
   if (st != ES_OK) return st;
   return plan_launch_all(p, s);
@@ -1726,10 +2161,11 @@ es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out,
   bool changed = false;
   es_status st = plan_prepare(p, in, out, ws, ws_bytes, s, &changed);
   if (st != ES_OK) return st;
-  // identity instances are plain copies of caller pointers: launched eagerly
+  // identity instances are plain copies of caller pointers: launched eagerly (persistent plans
+  // copy them in their own launches)
   st = plan_identity_copies(p, in, out, s);
   if (st != ES_OK) return st;
-  if (p->groups.empty()) return ES_OK;
+  if (p->groups.empty() && p->pgroups.empty()) return ES_OK;
   if (!p->exec) {
     // kernels read everything through the device tables, so the captured graph stays valid
     // when the caller's pointers change (only the tables are refreshed, above)
@@ -1744,7 +2180,8 @@ es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out,
     int64_t voxels = 0;
     for (const Geo& g : p->geos) voxels += g.N();
     const int def_br = voxels < kBranchMinVoxels ? 1 : 4;
-    const int nside = std::max(0, std::min(kSide, (br && *br ? atoi(br) : def_br) - 1));
+    int nside = std::max(0, std::min(kSide, (br && *br ? atoi(br) : def_br) - 1));
+    if (p->persistent) nside = std::min(kSide, (int)p->pgroups.size() - 1);  // one branch per launch
     hipError_t e = hipSuccess;
     for (int k = 0; k < nside && e == hipSuccess; ++k) e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking);
     std::vector<hipEvent_t> events;
@@ -1757,7 +2194,8 @@ es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out,
     if (e != hipSuccess) { cleanup(); return dev_fail(e, "hipStreamCreate"); }
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) { cleanup(); return dev_fail(e, "hipStreamBeginCapture"); }
-    st = nside ? plan_launch_all_forked(p, cap, side, nside, &events) : plan_launch_all(p, cap);
+    if (p->persistent) st = persistent_launch_all(p, cap, side, nside, &events);
+    else st = nside ? plan_launch_all_forked(p, cap, side, nside, &events) : plan_launch_all(p, cap);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cap, &graph);
     if (st != ES_OK) { cleanup(); if (graph) (void)hipGraphDestroy(graph); return st; }
@@ -1780,11 +2218,94 @@ es_status es_plan_execute(es_plan* p, const float* const* in, float* const* out,
 size_t es_plan_workspace_bytes(const es_plan* p) { return p ? (size_t)p->ws_total * sizeof(float) : 0; }
 
 int32_t es_plan_num_launches(const es_plan* p) {
+  if (p && p->persistent) return (int32_t)p->pgroups.size();
   return p ? (int32_t)(p->groups.size() + p->identity_inst.size()) : 0;
+}
+
+int32_t es_plan_is_persistent(const es_plan* p) { return p && p->persistent ? 1 : 0; }
+
+es_status es_plan_errors(es_plan* p, void* stream) {
+  if (!p) return fail(ES_EINVAL, "plan is NULL");
+  if (!p->persistent || p->host_only) return ES_OK;
+  ES_HIP(hipStreamSynchronize((hipStream_t)stream), "hipStreamSynchronize");
+  for (const es_plan::PGroup& G : p->pgroups) {
+    int32_t words[kPDone] = {};
+    ES_HIP(hipMemcpy(words, G.d_ctr, sizeof words, hipMemcpyDeviceToHost), "error word read");
+    if (words[kPMaxQueues] != 0)
+      return fail(ES_EDEVICE, "persistent plan (%d-D, %d-tap launch): a dependency wait gave up after its poll "
+                              "limit; the results of the last execution are invalid", G.D, G.L);
+    const int nq = (int)G.qbegin.size() - 1;
+    for (int q = 0; q < nq; ++q)
+      if (words[q] < G.qbegin[q + 1] - G.qbegin[q])
+        return fail(ES_EDEVICE, "persistent plan (%d-D, %d-tap launch): queue %d was not drained (no work-group ran "
+                                "on its XCD); the results of the last execution are invalid", G.D, G.L, q);
+  }
+  return ES_OK;
+}
+
+es_status es_plan_autotune(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
+                           int32_t reps, void* stream) {
+  if (!p) return fail(ES_EINVAL, "plan is NULL");
+  if (!p->persistent || p->geos.empty()) return ES_OK;
+  if (reps < 1) reps = 3;
+  const hipStream_t s = (hipStream_t)stream;
+  // candidates: coarse fusion depth (largest block the coarse step takes) x pipeline lag
+  const int64_t coarse[] = {kPCoarseMax, kPCoarseMax / 4};
+  const double lags[] = {0.25, 1.0, 4.0, 64.0};
+  hipEvent_t e0, e1;
+  ES_HIP(hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(ES_EDEVICE, "hipEventCreate"); }
+  es_status st = ES_OK;
+  float best = 1e30f;
+  int64_t best_c = p->coarse_limit;
+  double best_l = p->lag;
+  for (int64_t c : coarse) {
+    for (double l : lags) {
+      p->coarse_limit = c;
+      p->lag = l;
+      st = persistent_rebuild(p);
+      if (st == ES_OK) st = es_plan_execute_eager(p, in, out, ws, ws_bytes, stream);  // warm + table fill
+      if (st != ES_OK) break;
+      float tmin = 1e30f;
+      for (int round = 0; round < 3 && st == ES_OK; ++round) {
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(ES_EDEVICE, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && st == ES_OK; ++r) st = es_plan_execute_eager(p, in, out, ws, ws_bytes, stream);
+        float ms = 0.f;
+        if (st == ES_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                            hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = fail(ES_EDEVICE, "event timing failed");
+        tmin = std::min(tmin, ms);
+      }
+      if (st == ES_OK) st = es_plan_errors(p, stream);
+      if (st != ES_OK) break;
+      if (tmin < best) { best = tmin; best_c = c; best_l = l; }
+    }
+    if (st != ES_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  p->coarse_limit = best_c;
+  p->lag = best_l;
+  es_status st2 = persistent_rebuild(p);
+  if (st != ES_OK) return st;
+  return st2;
+}
+
+es_status es_plan_config(const es_plan* p, int64_t* coarse_limit, double* lag, int64_t* items) {
+  if (!p) return fail(ES_EINVAL, "plan is NULL");
+  if (coarse_limit) *coarse_limit = p->persistent ? p->coarse_limit : -1;
+  if (lag) *lag = p->persistent ? p->lag : -1.0;
+  if (items) {
+    int64_t n = 0;
+    for (const es_plan::PGroup& G : p->pgroups) n += (int64_t)G.h_items.size();
+    *items = n;
+  }
+  return ES_OK;
 }
 
 void es_plan_destroy(es_plan* p) {
   if (!p) return;
+  persistent_free(p);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   for (hipEvent_t ev : p->cap_events) (void)hipEventDestroy(ev);

@@ -127,6 +127,66 @@ constexpr int kCoarseMaxBlockBig = 16384;
 // Largest block (floats) the full-bank coarse-level kernels (tail kinds 1, 2) hold in LDS.
 constexpr int kFbCoarseMaxBlock = 8192;
 
+// ------------------------------------------------------------------------------------------
+// Persistent plan execution (persist.hip).  A plan's steps -- every level launch and coarse block
+// of every instance, as its frozen schedule lists them -- become a step table, and their tiles a
+// list of work items in an order the host chooses.  One launch per (dimensionality, taps) runs
+// them all: each work-group takes the next item of its XCD's queue, waits until the
+// step its step depends on (the previous step of the same instance) has finished all its
+// tiles, runs the tile, and counts it done.  Items are listed so that every step's dependency
+// comes earlier in the list: a work-group only waits for items that running work-groups have
+// already taken, so the queue always drains.  Every wait is bounded: past `spin_limit` polls it
+// sets the error word and goes on (the results are then invalid; the host reports ES_EDEVICE).
+enum PKind { P_LP_DOWN = 0, P_LP_UP = 1, P_COARSE = 2, P_COPY = 3 };
+
+struct PStep {
+  Task task;          // P_LP_DOWN / P_LP_UP: batch 1, tile_begin 0; P_COPY: in0 -> out0, bs_in0 floats
+  TailTask tail;      // P_COARSE: batch 1, the instance's coarse block
+  int32_t kind;       // PKind
+  int32_t L;          // taps
+  int32_t wait;       // step whose completion this step needs (-1: none)
+  int32_t wait_count; // tiles of that step
+  int32_t ntiles;     // tiles of this step
+  int32_t inst;       // instance (host bookkeeping)
+  int32_t pad_[2];
+};
+
+struct PItem {
+  int32_t step;
+  int32_t tile0;   // tiles tile0 .. tile0 + ntile - 1 of the step, run in order by one work-group
+  int32_t ntile;
+  int32_t pad_;
+};
+
+// Items are split into one queue per XCD: every instance is assigned to one queue, and a
+// work-group takes items only from the queue of the XCD it runs on, so all tiles of an instance
+// run on one XCD and its level arrays stay in that XCD's L2.  counters[q]: next item of queue q;
+// counters[kPMaxQueues]: error word; counters[kPDone + j]: finished tiles of step j.
+constexpr int kPMaxQueues = 8;
+constexpr int kPDone = kPMaxQueues + 1;
+constexpr int kPCopyChunk = 16384;  // floats per copy tile
+// Largest block the persistent kernels' coarse step holds in LDS (half the level kernels' small
+// class: the coarse body then needs no more LDS than the 2-D tile bodies).
+constexpr int kPCoarseMax = 2048;
+
+struct PArgs {
+  const PItem* items;
+  const PStep* steps;
+  int32_t* counters;
+  int32_t nq;                         // queues (XCDs)
+  int32_t spin_limit;
+  int32_t qbegin[kPMaxQueues + 1];    // queue q holds items [qbegin[q], qbegin[q + 1])
+  Filter f;                           // the launch's filter (one launch per dimensionality and taps)
+};
+
+// Work-group size of the persistent kernels and the tile variants they are built with.
+constexpr int kPThreads = 256;
+constexpr int kPVariant = 2;
+hipError_t launch_persist(int ndim, int taps, const PArgs& args, int grid, hipStream_t stream);
+// Work-groups of the persistent kernel of (ndim, taps) that fit on the device at once.
+int persist_resident_groups(int ndim, int taps);
+hipError_t launch_zero_ints(int32_t* p, int64_t n, hipStream_t stream);
+
 // Plain reference path: one launch per 1-D pass.
 struct PlainPass {
   const float* src;

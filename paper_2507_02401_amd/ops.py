@@ -218,6 +218,36 @@ class RaggedPlan:
         self.ws_bytes = int(self.lib.es_plan_workspace_bytes(self._p))
         self.workspace = torch.empty(max(1, self.ws_bytes), dtype=torch.uint8, device=self.device)
         self.num_launches = int(self.lib.es_plan_num_launches(self._p))
+        self.persistent = bool(self.lib.es_plan_is_persistent(self._p))
+
+    def _ptrs(self, inputs, outputs):
+        n = len(inputs)
+        ip = (ctypes.c_void_p * max(1, n))(*[x.data_ptr() for x in inputs])
+        op = (ctypes.c_void_p * max(1, n))(*[y.data_ptr() for y in outputs])
+        return ip, op
+
+    def config(self):
+        """(coarse limit, pipeline lag, work items per execution) of a persistent plan."""
+        c, l, n = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        check(self.lib.es_plan_config(self._p, ctypes.byref(c), ctypes.byref(l), ctypes.byref(n)))
+        return int(c.value), float(l.value), int(n.value)
+
+    def check_errors(self):
+        """Synchronise and raise if a persistent launch's bounded dependency wait gave up."""
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(self.lib.es_plan_errors(self._p, stream))
+
+    def autotune(self, inputs, outputs=None, reps=3):
+        """Time the persistent plan's coarse fusion depth and pipeline lag on these buffers and keep
+        the fastest (es_plan_autotune)."""
+        if outputs is None:
+            outputs = [torch.empty_like(x) for x in inputs]
+        ip, op = self._ptrs(inputs, outputs)
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            check(self.lib.es_plan_autotune(self._p, ip, op, self.workspace.data_ptr(), self.ws_bytes, int(reps), stream))
+        return outputs
 
     def __call__(self, inputs, outputs=None, graph=True):
         if len(inputs) != len(self.shapes):
@@ -229,9 +259,7 @@ class RaggedPlan:
                 raise ValueError(f"tensor shape must be {shp}")
             if x.dtype != torch.float32 or not x.is_contiguous() or not y.is_contiguous():
                 raise ValueError("contiguous float32 tensors required")
-        n = len(inputs)
-        ip = (ctypes.c_void_p * max(1, n))(*[x.data_ptr() for x in inputs])
-        op = (ctypes.c_void_p * max(1, n))(*[y.data_ptr() for y in outputs])
+        ip, op = self._ptrs(inputs, outputs)
         fn = self.lib.es_plan_execute if graph else self.lib.es_plan_execute_eager
         with torch.cuda.device(self.device):
             stream = torch.cuda.current_stream(self.device).cuda_stream

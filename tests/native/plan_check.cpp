@@ -26,6 +26,9 @@ hipError_t launch_block_copy(const float*, float*, const int*, const int*, const
 hipError_t launch_copy(const float*, float*, int64_t, hipStream_t) { abort(); }
 hipError_t launch_norm_finalize(const double*, const NormSegs&, double*, int64_t, hipStream_t) { abort(); }
 hipError_t launch_sumsq(const float*, int64_t, int64_t, double*, hipStream_t) { abort(); }
+hipError_t launch_persist(int, int, const PArgs&, int, hipStream_t) { abort(); }
+int persist_resident_groups(int, int) { abort(); }
+hipError_t launch_zero_ints(int32_t*, int64_t, hipStream_t) { abort(); }
 }  // namespace es
 
 static uint64_t up256(uint64_t v) { return (v + 255) & ~(uint64_t)255; }

@@ -71,15 +71,25 @@ def test_plan_branches_equal_chain(op):
         assert np.array_equal(res["1"][k], res["4"][k]), k
 
 
-def test_plan_equals_single_calls():
+@pytest.mark.parametrize("persistent", ["1", "0"])
+def test_plan_equals_single_calls(persistent):
+    """A plan gives the bits of single calls with the same schedule: persistent plans take coarse
+    blocks of at most 2048 floats (the single calls are told the same), phase-merged plans (the
+    default) the single calls' own."""
     descs = [((256, 512), 4, 5, 1.0), ((512, 256), 4, 5, 1.0), ((64, 64, 64), 2, 3, 2.0)]
     gen = np.random.default_rng(9)
     ins = [torch.from_numpy(gen.standard_normal(d[0]).astype(np.float32)).to(DEV) for d in descs]
-    plan = es.RaggedPlan(descs, es.OP_COV)
+    say("plan vs single calls, persistent", persistent)
+    with env(ESWAVE_PLAN_PERSISTENT=persistent):
+        plan = es.RaggedPlan(descs, es.OP_COV)
+    assert plan.persistent == (persistent == "1")
     outs = plan(ins)
-    for x, y, (shape, order, levels, s) in zip(ins, outs, descs):
-        single = es.matern_cov_apply(x, len(shape), order, levels, s)
-        assert torch.equal(single, y)
+    tail = {"ESWAVE_TAIL_MAX": "2048"} if persistent == "1" else {}
+    with env(**tail):
+        for x, y, (shape, order, levels, s) in zip(ins, outs, descs):
+            single = es.matern_cov_apply(x, len(shape), order, levels, s)
+            assert torch.equal(single, y)
+    plan.close()
 
 
 @pytest.mark.skip(reason="one run of this case (on a build with a different tile staging loop and tile decode, "

@@ -131,3 +131,26 @@ def test_host_plan_cannot_execute(lib):
                              lib.es_plan_workspace_bytes(plan.p), None)
     assert st != _lib.ES_OK
     plan.close()
+
+
+@pytest.mark.parametrize("op", [_lib.OP_COV, _lib.OP_SAMPLE])
+@pytest.mark.parametrize("descs", ["mixed", "ragged0", "ragged1"])
+def test_persistent_plan_tables_fill(lib, op, descs):
+    """Persistent plans (ESWAVE_PLAN_PERSISTENT=1): every step of every instance passes the
+    footprint check against the instance's own buffers and its (twice as large) workspace slice."""
+    d = MIXED if descs == "mixed" else list(inputs.ragged_descriptors(200, int(descs[-1])))
+    with env(ESWAVE_PLAN_PERSISTENT="1"):
+        plan = HostPlan(lib, d, op)
+    assert lib.es_plan_is_persistent(plan.p) == 1
+    merged = HostPlan(lib, d, op)
+    assert lib.es_plan_is_persistent(merged.p) == 0
+    # write-once level arrays: twice the phase-merged workspace
+    assert lib.es_plan_workspace_bytes(plan.p) == 2 * lib.es_plan_workspace_bytes(merged.p)
+    ins, outs, ws = _layout(d)
+    assert plan.fill(ins, outs, ws) == _lib.ES_OK, lib.es_last_error()
+    ins2, outs2, ws2 = _layout(d, base=9 << 40)
+    assert plan.fill(outs2, ins2, ws2) == _lib.ES_OK, lib.es_last_error()
+    assert merged.fill(ins, outs, ws) == _lib.ES_OK
+    assert plan.work_groups() > 0 and merged.work_groups() > 0
+    plan.close()
+    merged.close()

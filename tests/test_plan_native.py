@@ -42,8 +42,9 @@ def checker(tmp_path_factory):
     return out
 
 
-def _run(checker, text):
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+def _run(checker, text, persistent="0"):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1",
+               ESWAVE_PLAN_PERSISTENT=persistent)
     r = subprocess.run([checker], input=text, capture_output=True, text=True, timeout=600, env=env)
     assert r.returncode == 0 and r.stdout.startswith("ok"), (r.stdout[-2000:], r.stderr[-6000:])
     return r.stdout.split()
@@ -55,11 +56,12 @@ def test_mixed_every_op(checker):
     assert int(out[1]) == 4 and int(out[2]) > 0
 
 
+@pytest.mark.parametrize("persistent", ["0", "1"])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_ragged_recipe_draws(checker, seed):
+def test_ragged_recipe_draws(checker, seed, persistent):
     descs = list(inputs.ragged_descriptors(200, seed))
     text = "".join(_plan_text(op, descs) for op in range(4))
-    out = _run(checker, text)
+    out = _run(checker, text, persistent)
     assert int(out[1]) == 4
 
 
@@ -76,5 +78,6 @@ def test_random_small_plans(checker):
             shape = tuple(int(gen.integers(1, 6 if d == 3 else 12)) * (1 << levels) for _ in range(d))
             descs.append((shape, int(gen.integers(1, 9)), levels, float(gen.choice([-1.0, 0.5, 1.5]))))
         text += _plan_text(int(gen.integers(0, 4)), descs)
-    out = _run(checker, text)
-    assert int(out[1]) == 60
+    for persistent in ("0", "1"):
+        out = _run(checker, text, persistent)
+        assert int(out[1]) == 60
