@@ -132,6 +132,33 @@ es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order
                         const float* x, double* norms, void* ws, size_t ws_bytes, void* stream);
 size_t es_hs_norm_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
 
+/* ---- matrix-free Tikhonov / MAP solver around the prior ----------------------------------- */
+
+/* Solves, per instance, the normal equations of J(x) = 1/2 ||M x - p||^2 + alpha/2 ||x||^2_{H^s}
+ * (Sec. 3: the Tikhonov functional and the linear equation of its minimiser; Sec. 4: iterative
+ * solvers such as conjugate gradients on the wavelet form):
+ *     (M + alpha W^T D_{-2s} W) x = M p,   M = diag(mask),
+ * by conjugate gradients preconditioned with W^T D_{2s} W = matern_cov_apply(s), starting from
+ * x = 0.  Every step runs on the device: two operator applications per iteration (matern_cov_apply
+ * with -s and +s) and fused element-wise update / inner-product kernels; inner products are FP32
+ * with compensated per-thread sums, pairwise trees and a fixed-order per-instance reduction
+ * (deterministic).  An instance stops changing once ||r|| / ||M p|| <= rtol; the host reads the
+ * residuals every `check_every` iterations (synchronising `stream`) and stops when all instances
+ * are below rtol or after max_iter iterations.
+ *   p, mask, x   device, batch * prod(shape) floats, 16-byte aligned; x is written (must not
+ *                overlap p, mask or ws).
+ *   iterations   host, receives the iterations run (may be NULL).
+ *   rel_residual host, batch floats: ||r|| / ||M p|| of each instance at the end (0 when M p = 0).
+ *   ws           device, es_tikhonov_pcg_workspace_bytes(...) bytes, 256-byte aligned: r, z, d, A d,
+ *                partial sums, per-instance scalars and the operator's workspace.
+ * Other arguments as for matern_cov_apply.  Errors: ES_EINVAL (arguments, alpha <= 0, rtol < 0,
+ * max_iter < 0), ES_EWORKSPACE, ES_EUNSUPPORTED, ES_EDEVICE.  Synchronous on return. */
+es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                          double alpha, const float* p, const float* mask, float* x, int32_t max_iter, double rtol,
+                          int32_t check_every, int32_t* iterations, float* rel_residual, void* ws, size_t ws_bytes,
+                          void* stream);
+size_t es_tikhonov_pcg_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
+
 /* ---- Fourier form of E_s^* (Sec. 4, Implementation) ------------------------------------ */
 
 /* y_b = ifft(B . fft(x_b)) for each of `batch` instances: the paper's second realisation of the

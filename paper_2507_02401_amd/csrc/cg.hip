@@ -1,0 +1,388 @@
+// Matrix-free Tikhonov / MAP solver around the wavelet prior: preconditioned conjugate gradients
+// on the normal equations of J(x) = 1/2 ||M x - p||^2 + alpha/2 ||x||^2_{H^s} (Sec. 3: the
+// Tikhonov functional and the linear equation of its minimiser; Sec. 4: the wavelet form of the
+// Sobolev operators and the remark that iterative solvers such as conjugate gradients apply to
+// it), i.e.
+//     (M + alpha Gamma^2) x = M p,   Gamma^2 = W^T D_{-2s} W,   M = diag(mask),
+// preconditioned with W^T D_{2s} W (the covariance: the inverse of the penalty term up to the
+// factor 1/alpha, which CG's iterates do not depend on).
+//
+// Every step runs on the device: the two operator applications per iteration are the library's
+// matern_cov_apply (smoothness -s and +s), the vector updates are fused element-wise kernels
+// that also produce per-work-group partial inner products, and one work-group per instance
+// reduces those partials in a fixed order and updates the instance's CG scalars.  All sums are
+// FP32 with compensation (Neumaier) per thread and pairwise trees across threads; results are
+// deterministic.  The host looks at the residuals only every `check_every` iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/eswave.h"
+#include "internal.h"
+#include "kcommon.h"
+
+namespace es {
+namespace {
+
+constexpr int kCgThreads = 256;
+constexpr int kCgChunk = 4096;  // elements of one instance per work-group of the element-wise kernels
+
+// Per-instance CG scalars (device).
+struct CgScal {
+  float bn;      // ||b||
+  float rz;      // r . z
+  float a;       // step length of this iteration (0 once converged)
+  float beta;    // direction update of this iteration (0 once converged)
+  float rel;     // ||r|| / ||b||
+  float active;  // 1 while rel > rtol at the start of the iteration
+  float pad_[2];
+};
+
+// Compensated accumulation (Neumaier): s + c holds the sum.
+struct KSum {
+  float s = 0.f, c = 0.f;
+  DEVI void add(float v) {
+    const float t = s + v;
+    c += fabsf(s) >= fabsf(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+  }
+  DEVI float value() const { return s + c; }
+};
+
+// Sum of one value per thread over the work-group, pairwise (fixed order); thread 0 gets it.
+DEVI float wg_sum(float v) {
+  __shared__ float part[kCgThreads / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part[w] = v;
+  __syncthreads();
+  float t = 0.f;
+  if (threadIdx.x == 0) t = (part[0] + part[1]) + (part[2] + part[3]);
+  __syncthreads();
+  return t;
+}
+
+// Work-group -> (instance, chunk) of the element-wise kernels.
+struct Span {
+  int64_t inst, lo, hi;  // elements [lo, hi) of instance inst
+};
+DEVI Span span_of(int64_t n, int per) {
+  Span sp;
+  sp.inst = blockIdx.x / per;
+  sp.lo = (int64_t)(blockIdx.x % per) * kCgChunk;
+  sp.hi = min(n, sp.lo + kCgChunk);
+  return sp;
+}
+
+// Element-wise loop over one chunk; vectors of four where the instance size allows.
+template <class F>
+DEVI void for_chunk(const Span& sp, int64_t n, F f) {
+  const int64_t base = sp.inst * n;
+  if ((n & 3) == 0) {
+    for (int64_t i = sp.lo + 4 * threadIdx.x; i < sp.hi; i += 4 * kCgThreads) f(base + i, 4);
+  } else {
+    for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += kCgThreads) f(base + i, 1);
+  }
+}
+
+// r = mask * p, x = 0; partial r . r
+__global__ void __launch_bounds__(kCgThreads) k_cg_init(int64_t n, int per, const float* __restrict__ p,
+                                                        const float* __restrict__ mask, float* __restrict__ x,
+                                                        float* __restrict__ r, float* __restrict__ part) {
+  const Span sp = span_of(n, per);
+  KSum acc;
+  for_chunk(sp, n, [&](int64_t i, int w) {
+    for (int k = 0; k < w; ++k) {
+      const float v = gld(mask + i + k) * gld(p + i + k);
+      gst(r + i + k, v);
+      gst(x + i + k, 0.f);
+      acc.add(v * v);
+    }
+  });
+  const float t = wg_sum(acc.value());
+  if (threadIdx.x == 0) gst(part + blockIdx.x, t);
+}
+
+// partial a . b (and, when dst is given, dst = b: the first direction d = z)
+__global__ void __launch_bounds__(kCgThreads) k_cg_dot(int64_t n, int per, const float* __restrict__ a,
+                                                       const float* __restrict__ b, float* __restrict__ dst,
+                                                       float* __restrict__ part) {
+  const Span sp = span_of(n, per);
+  KSum acc;
+  for_chunk(sp, n, [&](int64_t i, int w) {
+    if (w == 4) {
+      const float4 u = gld4(a + i), v = gld4(b + i);
+      if (dst) gst4(dst + i, v);
+      acc.add(u.x * v.x);
+      acc.add(u.y * v.y);
+      acc.add(u.z * v.z);
+      acc.add(u.w * v.w);
+    } else {
+      const float v = gld(b + i);
+      if (dst) gst(dst + i, v);
+      acc.add(gld(a + i) * v);
+    }
+  });
+  const float t = wg_sum(acc.value());
+  if (threadIdx.x == 0) gst(part + blockIdx.x, t);
+}
+
+// ad = alpha * ad + mask * d (ad holds W^T D_{-2s} W d on entry); partial d . ad
+__global__ void __launch_bounds__(kCgThreads) k_cg_apply(int64_t n, int per, float alpha, const float* __restrict__ mask,
+                                                         const float* __restrict__ d, float* __restrict__ ad,
+                                                         float* __restrict__ part) {
+  const Span sp = span_of(n, per);
+  KSum acc;
+  for_chunk(sp, n, [&](int64_t i, int w) {
+    if (w == 4) {
+      const float4 m = gld4(mask + i), dv = gld4(d + i), g = gld4(ad + i);
+      const float4 o = make_float4(fmaf(m.x, dv.x, alpha * g.x), fmaf(m.y, dv.y, alpha * g.y),
+                                   fmaf(m.z, dv.z, alpha * g.z), fmaf(m.w, dv.w, alpha * g.w));
+      gst4(ad + i, o);
+      acc.add(dv.x * o.x);
+      acc.add(dv.y * o.y);
+      acc.add(dv.z * o.z);
+      acc.add(dv.w * o.w);
+    } else {
+      const float dv = gld(d + i);
+      const float o = fmaf(gld(mask + i), dv, alpha * gld(ad + i));
+      gst(ad + i, o);
+      acc.add(dv * o);
+    }
+  });
+  const float t = wg_sum(acc.value());
+  if (threadIdx.x == 0) gst(part + blockIdx.x, t);
+}
+
+// x += a d, r -= a ad; partial r . r
+__global__ void __launch_bounds__(kCgThreads) k_cg_step(int64_t n, int per, const CgScal* __restrict__ sc,
+                                                        float* __restrict__ x, float* __restrict__ r,
+                                                        const float* __restrict__ d, const float* __restrict__ ad,
+                                                        float* __restrict__ part) {
+  const Span sp = span_of(n, per);
+  const float a = sc[sp.inst].a;
+  KSum acc;
+  for_chunk(sp, n, [&](int64_t i, int w) {
+    if (w == 4) {
+      const float4 xv = gld4(x + i), rv = gld4(r + i), dv = gld4(d + i), g = gld4(ad + i);
+      const float4 xn = make_float4(fmaf(a, dv.x, xv.x), fmaf(a, dv.y, xv.y), fmaf(a, dv.z, xv.z), fmaf(a, dv.w, xv.w));
+      const float4 rn = make_float4(fmaf(-a, g.x, rv.x), fmaf(-a, g.y, rv.y), fmaf(-a, g.z, rv.z), fmaf(-a, g.w, rv.w));
+      gst4(x + i, xn);
+      gst4(r + i, rn);
+      acc.add(rn.x * rn.x);
+      acc.add(rn.y * rn.y);
+      acc.add(rn.z * rn.z);
+      acc.add(rn.w * rn.w);
+    } else {
+      gst(x + i, fmaf(a, gld(d + i), gld(x + i)));
+      const float rn = fmaf(-a, gld(ad + i), gld(r + i));
+      gst(r + i, rn);
+      acc.add(rn * rn);
+    }
+  });
+  const float t = wg_sum(acc.value());
+  if (threadIdx.x == 0) gst(part + blockIdx.x, t);
+}
+
+// d = beta d + z
+__global__ void __launch_bounds__(kCgThreads) k_cg_dir(int64_t n, int per, const CgScal* __restrict__ sc,
+                                                       float* __restrict__ d, const float* __restrict__ z) {
+  const Span sp = span_of(n, per);
+  const float beta = sc[sp.inst].beta;
+  for_chunk(sp, n, [&](int64_t i, int w) {
+    if (w == 4) {
+      const float4 dv = gld4(d + i), zv = gld4(z + i);
+      gst4(d + i, make_float4(fmaf(beta, dv.x, zv.x), fmaf(beta, dv.y, zv.y), fmaf(beta, dv.z, zv.z),
+                              fmaf(beta, dv.w, zv.w)));
+    } else {
+      gst(d + i, fmaf(beta, gld(d + i), gld(z + i)));
+    }
+  });
+}
+
+enum CgFinal { F_INIT = 0, F_RZ0 = 1, F_A = 2, F_RR = 3, F_BETA = 4 };
+
+// One work-group per instance: the sum of its `per` partials, in a fixed order, and the scalar
+// update of step `kind`.
+__global__ void __launch_bounds__(kCgThreads) k_cg_final(int kind, int per, const float* __restrict__ part,
+                                                         CgScal* __restrict__ sc, float rtol) {
+  const int64_t inst = blockIdx.x;
+  KSum acc;
+  for (int k = threadIdx.x; k < per; k += kCgThreads) acc.add(part[inst * per + k]);
+  const float sum = wg_sum(acc.value());
+  if (threadIdx.x != 0) return;
+  CgScal c = sc[inst];
+  switch (kind) {
+    case F_INIT:
+      c.bn = sqrtf(sum);
+      c.rel = c.bn > 0.f ? 1.f : 0.f;
+      c.active = c.rel > rtol ? 1.f : 0.f;
+      c.a = c.beta = 0.f;
+      break;
+    case F_RZ0: c.rz = sum; break;
+    case F_A: c.a = (c.active != 0.f && sum > 0.f) ? c.rz / sum : 0.f; break;
+    case F_RR: c.rel = c.bn > 0.f ? sqrtf(sum) / c.bn : 0.f; break;
+    default:  // F_BETA: sum = r . z of the new residual
+      c.beta = (c.active != 0.f && c.rz > 0.f) ? sum / c.rz : 0.f;
+      c.rz = sum;
+      c.active = c.rel > rtol ? c.active : 0.f;  // converged instances stay frozen
+      break;
+  }
+  sc[inst] = c;
+}
+
+int64_t cg_parts(int64_t n) { return (n + kCgChunk - 1) / kCgChunk; }
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct CgLayout {
+  size_t r, z, d, ad, part, scal, cov, total;
+};
+
+CgLayout cg_layout(int64_t n, int64_t batch, size_t cov_bytes) {
+  CgLayout L;
+  const size_t vec = a256((size_t)(n * batch) * sizeof(float));
+  L.r = 0;
+  L.z = L.r + vec;
+  L.d = L.z + vec;
+  L.ad = L.d + vec;
+  L.part = L.ad + vec;
+  L.scal = L.part + a256((size_t)(cg_parts(n) * batch) * sizeof(float));
+  L.cov = L.scal + a256((size_t)batch * sizeof(CgScal));
+  L.total = L.cov + cov_bytes;
+  return L;
+}
+
+}  // namespace
+}  // namespace es
+
+using namespace es;
+
+extern "C" {
+
+size_t es_tikhonov_pcg_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels) {
+  if (batch < 1 || ndim < 1 || ndim > 3 || !shape) return 0;
+  int64_t n = 1;
+  for (int k = 0; k < ndim; ++k) n *= shape[k];
+  const size_t cov = es_workspace_bytes(ndim, shape, batch, order, levels, ES_OP_COV);
+  return cg_layout(n, batch, cov).total;
+}
+
+es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s, double alpha,
+                          const float* p, const float* mask, float* x, int32_t max_iter, double rtol,
+                          int32_t check_every, int32_t* iterations, float* rel_residual, void* ws, size_t ws_bytes,
+                          void* stream) {
+  char msg[256];
+  if (ndim < 1 || ndim > 3 || !shape) return report_error(ES_EINVAL, "ndim must be 1..3 and shape non-NULL");
+  if (batch < 0) return report_error(ES_EINVAL, "batch must be >= 0");
+  if (!(alpha > 0) || !std::isfinite(alpha)) return report_error(ES_EINVAL, "alpha must be positive and finite");
+  if (!(rtol >= 0) || !std::isfinite(rtol)) return report_error(ES_EINVAL, "rtol must be finite and >= 0");
+  if (max_iter < 0) return report_error(ES_EINVAL, "max_iter must be >= 0");
+  if (check_every < 1) check_every = 1;
+  if (iterations) *iterations = 0;
+  if (batch == 0) return ES_OK;
+  if (batch > 0x7fffffffll) return report_error(ES_EINVAL, "batch too large");
+  int64_t n = 1;
+  for (int k = 0; k < ndim; ++k) {
+    if (shape[k] < 1) return report_error(ES_EINVAL, "shape entries must be positive");
+    n *= shape[k];
+  }
+  const int64_t per = cg_parts(n);
+  if (per * batch > 0x7fffffffll) return report_error(ES_EINVAL, "problem too large");
+  // validates the operator arguments (order, levels, divisibility) through the workspace query
+  const size_t cov = es_workspace_bytes(ndim, shape, batch, order, levels, ES_OP_COV);
+  if (cov == 0 && levels > 1) return report_error(ES_EINVAL, "invalid operator arguments (order, levels, shape)");
+  const CgLayout L = cg_layout(n, batch, cov);
+  if (!p || !mask || !x || !rel_residual) return report_error(ES_EINVAL, "p, mask, x and rel_residual must be non-NULL");
+  if (((uintptr_t)p | (uintptr_t)mask | (uintptr_t)x) & 15) return report_error(ES_EINVAL, "p, mask and x must be 16-byte aligned");
+  if (!ws || ws_bytes < L.total) {
+    snprintf(msg, sizeof msg, "workspace of %zu bytes required", L.total);
+    return report_error(ES_EWORKSPACE, msg);
+  }
+  if ((uintptr_t)ws & 255) return report_error(ES_EINVAL, "workspace must be 256-byte aligned");
+  const size_t vb = (size_t)(n * batch) * sizeof(float);
+  auto ov = [](const void* a, size_t na, const void* b, size_t nb) {
+    return (const char*)a < (const char*)b + nb && (const char*)b < (const char*)a + na;
+  };
+  if (ov(x, vb, p, vb) || ov(x, vb, mask, vb) || ov(ws, L.total, x, vb) || ov(ws, L.total, p, vb) ||
+      ov(ws, L.total, mask, vb))
+    return report_error(ES_EINVAL, "x must not overlap p, mask or the workspace; the workspace must not overlap p or mask");
+  es_status st = device_check();
+  if (st != ES_OK) return st;
+
+  char* w = (char*)ws;
+  float* r = (float*)(w + L.r);
+  float* z = (float*)(w + L.z);
+  float* d = (float*)(w + L.d);
+  float* ad = (float*)(w + L.ad);
+  float* part = (float*)(w + L.part);
+  CgScal* sc = (CgScal*)(w + L.scal);
+  void* cws = cov ? (void*)(w + L.cov) : nullptr;
+  const hipStream_t hs = (hipStream_t)stream;
+  const dim3 grid((unsigned)(per * batch)), blk(kCgThreads);
+  const float frtol = (float)rtol;
+  auto ok = [&](const char* what) -> es_status {
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return ES_OK;
+    snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
+    return report_error(ES_EDEVICE, msg);
+  };
+  auto final_ = [&](int kind) -> es_status {
+    hipLaunchKernelGGL(k_cg_final, dim3((unsigned)batch), blk, 0, hs, kind, (int)per, part, sc, frtol);
+    return ok("CG scalar update launch");
+  };
+  auto cov_apply = [&](const float* in, float* out, double sm) -> es_status {
+    return matern_cov_apply(ndim, shape, batch, order, levels, sm, in, out, cws, cov, stream);
+  };
+
+  // r = b = M p, x = 0, ||b||; z = P r, d = z, rz = r . z
+  hipLaunchKernelGGL(k_cg_init, grid, blk, 0, hs, n, (int)per, p, mask, x, r, part);
+  if ((st = ok("CG init launch")) != ES_OK || (st = final_(F_INIT)) != ES_OK) return st;
+  if ((st = cov_apply(r, z, s)) != ES_OK) return st;
+  hipLaunchKernelGGL(k_cg_dot, grid, blk, 0, hs, n, (int)per, r, z, d, part);
+  if ((st = ok("CG dot launch")) != ES_OK || (st = final_(F_RZ0)) != ES_OK) return st;
+
+  std::vector<CgScal> host((size_t)batch);
+  int it = 0;
+  bool done = false;
+  while (it < max_iter && !done) {
+    // ad = alpha Gamma^2 d + M d, a = rz / (d . ad)
+    if ((st = cov_apply(d, ad, -s)) != ES_OK) return st;
+    hipLaunchKernelGGL(k_cg_apply, grid, blk, 0, hs, n, (int)per, (float)alpha, mask, d, ad, part);
+    if ((st = ok("CG operator update launch")) != ES_OK || (st = final_(F_A)) != ES_OK) return st;
+    // x += a d, r -= a ad, rel = ||r|| / ||b||
+    hipLaunchKernelGGL(k_cg_step, grid, blk, 0, hs, n, (int)per, sc, x, r, d, ad, part);
+    if ((st = ok("CG step launch")) != ES_OK || (st = final_(F_RR)) != ES_OK) return st;
+    // z = P r, beta = (r . z) / rz, d = z + beta d
+    if ((st = cov_apply(r, z, s)) != ES_OK) return st;
+    hipLaunchKernelGGL(k_cg_dot, grid, blk, 0, hs, n, (int)per, r, z, (float*)nullptr, part);
+    if ((st = ok("CG dot launch")) != ES_OK || (st = final_(F_BETA)) != ES_OK) return st;
+    hipLaunchKernelGGL(k_cg_dir, grid, blk, 0, hs, n, (int)per, sc, d, z);
+    if ((st = ok("CG direction launch")) != ES_OK) return st;
+    ++it;
+    if (it % check_every == 0 || it == max_iter) {
+      hipError_t e = hipMemcpyAsync(host.data(), sc, host.size() * sizeof(CgScal), hipMemcpyDeviceToHost, hs);
+      if (e == hipSuccess) e = hipStreamSynchronize(hs);
+      if (e != hipSuccess) {
+        snprintf(msg, sizeof msg, "CG residual read: %s", hipGetErrorString(e));
+        return report_error(ES_EDEVICE, msg);
+      }
+      done = true;
+      for (const CgScal& c : host) done = done && !(c.rel > frtol);
+    }
+  }
+  hipError_t e = hipMemcpyAsync(host.data(), sc, host.size() * sizeof(CgScal), hipMemcpyDeviceToHost, hs);
+  if (e == hipSuccess) e = hipStreamSynchronize(hs);
+  if (e != hipSuccess) {
+    snprintf(msg, sizeof msg, "CG residual read: %s", hipGetErrorString(e));
+    return report_error(ES_EDEVICE, msg);
+  }
+  for (int64_t b = 0; b < batch; ++b) rel_residual[b] = host[(size_t)b].rel;
+  if (iterations) *iterations = it;
+  return ES_OK;
+}
+
+}  // extern "C"

@@ -35,3 +35,20 @@ def test_tikhonov_pcg_matches_oracle(shape, ndim, order, levels, s, alpha):
         ref = oracle.tikhonov_solve(ps[b].astype(np.float64), ms[b].astype(np.float64), order, levels, s, alpha)
         err = rel_l2(xs[b], ref)
         assert err <= SOLVE_TOL, (b, err)
+
+
+def test_tikhonov_pcg_deterministic_and_frozen_instances():
+    """Two solves give the same bits (fixed-order reductions); an instance with an empty mask
+    (M p = 0) stays at x = 0 with residual 0 while the others converge."""
+    gen = np.random.default_rng(5)
+    shape = (3, 64, 64)
+    mask = (gen.random(shape) < 0.3).astype(np.float32)
+    mask[1] = 0.0
+    p = gen.standard_normal(shape).astype(np.float32)
+    pt, mt = torch.from_numpy(p).cuda(), torch.from_numpy(mask).cuda()
+    say("tikhonov_pcg determinism")
+    x1, i1 = tikhonov_pcg(pt, mt, 2, 4, 4, 1.0, 0.1, iters=100, rtol=1e-6)
+    x2, i2 = tikhonov_pcg(pt, mt, 2, 4, 4, 1.0, 0.1, iters=100, rtol=1e-6)
+    assert torch.equal(x1, x2) and i1["iterations"] == i2["iterations"]
+    assert float(x1[1].abs().max()) == 0.0 and float(i1["rel_residual"][1]) == 0.0
+    assert bool((i1["rel_residual"] <= 1e-6).all())

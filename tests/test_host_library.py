@@ -170,3 +170,23 @@ def test_noalloc_refuses_oversize_on_host(lib):
     assert need > lib.es_noalloc_scratch_bytes() == 64 << 20
     assert lib.matern_cov_apply_noalloc(2, shp, 64, 8, 7, 1.5, 1 << 20, 1 << 30, None) == _lib.ES_EWORKSPACE
     assert b"scratch" in lib.es_last_error()
+
+
+def test_tikhonov_pcg_validates_on_host(lib):
+    """The solver entry point refuses bad arguments before any device call."""
+    shp = _lib.shape_arg((64, 64))
+    need = lib.es_tikhonov_pcg_workspace_bytes(2, shp, 2, 4, 3)
+    assert need >= 4 * 2 * 64 * 64 * 4
+    rel = (ctypes.c_float * 2)()
+    its = ctypes.c_int32()
+    P, M, X, WS = 1 << 20, 1 << 24, 1 << 28, 1 << 32
+    def call(alpha=0.1, rtol=1e-6, max_iter=10, ws=WS, ws_bytes=need, x=X):
+        return lib.es_tikhonov_pcg(2, shp, 2, 4, 3, 1.0, alpha, P, M, x, max_iter, rtol, 4, ctypes.byref(its), rel,
+                                   ws, ws_bytes, None)
+    assert call(alpha=0.0) == _lib.ES_EINVAL
+    assert call(alpha=float("nan")) == _lib.ES_EINVAL
+    assert call(rtol=-1.0) == _lib.ES_EINVAL
+    assert call(max_iter=-1) == _lib.ES_EINVAL
+    assert call(ws_bytes=need - 1) == _lib.ES_EWORKSPACE
+    assert call(ws=WS + 16) == _lib.ES_EINVAL          # workspace alignment
+    assert call(x=P + 64) == _lib.ES_EINVAL            # x overlaps p
