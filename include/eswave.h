@@ -123,13 +123,15 @@ size_t es_workspace_bytes_plain(int ndim, const int64_t* shape, int64_t batch, i
  * of 2^{2 s j} c^2 (detail level i: j = m - i; approximation: weight 1), the squared norm that
  * defines the prior (Sec. 3, ||x||_{H^s} = ||Gamma x||, with the wavelet weights of Sec. 4).  Its
  * gradient is 2 W^T D_{-2s} W x = 2 * matern_cov_apply(x) with smoothness -s.  The analysis runs
- * in squared-norm mode (coefficients are squared and summed per work-group, never stored); each
- * instance's partial sums are added in a fixed order in FP64, so results are deterministic.
- * x: device, batch * prod(shape) floats, 16-byte aligned.  norms: device, batch doubles, 8-byte
+ * in squared-norm mode (coefficients are squared and summed per work-group, never stored).  All
+ * sums are FP32 with compensation (Neumaier per thread, error-free pair sums across threads and
+ * work-groups) in a fixed order, so results are deterministic and, the terms being non-negative,
+ * within a few FP32 roundings of the exact sum of the computed squares.
+ * x: device, batch * prod(shape) floats, 16-byte aligned.  norms: device, batch floats, 4-byte
  * aligned.  ws: device, es_hs_norm_workspace_bytes(...) bytes, 256-byte aligned.  Other
  * arguments and errors as for es_adjoint. */
 es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
-                        const float* x, double* norms, void* ws, size_t ws_bytes, void* stream);
+                        const float* x, float* norms, void* ws, size_t ws_bytes, void* stream);
 size_t es_hs_norm_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
 
 /* ---- matrix-free Tikhonov / MAP solver around the prior ----------------------------------- */

@@ -817,7 +817,7 @@ void launch_accesses(const Launch& l, std::vector<Access>* acc) {
     case K_FB_DOWN:
     case K_FB_DOWN_S:
       add(t.in0, t.bs_in0, block_span(t.b, t.st_in0[0], t.st_in0[1]), false);
-      if (t.flags & kNormSq) {  // per-work-group partial sums (doubles) in place of the bands
+      if (t.flags & kNormSq) {  // per-work-group partial sums (8-byte pairs) in place of the bands
         acc->push_back(Access{t.out0, 0, (int64_t)t.tiles_per_inst * t.batch * 8, true});
         if (!(t.flags & kNormLL)) add(t.out1, t.bs_out1, block_span(h, t.st_out1[0], t.st_out1[1]), true);
       } else {
@@ -1930,7 +1930,7 @@ size_t es_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int ord
 // and summed per work-group instead of stored, and one finalising launch adds the partials of
 // each instance in a fixed order.
 
-// Partial sums (doubles) the squared-norm mode needs per instance: for every level launch the
+// Partial sums (compensated FP32 pairs, 8 bytes each) the squared-norm mode needs per instance: for every level launch the
 // most tiles any of its candidates uses, plus one for the coarse-level kernel.
 int64_t norm_partials_per_instance(const Geo& g) {
   Schedule sc;
@@ -1956,7 +1956,7 @@ size_t norm_ws_bytes(const Geo& g, int64_t batch) {
   const int64_t per = norm_partials_per_instance(g);
   if (per < 0) return 0;
   const size_t lv = ((size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float) + 255) & ~(size_t)255;
-  return lv + (size_t)batch * (size_t)per * sizeof(double);
+  return lv + (size_t)batch * (size_t)per * sizeof(float2);
 }
 
 size_t es_hs_norm_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels) {
@@ -1966,7 +1966,7 @@ size_t es_hs_norm_workspace_bytes(int ndim, const int64_t* shape, int64_t batch,
 }
 
 es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
-                        const float* x, double* norms, void* ws, size_t ws_bytes, void* stream) {
+                        const float* x, float* norms, void* ws, size_t ws_bytes, void* stream) {
   Geo g;
   es_status st = make_geo(ndim, shape, order, levels, -s, &g);  // weights 2^{+s j}
   if (st != ES_OK) return st;
@@ -1974,16 +1974,16 @@ es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order
   if (batch == 0) return ES_OK;
   if (batch > 0x7fffffffll) return fail(ES_EINVAL, "batch too large");
   if (!x || !norms) return fail(ES_EINVAL, "input and output pointers must be non-NULL");
-  if (((uintptr_t)x & 15) || ((uintptr_t)norms & 7))
-    return fail(ES_EINVAL, "input must be 16-byte and output 8-byte aligned");
+  if (((uintptr_t)x & 15) || ((uintptr_t)norms & 3))
+    return fail(ES_EINVAL, "input must be 16-byte and output 4-byte aligned");
   const size_t xbytes = (size_t)(batch * g.N()) * sizeof(float);
-  if (overlap(x, xbytes, norms, (size_t)batch * sizeof(double))) return fail(ES_EINVAL, "input and output overlap");
+  if (overlap(x, xbytes, norms, (size_t)batch * sizeof(float))) return fail(ES_EINVAL, "input and output overlap");
   const size_t need = norm_ws_bytes(g, batch);
   if (need) {
     if (!ws) return fail(ES_EWORKSPACE, "workspace of %zu bytes required, got NULL", need);
     if (ws_bytes < need) return fail(ES_EWORKSPACE, "workspace of %zu bytes required, got %zu", need, ws_bytes);
     if ((uintptr_t)ws & 255) return fail(ES_EINVAL, "workspace must be 256-byte aligned");
-    if (overlap(ws, need, x, xbytes) || overlap(ws, need, norms, (size_t)batch * sizeof(double)))
+    if (overlap(ws, need, x, xbytes) || overlap(ws, need, norms, (size_t)batch * sizeof(float)))
       return fail(ES_EINVAL, "workspace overlaps input or output");
   }
   st = check_device();
@@ -1994,7 +1994,7 @@ es_status es_hs_norm_sq(int ndim, const int64_t* shape, int64_t batch, int order
     return ES_OK;
   }
   float* lv = (float*)ws;
-  double* partials = (double*)((char*)ws + (((size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float) + 255) &
+  float2* partials = (float2*)((char*)ws + (((size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float) + 255) &
                                             ~(size_t)255));
   Schedule sc;
   // the coefficient array is never written in squared-norm mode: pass the partials as its address

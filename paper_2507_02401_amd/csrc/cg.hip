@@ -41,17 +41,6 @@ struct CgScal {
   float pad_[2];
 };
 
-// Compensated accumulation (Neumaier): s + c holds the sum.
-struct KSum {
-  float s = 0.f, c = 0.f;
-  DEVI void add(float v) {
-    const float t = s + v;
-    c += fabsf(s) >= fabsf(v) ? (s - t) + v : (v - t) + s;
-    s = t;
-  }
-  DEVI float value() const { return s + c; }
-};
-
 // Sum of one value per thread over the work-group, pairwise (fixed order); thread 0 gets it.
 DEVI float wg_sum(float v) {
   __shared__ float part[kCgThreads / 64];

@@ -50,8 +50,9 @@ struct Task {
   int32_t flags;       // kNorm*: squared-norm mode of the full-bank analysis kernels
 };
 // Squared-norm mode (FB_DOWN / FB_DOWN_S / full-bank coarse analysis): the weighted coefficients
-// are summed as squares instead of stored; each work-group writes its partial sum (double) to
-// ((double*)out0)[work-group index within the task] (tail: ((double*)out)[instance]).
+// are summed as squares instead of stored; each work-group writes its partial sum, a compensated
+// FP32 pair (leading part, remainder), to ((float2*)out0)[work-group index within the task]
+// (tail: ((float2*)out)[instance]).
 constexpr int32_t kNormSq = 1;   // detail bands are summed, not stored
 constexpr int32_t kNormLL = 2;   // the approximation output is final: summed, not stored
 
@@ -205,17 +206,18 @@ hipError_t launch_block_copy(const float* src, float* dst, const int b[3], const
 hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t stream);
 
 // Squared-norm finalisation: out[b] = sum over segments k of partials[off_k + b*per_k + t],
-// t < per_k, in a fixed order (deterministic).  kMaxNormSegs segments at most.
+// t < per_k (compensated pairs, in units of pairs), in a fixed order (deterministic), rounded to
+// FP32.  kMaxNormSegs segments at most.
 constexpr int kMaxNormSegs = 40;
 struct NormSegs {
   int64_t off[kMaxNormSegs];
   int32_t per[kMaxNormSegs];
   int32_t count;
 };
-hipError_t launch_norm_finalize(const double* partials, const NormSegs& segs, double* out, int64_t batch,
+hipError_t launch_norm_finalize(const float2* partials, const NormSegs& segs, float* out, int64_t batch,
                                 hipStream_t stream);
 // Sum of squares of each of `batch` contiguous instances of n floats (identity transform).
-hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, double* out, hipStream_t stream);
+hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, float* out, hipStream_t stream);
 
 // Host filter derivation (filters.cpp).
 bool daubechies_filter(int order, double* h_out);

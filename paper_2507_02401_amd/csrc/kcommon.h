@@ -52,21 +52,53 @@ DEVI void gather_to_lds(int n, Src src, Dst dst) {
   }
 }
 
-// Sum of one value per thread over the work-group, in a fixed order (wave reduction, then the
-// waves in index order); thread 0 stores it.  Every thread of the work-group must call it.
+// Error-free sum of two floats (Knuth's TwoSum): s + e == a + b exactly, s = fl(a + b).
+DEVI void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated FP32 accumulation (Neumaier's variant of Kahan summation): s + c holds the sum.
+struct KSum {
+  float s = 0.f, c = 0.f;
+  DEVI void add(float v) {
+    const float t = s + v;
+    c += fabsf(s) >= fabsf(v) ? (s - t) + v : (v - t) + s;
+    s = t;
+  }
+  // adds another compensated sum: the two leading parts exactly, the compensations plainly
+  DEVI void merge(float os, float oc) {
+    float t, e;
+    two_sum(s, os, t, e);
+    s = t;
+    c += oc + e;
+  }
+  DEVI float value() const { return s + c; }
+};
+
+// Sum of one compensated sum per thread over the work-group, in a fixed order (pairwise over
+// the lanes of each wave, then the waves in index order); thread 0 stores it as a pair
+// (leading part, remainder), normalised so that the leading part is the rounded sum.  Every
+// thread of the work-group must call it.
 template <int NT>
-DEVI void store_wg_sum(double v, double* dst) {
-  __shared__ double part[NT / 64];
+DEVI void store_wg_sum(KSum v, float2* dst) {
+  __shared__ float2 part[NT / 64];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  for (int o = 32; o > 0; o >>= 1) {
+    const float os = __shfl_down(v.s, o, 64), oc = __shfl_down(v.c, o, 64);
+    v.merge(os, oc);
+  }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) part[w] = v;
+  if (lane == 0) part[w] = make_float2(v.s, v.c);
   __syncthreads();
   if (threadIdx.x == 0) {
-    double tsum = 0.0;
+    KSum t = {part[0].x, part[0].y};
 #pragma unroll
-    for (int i = 0; i < NT / 64; ++i) tsum += part[i];
-    *dst = tsum;
+    for (int i = 1; i < NT / 64; ++i) t.merge(part[i].x, part[i].y);
+    float hi, lo;
+    two_sum(t.s, t.c, hi, lo);
+    *dst = make_float2(hi, lo);
   }
 }
 

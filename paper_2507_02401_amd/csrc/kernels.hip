@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
   for (int j = 0; j < H; ++j)
 #pragma unroll
     for (int u = 0; u < QT; ++u) alo[j][u] = ahi[j][u] = 0.f;
-  float nsq = 0.f;  // squared-norm mode: this thread's sum
+  KSum nsq;  // squared-norm mode: this thread's compensated sum
 
   for (int p = 0; p < NP; ++p) {
     if constexpr (VEC) {
@@ -388,14 +388,14 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
           // band (e0, e1, e2) at half-res position (g0, g1, g2)
           const float lo = alo[H - 1][u], hi = ahi[H - 1][u];
           if ((e1 | e2) == 0) {
-            if (t.flags & kNormLL) nsq = fmaf(beta * lo, beta * lo, nsq);
+            if (t.flags & kNormLL) nsq.add((beta * lo) * (beta * lo));
             else gst(ll + g0 * t.st_out1[0] + g1 * t.st_out1[1] + g2, beta * lo);
           } else if (t.flags & kNormSq) {
-            nsq = fmaf(alpha * lo, alpha * lo, nsq);
+            nsq.add((alpha * lo) * (alpha * lo));
           } else {
             gst(coef + g0 * t.st_out0[0] + (e1 * h1 + g1) * t.st_out0[1] + e2 * h2 + g2, alpha * lo);
           }
-          if (t.flags & kNormSq) nsq = fmaf(alpha * hi, alpha * hi, nsq);
+          if (t.flags & kNormSq) nsq.add((alpha * hi) * (alpha * hi));
           else gst(coef + (h0 + g0) * t.st_out0[0] + (e1 * h1 + g1) * t.st_out0[1] + e2 * h2 + g2, alpha * hi);
         }
       }
@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
 #pragma unroll
     for (int u = 0; u < QT; ++u) alo[0][u] = ahi[0][u] = 0.f;
   }
-  if (t.flags & kNormSq) store_wg_sum<NT>(nsq, reinterpret_cast<double*>(t.out0) + (wg - t.tile_begin));
+  if (t.flags & kNormSq) store_wg_sum<NT>(nsq, reinterpret_cast<float2*>(t.out0) + (wg - t.tile_begin));
 }
 
 // FB_UP_S: full-res output tile U1 x U2 in-plane, R output slices (R even).  Output pair Q (full-
@@ -632,15 +632,15 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
 
   const int n0h = b0 >> 1, n1h = b1 >> 1, n2h = b2 >> 1;
   const float alpha = t.alpha, beta = t.beta;
-  float nsq = 0.f;  // squared-norm mode: this thread's sum
+  KSum nsq;  // squared-norm mode: this thread's compensated sum
   // write one coefficient of band (e0,e1,e2) at half-res position (g0,g1,g2)
   auto emit = [&](int e0, int e1, int e2, int g0, int g1, int g2, float v) {
     if (g0 >= (D >= 3 ? n0h : 1) || g1 >= (D >= 2 ? n1h : 1) || g2 >= n2h) return;
     if ((e0 | e1 | e2) == 0) {
-      if (t.flags & kNormLL) nsq = fmaf(beta * v, beta * v, nsq);
+      if (t.flags & kNormLL) nsq.add((beta * v) * (beta * v));
       else gst(ll + (D >= 3 ? g0 * t.st_out1[0] : 0) + (D >= 2 ? g1 * t.st_out1[1] : 0) + g2, beta * v);
     } else if (t.flags & kNormSq) {
-      nsq = fmaf(alpha * v, alpha * v, nsq);
+      nsq.add((alpha * v) * (alpha * v));
     } else {
       const int r0 = e0 * n0h + g0, r1 = e1 * n1h + g1, r2 = e2 * n2h + g2;
       gst(coef + (D >= 3 ? r0 * t.st_out0[0] : 0) + (D >= 2 ? r1 * t.st_out0[1] : 0) + r2, alpha * v);
@@ -694,7 +694,7 @@ __global__ void __launch_bounds__(NT) k_fb_down(TaskArgs args, Filter f) {
           emit(1, e1, e2, g0, g1, g2, hi);
         });
   }
-  if (t.flags & kNormSq) store_wg_sum<NT>(nsq, reinterpret_cast<double*>(t.out0) + (wg - t.tile_begin));
+  if (t.flags & kNormSq) store_wg_sum<NT>(nsq, reinterpret_cast<float2*>(t.out0) + (wg - t.tile_begin));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1137,16 +1137,16 @@ __global__ void __launch_bounds__(kFbCoarseThreads) k_fb_coarse(TailArgs args, F
       }
     }
     const bool norm = (tp->flags & kNormSq) != 0;
-    float nsq = 0.f;
+    KSum nsq;
     for (int e = threadIdx.x; e < B; e += blockDim.x) {
       int c0, c1, c2;
       split3(e, n1, n2, l1, l2, c0, c1, c2);
       const float w = fbc_weight(tp->coef, nl, n0, n1, n2, c0, c1, c2, D);
       const float v = w * sm[CUR + e];
-      if (norm) nsq = fmaf(v, v, nsq);
+      if (norm) nsq.add(v * v);
       else gst(out + (D >= 3 ? c0 * out0 : 0) + (D >= 2 ? c1 * out1 : 0) + c2, v);
     }
-    if (norm) store_wg_sum<kFbCoarseThreads>(nsq, reinterpret_cast<double*>(tp->out) + inst);
+    if (norm) store_wg_sum<kFbCoarseThreads>(nsq, reinterpret_cast<float2*>(tp->out) + inst);
   } else {
     gather_to_lds<kFbCoarseThreads, U>(
         B,
@@ -1284,27 +1284,35 @@ namespace {
 // (kind, ndim, variant, taps) -> tile.  Variant 0 = wide, 1 = narrow (thin or small blocks).
 // Analysis kinds: half-res output tile per band; synthesis kinds: full-res output tile.
 // Squared-norm finalisation: one work-group per instance, segments in order, each segment's
-// partials strided over the threads, then the work-group sum (fixed order: deterministic).
-__global__ void __launch_bounds__(256) k_norm_finalize(const double* __restrict__ partials, NormSegs segs,
-                                                       double* __restrict__ out) {
+// partials (compensated pairs) strided over the threads, then the work-group sum (fixed order:
+// deterministic); the instance's norm is the rounded sum.
+__global__ void __launch_bounds__(256) k_norm_finalize(const float2* __restrict__ partials, NormSegs segs,
+                                                       float* __restrict__ out) {
+  __shared__ float2 sum;
   const int b = blockIdx.x;
-  double acc = 0.0;
+  KSum acc;
   for (int k = 0; k < segs.count; ++k) {
-    const double* p = partials + segs.off[k] + (int64_t)b * segs.per[k];
-    for (int i = threadIdx.x; i < segs.per[k]; i += 256) acc += p[i];
+    const float2* p = partials + segs.off[k] + (int64_t)b * segs.per[k];
+    for (int i = threadIdx.x; i < segs.per[k]; i += 256) {
+      const float2 v = p[i];
+      acc.merge(v.x, v.y);
+    }
   }
-  store_wg_sum<256>(acc, out + b);
+  store_wg_sum<256>(acc, &sum);
+  if (threadIdx.x == 0) out[b] = sum.x;
 }
 
 // Sum of squares of each instance (levels = 0: the transform is the identity).
-__global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ x, int64_t n, double* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_sumsq(const float* __restrict__ x, int64_t n, float* __restrict__ out) {
+  __shared__ float2 sum;
   const float* p = x + (int64_t)blockIdx.x * n;
-  double acc = 0.0;
+  KSum acc;
   for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double v = gld(p + i);
-    acc += v * v;
+    const float v = gld(p + i);
+    acc.add(v * v);
   }
-  store_wg_sum<256>(acc, out + blockIdx.x);
+  store_wg_sum<256>(acc, &sum);
+  if (threadIdx.x == 0) out[blockIdx.x] = sum.x;
 }
 
 
@@ -1467,14 +1475,14 @@ hipError_t launch_block_copy(const float* src, float* dst, const int b[3], const
   return hipGetLastError();
 }
 
-hipError_t launch_norm_finalize(const double* partials, const NormSegs& segs, double* out, int64_t batch,
+hipError_t launch_norm_finalize(const float2* partials, const NormSegs& segs, float* out, int64_t batch,
                                 hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_norm_finalize, dim3((unsigned)batch), dim3(256), 0, s, partials, segs, out);
   return hipGetLastError();
 }
 
-hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, double* out, hipStream_t s) {
+hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, float* out, hipStream_t s) {
   if (batch <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_sumsq, dim3((unsigned)batch), dim3(256), 0, s, x, n, out);
   return hipGetLastError();

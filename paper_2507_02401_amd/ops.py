@@ -82,13 +82,14 @@ def matern_sample(xi, ndim, order, levels, s, out=None, workspace=None):
 
 
 def hs_norm_sq(x, ndim, order, levels, s, workspace=None):
-    """||x||^2_{H^s} per instance (float64 tensor of the batch shape): sum of 2^{2sj} c^2 over
-    the orthonormal wavelet coefficients c = W x, summed on the GPU without storing c."""
+    """||x||^2_{H^s} per instance (float32 tensor of the batch shape): sum of 2^{2sj} c^2 over
+    the orthonormal wavelet coefficients c = W x, summed on the GPU (compensated FP32) without
+    storing c."""
     grid, batch = _split(x, ndim)
     x = x.contiguous()
     lib = load()
     shp = shape_arg(grid)
-    out = torch.empty(batch, dtype=torch.float64, device=x.device)
+    out = torch.empty(batch, dtype=torch.float32, device=x.device)
     need = int(lib.es_hs_norm_workspace_bytes(ndim, shp, batch, int(order), int(levels)))
     ws = _ws(need, x.device, workspace)
     with torch.cuda.device(x.device):

@@ -24,8 +24,8 @@ hipError_t launch_tail(int, int, int, const TailArgs&, int, size_t, const Filter
 hipError_t launch_plain_pass(const PlainPass&, int, const Filter&, hipStream_t) { abort(); }
 hipError_t launch_block_copy(const float*, float*, const int*, const int*, const int*, hipStream_t) { abort(); }
 hipError_t launch_copy(const float*, float*, int64_t, hipStream_t) { abort(); }
-hipError_t launch_norm_finalize(const double*, const NormSegs&, double*, int64_t, hipStream_t) { abort(); }
-hipError_t launch_sumsq(const float*, int64_t, int64_t, double*, hipStream_t) { abort(); }
+hipError_t launch_norm_finalize(const float2*, const NormSegs&, float*, int64_t, hipStream_t) { abort(); }
+hipError_t launch_sumsq(const float*, int64_t, int64_t, float*, hipStream_t) { abort(); }
 hipError_t launch_persist(int, int, const PArgs&, int, hipStream_t) { abort(); }
 int persist_resident_groups(int, int) { abort(); }
 hipError_t launch_zero_ints(int32_t*, int64_t, hipStream_t) { abort(); }

@@ -137,6 +137,7 @@ def test_norm_workspace_and_validation(lib):
     x, o, w = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 32)
     assert lib.es_hs_norm_sq(2, shp, 3, 4, 7, 1.0, x, o, w, need, None) == 1  # 64 not divisible by 2^7
     assert lib.es_hs_norm_sq(2, shp, 3, 4, 3, 1.0, ctypes.c_void_p((1 << 20) + 4), o, w, need, None) == 1  # misaligned
+    assert lib.es_hs_norm_sq(2, shp, 3, 4, 3, 1.0, x, ctypes.c_void_p((1 << 30) + 2), w, need, None) == 1  # misaligned
     assert lib.es_hs_norm_sq(2, shp, 3, 4, 3, 1.0, x, o, w, need - 1, None) == 2  # workspace too small
     assert lib.es_hs_norm_sq(2, shp, 3, 4, 3, 1.0, x, o, None, 0, None) == 2
     assert lib.es_hs_norm_sq(2, shp, 0, 4, 3, 1.0, None, None, None, 0, None) == 0  # empty batch
