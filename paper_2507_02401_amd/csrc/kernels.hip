@@ -37,112 +37,16 @@ __global__ void __launch_bounds__(NT) k_lp_down(TaskArgs args, Filter f) {
 }
 
 // ---------------------------------------------------------------------------------------
-// LP_DOWN_S (2-D): a_out = A a_in, streamed along axis 1.  A work-group owns a strip of T2 output
-// columns and a run of R output rows.  It visits the input rows of the run in chunks of 2 RB
-// (with the next chunk's 16-byte loads in flight while the current one is filtered), filters
-// each row along axis 2 once into a ring of the last 2 RB + L - 2 filtered rows, and forms RB
-// output rows per chunk from the ring along axis 1.  Input rows are read once per run (plus
-// L - 2 at its start) instead of once per tile row; the arithmetic per output is that of
-// k_lp_down, so both give identical results.
+// LP_DOWN_S (2-D): a_out = A a_in, streamed along axis 1 (body: lp_down_stream).  A work-group
+// owns a strip of T2 output columns and a run of R output rows; input rows are read once per
+// run (plus L - 2 at its start) and filtered along axis 2 once, instead of once per tile row.
 template <int L, int R, int T2, int NT, bool VEC>
 __global__ void __launch_bounds__(NT) k_lp_down_s(TaskArgs args, Filter f) {
-  constexpr int RB = 4, CR = 2 * RB;     // output rows / input rows per chunk
-  constexpr int W = CR + L - 2;          // ring rows
-  constexpr int NC = (2 * R + L - 2 + CR - 1) / CR;
-  constexpr int I2 = 2 * T2 + L - 2, I2P = (I2 + 3) & ~3, NV = I2P / 4;
-  constexpr int P = 4, NCH = T2 / P;     // row pass: P outputs per task
-  constexpr int CPT = NT / T2 > 0 ? NT / T2 : 1, RPT = RB / CPT;  // column pass: threads per column, rows per thread
-  static_assert(T2 % P == 0 && RB % CPT == 0, "tile shape");
-  __shared__ __attribute__((aligned(16))) float s_in[CR * I2P];
-  __shared__ float s_ring[W * T2];
-  __shared__ int s_row[NC * CR];
-  __shared__ int s_col[NV];
-
+  __shared__ LpDownStreamSmem<L, R, T2, kStreamRows> sm;
   const int wg = logical_wg(args.total_wg, args.reverse);
   if (wg < 0) return;
   const Task t = pick_task<Task>(args, wg);
-  const Tile tl = decode_tile(t, wg);
-  const float* __restrict__ src = t.in0 + tl.inst * t.bs_in0;
-  float* __restrict__ dst = t.out0 + tl.inst * t.bs_out0;
-  const int b1 = t.b[1], b2 = t.b[2];
-  const int h1 = b1 >> 1, h2 = b2 >> 1;
-  const int k0 = R * tl.c1, o2 = 2 * T2 * tl.c2;
-
-  for (int i = threadIdx.x; i < NC * CR; i += NT) s_row[i] = pmod(2 * k0 + i, b1) * t.st_in0[1];
-  for (int i = threadIdx.x; i < NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
-  __syncthreads();
-
-  constexpr int NLD = CR * NV, ITL = (NLD + NT - 1) / NT;
-  float4 pf[VEC ? ITL : 1];
-  auto load_chunk = [&](int c) {
-#pragma unroll
-    for (int it = 0; it < ITL; ++it) {
-      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
-      pf[it] = gld4(src + s_row[c * CR + q / NV] + s_col[q % NV]);
-    }
-  };
-  if constexpr (VEC) load_chunk(0);
-
-  for (int c = 0; c < NC; ++c) {
-    if constexpr (VEC) {
-      float4* d4 = reinterpret_cast<float4*>(s_in);  // row length I2P = 4 NV: LDS slot = load index
-#pragma unroll
-      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
-      __syncthreads();
-      load_chunk(min(c + 1, NC - 1));
-    } else {
-      stage_rows<NT, CR, NV, false>(src, s_row + c * CR, s_col, s_in, I2P, b2);
-      __syncthreads();
-    }
-    // axis 2: the chunk's rows into their ring slots
-    const int sb = (c * CR) % W;
-    for (int task = threadIdx.x; task < CR * NCH; task += NT) {
-      const int ch = task % NCH, r = task / NCH;
-      constexpr int WN = 2 * P + L - 2, W4 = (WN + 3) / 4;
-      const float4* p4 = reinterpret_cast<const float4*>(s_in + r * I2P + 2 * P * ch);
-      float win[4 * W4];
-#pragma unroll
-      for (int v = 0; v < W4; ++v) {
-        const float4 x = p4[v];
-        win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
-      }
-      const int slot = sb + r >= W ? sb + r - W : sb + r;
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        float a = 0.f;
-#pragma unroll
-        for (int tt = 0; tt < L; ++tt) a = fmaf(f.h[tt], win[2 * q + tt], a);
-        s_ring[slot * T2 + P * ch + q] = a;
-      }
-    }
-    __syncthreads();
-    // axis 1: outputs kb .. kb+RB-1 of the run from ring rows 2 kb .. 2 kb + W - 1
-    const int kb = RB * c - (L / 2 - 1);
-    if (kb + RB > 0) {
-      const int rb = pmod(2 * kb, W);
-      for (int task = threadIdx.x; task < T2 * CPT; task += NT) {
-        const int col = task % T2, part = task / T2;
-        constexpr int WC = 2 * RPT + L - 2;
-        float win[WC];
-#pragma unroll
-        for (int j = 0; j < WC; ++j) {
-          int sl = rb + 2 * RPT * part + j;
-          sl = sl >= W ? sl - W : sl;
-          sl = sl >= W ? sl - W : sl;
-          win[j] = s_ring[sl * T2 + col];
-        }
-        const int g2 = T2 * tl.c2 + col;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-          float a = 0.f;
-#pragma unroll
-          for (int tt = 0; tt < L; ++tt) a = fmaf(f.h[tt], win[2 * r + tt], a);
-          const int k = kb + RPT * part + r;
-          if (k >= 0 && k < R && k0 + k < h1 && g2 < h2) gst(dst + (k0 + k) * h2 + g2, a);
-        }
-      }
-    }
-  }
+  lp_down_stream<L, R, T2, kStreamRows, NT, VEC>(t, wg, f, sm);
 }
 
 template <int D, int L, int U0, int U1, int U2, int NT, bool VEC>

@@ -95,6 +95,130 @@ DEVI void lp_down_tile(const Task& t, int wg, const Filter& f, LpDownSmem<D, L, 
 }
 
 // ---------------------------------------------------------------------------------------
+// LP_DOWN streamed along axis 1 (2-D): a_out = A a_in for a strip of T2 output columns and a
+// run of R output rows per work-group.  The run's input rows are visited in chunks of CR = 2 RB
+// rows; each row is filtered along axis 2 exactly once, into a ring holding the last W = CR + L - 2
+// filtered rows (the rows that RB output rows read), and RB output rows are formed per chunk from
+// the ring along axis 1.  Every ring row but the last is also written W rows further on (a
+// mirror), so a window of up to W consecutive ring rows never wraps and is read at fixed offsets.
+// The next chunk's 16-byte loads are in flight while the current chunk is filtered.  The
+// arithmetic per output is that of lp_down_tile (axis 2, then axis 1, taps in order), so both
+// give identical results.
+template <int L, int R, int T2, int RB>
+struct LpDownStreamGeom {
+  static constexpr int CR = 2 * RB;                          // input rows per chunk
+  static constexpr int W = CR + L - 2;                       // ring rows the outputs of a chunk read
+  static constexpr int NRING = 2 * W - 1;                    // with the mirror
+  static constexpr int NC = (2 * R + L - 2 + CR - 1) / CR;   // chunks of a run
+  static constexpr int I2 = 2 * T2 + L - 2;
+  static constexpr int I2P = (I2 + 3) & ~3;
+  static constexpr int NV = I2P / 4;
+};
+
+template <int L, int R, int T2, int RB>
+struct LpDownStreamSmem {
+  using G = LpDownStreamGeom<L, R, T2, RB>;
+  alignas(16) float s_in[G::CR * G::I2P];
+  alignas(16) float s_ring[G::NRING * T2];
+  int s_row[G::NC * G::CR];
+  int s_col[G::NV];
+};
+
+template <int L, int R, int T2, int RB, int NT, bool VEC>
+DEVI void lp_down_stream(const Task& t, int wg, const Filter& f, LpDownStreamSmem<L, R, T2, RB>& sm) {
+  using G = LpDownStreamGeom<L, R, T2, RB>;
+  constexpr int CR = G::CR, W = G::W, NC = G::NC, I2P = G::I2P, NV = G::NV;
+  constexpr int P = 4, NCH = T2 / P;              // axis-2 pass: P outputs per task
+  constexpr int CPT = NT / T2 > 0 ? NT / T2 : 1;  // axis-1 pass: tasks per column
+  constexpr int RPT = RB / CPT;                   // output rows per axis-1 task
+  constexpr int WC = 2 * RPT + L - 2;             // ring rows one axis-1 task reads
+  static_assert(T2 % P == 0 && RB % CPT == 0 && RPT >= 1 && WC <= W, "tile shape");
+  float* s_in = sm.s_in;
+  float* s_ring = sm.s_ring;
+  int* s_row = sm.s_row;
+  int* s_col = sm.s_col;
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ src = t.in0 + tl.inst * t.bs_in0;
+  float* __restrict__ dst = t.out0 + tl.inst * t.bs_out0;
+  const int b1 = t.b[1], b2 = t.b[2];
+  const int h1 = b1 >> 1, h2 = b2 >> 1;
+  const int k0 = R * tl.c1, o2 = 2 * T2 * tl.c2;
+  for (int i = threadIdx.x; i < NC * CR; i += NT) s_row[i] = pmod(2 * k0 + i, b1) * t.st_in0[1];
+  for (int i = threadIdx.x; i < NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
+  __syncthreads();
+
+  constexpr int NLD = CR * NV, ITL = (NLD + NT - 1) / NT;
+  float4 pf[VEC ? ITL : 1];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
+      pf[it] = gld4(src + s_row[c * CR + q / NV] + s_col[q % NV]);
+    }
+  };
+  if constexpr (VEC) load_chunk(0);
+
+  for (int c = 0; c < NC; ++c) {
+    if constexpr (VEC) {
+      float4* d4 = reinterpret_cast<float4*>(s_in);  // row length I2P = 4 NV: LDS slot = load index
+#pragma unroll
+      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
+      __syncthreads();
+      if (c + 1 < NC) load_chunk(c + 1);
+    } else {
+      stage_rows<NT, CR, NV, false>(src, s_row + c * CR, s_col, s_in, I2P, b2);
+      __syncthreads();
+    }
+    // axis 2: the chunk's rows into their ring slots (and mirrors)
+    const int sb = (c * CR) % W;
+    for (int task = threadIdx.x; task < CR * NCH; task += NT) {
+      const int ch = task % NCH, r = task / NCH;
+      constexpr int WN = 2 * P + L - 2, W4 = (WN + 3) / 4;
+      const float4* p4 = reinterpret_cast<const float4*>(s_in + r * I2P + 2 * P * ch);
+      float win[4 * W4];
+#pragma unroll
+      for (int v = 0; v < W4; ++v) {
+        const float4 x = p4[v];
+        win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
+      }
+      float a[P];
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        a[q] = 0.f;
+#pragma unroll
+        for (int tt = 0; tt < L; ++tt) a[q] = fmaf(f.h[tt], win[2 * q + tt], a[q]);
+      }
+      const float4 o = make_float4(a[0], a[1], a[2], a[3]);
+      const int slot = sb + r >= W ? sb + r - W : sb + r;
+      *reinterpret_cast<float4*>(s_ring + slot * T2 + P * ch) = o;
+      if (slot < W - 1) *reinterpret_cast<float4*>(s_ring + (slot + W) * T2 + P * ch) = o;
+    }
+    __syncthreads();
+    // axis 1: output rows kb .. kb + RB - 1 of the run (input rows 2 kb .. 2 kb + W - 1)
+    const int kb = RB * c - (L / 2 - 1);
+    if (kb + RB > 0) {
+      for (int task = threadIdx.x; task < T2 * CPT; task += NT) {
+        const int col = task % T2, part = task / T2;
+        const int kp = kb + RPT * part;
+        const float* rp = s_ring + pmod(2 * kp, W) * T2 + col;
+        float win[WC];
+#pragma unroll
+        for (int j = 0; j < WC; ++j) win[j] = rp[j * T2];
+        const int g2 = T2 * tl.c2 + col;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+          float a = 0.f;
+#pragma unroll
+          for (int tt = 0; tt < L; ++tt) a = fmaf(f.h[tt], win[2 * r + tt], a);
+          const int k = kp + r;
+          if (k >= 0 && k < R && k0 + k < h1 && g2 < h2) gst(dst + (k0 + k) * h2 + g2, a);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // LP_UP: out = alpha*same + beta*(A^T z) on a (U0,U1,U2) full-resolution tile.
 
 // LDS of one LP_UP tile.

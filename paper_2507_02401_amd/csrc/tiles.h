@@ -12,7 +12,7 @@ struct Shape3 {
 constexpr Shape3 shape_of(int K, int D, int V, int L) {
   // V: 0 wide, 1 narrow, 2 medium
   if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 32, 64} : Shape3{1, 32, 128});
-  if (K == K_LP_DOWN_S) return V == 0 ? Shape3{1, 64, 256} : (V == 1 ? Shape3{1, 16, 128} : Shape3{1, 32, 256});
+  if (K == K_LP_DOWN_S) return V == 0 ? Shape3{1, 64, 64} : (V == 1 ? Shape3{1, 16, 64} : Shape3{1, 32, 64});
   if (K == K_FB_DOWN_S) return V == 0 ? Shape3{16, 8, 32} : (V == 1 ? Shape3{8, 8, 16} : Shape3{8, 8, 32});
   if (K == K_FB_UP_S) return V == 0 ? Shape3{16, 16, 32} : (V == 1 ? Shape3{8, 8, 32} : Shape3{8, 16, 32});
   if (D == 1) {
@@ -42,6 +42,9 @@ constexpr Shape3 shape_of(int K, int D, int V, int L) {
 }
 constexpr int kThreads = 256;       // threads of every level-kernel work-group
 
+// Output rows per chunk of the streamed 2-D low-pass analysis kernel (measured on 64 x 1024^2 and
+// 64 x 512^2 db8 levels against 4 and 16, with strips of 64, 128 and 256 columns).
+constexpr int kStreamRows = 8;
 constexpr int kCoarseThreads = 1024;    // low-pass coarse kernel
 constexpr int kFbCoarseThreads = 1024;  // full-bank coarse kernels
 
