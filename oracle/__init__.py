@@ -30,6 +30,13 @@ Pinning status (see tests/test_oracle_*.py):
                     form, aliased wave numbers included), a point-by-point DFT
                     sum on tiny grids and its invariants (identity at s = 0,
                     semigroup, symmetry, shift equivariance).
+  * symmetric-extension transform and W^{-1} D W (Sec. 4: MATLAB's transform,
+                    band lengths in a book-keeping matrix) -- pinned by the periodic
+                    transform of the mirrored signal (analysis) and of zero-padded
+                    coefficients (synthesis), the Haar hand example, perfect
+                    reconstruction, dense W^{-1} W = I, equality with the periodic
+                    operator for Haar on dyadic sides, identities at s = 0 and for
+                    constants, and the low-pass recurrence;
   The absolute Matern scale constant of Cor. 4.3 is not part of the path and
   is not implemented (parity unpinned; the constant is dropped as Remark 3.3
   allows).
@@ -40,6 +47,7 @@ from .dwt import analysis_axis, synthesis_axis, dwt, idwt, level_weights, weight
 from .ops import es_adjoint, es_apply, matern_cov_apply, matern_sample, hs_norm_sq
 from .solver import tikhonov_solve
 from .fourier import fft_cov_apply, fourier_multiplier
+from .symdwt import sym_cov_apply, sym_dwt, sym_idwt, sym_lengths
 from . import dense
 
 __all__ = [
