@@ -680,6 +680,27 @@ def main():
             "rel_l2_vs_fp64_oracle_image5": None,
             "period": 1.0}
         del fws
+        # non-periodic (symmetric-extension) transform of the same batch: W^{-1} D_2s W
+        print("[bench] non-periodic transform", file=sys.stderr, flush=True)
+        sws = torch.empty(max(1, lib.es_sym_workspace_bytes(2, shp, IMAGES, ORDER, LEVELS)), dtype=torch.uint8,
+                          device=dev)
+        tsym = _time(lambda: es.sym_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=sws), torch, reps)
+        pending["sym"] = es.sym_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=sws)[i_s].double().cpu().numpy()
+        lens = [SIDE] + es.sym_band_lengths(SIDE, ORDER, LEVELS)
+        area = [IMAGES * v * v for v in lens]
+        # schedule bytes: each down level reads a_{i-1} and writes a_i; each up level reads z = a_j and
+        # same = a_{j-1} and writes a_{j-1} (y at the last)
+        sched = 4 * (sum(area[i - 1] + area[i] for i in range(1, LEVELS))
+                     + sum(area[j] + 2 * area[j - 1] for j in range(1, LEVELS)))
+        result["sym_cov_apply"] = {
+            "ms": round(1e3 * tsym, 4), "voxels_per_s": round(voxels / tsym, 1),
+            "effective_GBps": round(8.0 * voxels / tsym / 1e9, 1),
+            "frac_of_hbm_peak_whole_op": round(8.0 * voxels / tsym / 1e9 / HBM_PEAK_GBPS, 4),
+            "schedule_bytes": sched, "schedule_GBps": round(sched / tsym / 1e9, 1),
+            "band_lengths": lens[1:], "launches": 2 * (LEVELS - 1),
+            "periodic_cov_ms": round(1e3 * elapsed / args.steps, 4),
+            "rel_l2_vs_fp64_oracle_image5": None}
+        del sws
         result["other_workloads"] = other_workloads(args, es, inputs, torch, np)
 
     if not args.no_plain:
@@ -707,6 +728,15 @@ def main():
             result["hs_norm_sq"]["rel_err_vs_fp64_oracle_image5"] = abs(pending["norm"] - nref) / nref
         if "fft" in pending:
             result["fft_cov_apply"]["rel_l2_vs_fp64_oracle_image5"] = rel_l2(pending["fft"], oracle.fft_cov_apply(xs, 2, S))
+        if "sym" in pending:
+            from oracle import symdwt
+            t0 = time.perf_counter()
+            sref = symdwt.sym_cov_apply(xs, ORDER, LEVELS, S)
+            tso = time.perf_counter() - t0
+            result["sym_cov_apply"]["rel_l2_vs_fp64_oracle_image5"] = rel_l2(pending["sym"], sref)
+            result["sym_cov_apply"]["cpu_oracle"] = {
+                "voxels_per_s": round(SIDE * SIDE / tso, 1), "cores": 1, "sample": "image 5, one thread",
+                "gpu_over_cpu": round(result["sym_cov_apply"]["voxels_per_s"] / (SIDE * SIDE / tso), 1)}
         # one image at a time in this thread, then the whole batch over a pool of threads (numpy
         # releases the interpreter lock inside its array operations); the oracle is unchanged
         from concurrent.futures import ThreadPoolExecutor

@@ -195,6 +195,33 @@ es_status es_fft_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, 
 /* Waits for every device that holds cached plans and destroys them. */
 es_status es_fft_release_plans(void);
 
+/* ---- non-periodic transform (Sec. 4, the fast wavelet transform with band lengths l(i)) ---- */
+
+/* y_b = W^{-1} D_{2s} W x_b with W the non-periodic DWT of depth `levels` that Sec. 4 evaluates
+ * with MATLAB's fast wavelet transform: half-point symmetric extension (the signal mirrored about
+ * its ends, end samples repeated), one step of a length-n axis keeping
+ *     a[k] = sum_t h[t] x_ext[2k + t - (L-2)],  d[k] = sum_t g[t] x_ext[2k + t - (L-2)],
+ *     k < l = floor((n + L - 1) / 2)   (the book-keeping lengths, es_sym_band_lengths),
+ * separable over the axes of the approximation block, and W^{-1} its left inverse (keeps the
+ * central n samples of the upsampled, filtered bands; not W^T: the transform is redundant and not
+ * orthogonal, so the operator is not symmetric).  D weights detail level i by 2^{-2s(m-i)} and the
+ * approximation by 1, as for matern_cov_apply.  Only the all-low band of each level is formed (the
+ * projection form, exact because the synthesis halves S_a, S_d satisfy S_a A + S_d B = I).
+ *   ndim, shape  1..3 axes, every side in 1..2^30 (any length; no divisibility condition); every
+ *                level at most 2^31-1 elements per instance (levels may grow for sides < L - 1).
+ *   order 1..8, levels 0..30 (levels <= 1 give the identity), s finite, any sign.
+ *   x, y         device, batch * prod(shape) floats, 16-byte aligned, must not overlap.
+ *   ws           device, es_sym_workspace_bytes(...) bytes (the arrays a_1 .. a_{m-1}), 256-byte
+ *                aligned, may be NULL when that size is 0.
+ * Errors: ES_EINVAL (arguments, overlap, alignment), ES_EWORKSPACE, ES_EUNSUPPORTED, ES_EDEVICE;
+ * all checks on the host before any launch.  Asynchronous on `stream`. */
+es_status es_sym_cov_apply(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                           const float* x, float* y, void* ws, size_t ws_bytes, void* stream);
+/* Workspace bytes of es_sym_cov_apply (0 for invalid arguments or batch <= 0). */
+size_t es_sym_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
+/* Band lengths l_1 .. l_levels of one axis of length n (host array of `levels` entries). */
+es_status es_sym_band_lengths(int64_t n, int order, int levels, int64_t* lengths);
+
 /* ---- ragged batches: many geometries in one captured launch sequence ------------------ */
 
 typedef struct {

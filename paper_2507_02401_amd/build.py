@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libeswave.so")
-SOURCES = ["kernels.hip", "persist.hip", "api.cpp", "filters.cpp", "spectral.hip", "noalloc.cpp", "cg.hip"]
+SOURCES = ["kernels.hip", "persist.hip", "api.cpp", "filters.cpp", "spectral.hip", "noalloc.cpp", "cg.hip", "symmetric.hip"]
 ARCH = "gfx950"
 ROCM_LIB = "/opt/rocm/lib"
 

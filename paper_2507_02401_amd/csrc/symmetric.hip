@@ -1,0 +1,551 @@
+// Non-periodic realisation of E_s^* = W^{-1} D W (Sec. 4): the fast wavelet transform that the
+// paper evaluates with MATLAB's routines, whose default boundary handling is half-point symmetric
+// extension and whose band lengths l(i) shrink per level and are kept in a book-keeping matrix.
+//
+// One analysis step of a length-n axis mirrors the signal about its ends, repeating the end
+// samples (x_ext[-1-j] = x[j], x_ext[n+j] = x[n-1-j]; period 2n), and keeps
+//   a[k] = sum_t h[t] x_ext[2k + t - (L-2)],   k < l = floor((n + L - 1) / 2),
+// and the same with g[t] = (-1)^t h[L-1-t] for the detail band.  The step is redundant (2l >= n)
+// and not orthogonal; its left inverse keeps the central n samples of the upsampled, filtered
+// bands:
+//   x[i] = sum_k h[i + L - 2 - 2k] a[k] + g[i + L - 2 - 2k] d[k],   0 <= k < l.
+// With S_a, S_d the two halves of that synthesis and A, B the two analysis halves,
+// S_a A + S_d B = I on every length-n signal, and a d-dimensional level is the tensor product of
+// the steps along every axis (the all-low band's synthesis S_a^{(d)} after A^{(d)}, plus 2^d - 1
+// detail terms that sum to I - S_a^{(d)} A^{(d)}).  With detail level i weighted
+// w_i = 2^{-2s(m-i)} and the approximation weighted 1 (= w_m), the operator therefore has the
+// projection form of the periodic case with A^T replaced by S_a:
+//   W^{-1} D W = w_1 I + sum_{i=1}^{m-1} c_i S_a^i A^i,   c_i = w_{i+1} - w_i,
+// evaluated by the Horner recurrence
+//   a_i = A a_{i-1} (a_0 = x),  z_{m-1} = c_{m-1} a_{m-1},  z_i = c_i a_i + S_a z_{i+1},
+//   y = w_1 x + S_a z_1.
+// Only all-low bands are formed; level m is never visited.
+//
+// Kernels (one work-group = one output tile, 256 threads):
+//   k_sym_down  a_out = A a_in: the tile's input window (2T + L - 2 per axis) is staged in LDS
+//               through per-axis tables of reflected indices, then filtered axis 2, 1, 0.
+//   k_sym_up    out = alpha * same + beta * S_a z: the window of z (U/2 + L/2 - 1 per axis,
+//               starting at half the tile origin) is staged with zeros outside [0, l), then
+//               filtered axis 2, 1, 0; the last pass writes the combination to global memory.
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/eswave.h"
+#include "internal.h"
+#include "kcommon.h"
+
+namespace es {
+
+namespace {
+
+// Position j of the half-point symmetric extension of a length-n axis, as an index into [0, n).
+DEVI int sym_ix(int j, int n) {
+  const int p = 2 * n;
+  j %= p;
+  if (j < 0) j += p;
+  return j < n ? j : p - 1 - j;
+}
+
+struct SymTask {
+  const float* in;    // down: a_{i-1}; up: the coarser array z
+  const float* same;  // up: the array combined with weight alpha (may equal out)
+  float* out;
+  int64_t bs_in, bs_same, bs_out;  // per-instance strides in floats (contiguous instances)
+  int32_t ni[3];                   // padded dims of `in` (1-D: (1,1,n), 2-D: (1,n0,n1))
+  int32_t no[3];                   // padded dims of `out` (and `same`)
+  int32_t nt[3];                   // tiles per axis
+  int32_t tiles_per_inst;
+  float alpha, beta;
+};
+
+// Output tile (T0, T1, T2) of one analysis level; input window I_k = 2 T_k + L - 2.
+template <int D, int L, int T0, int T1, int T2, int NT>
+__global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
+  constexpr int I0 = D >= 3 ? 2 * T0 + L - 2 : 1;
+  constexpr int I1 = D >= 2 ? 2 * T1 + L - 2 : 1;
+  constexpr int I2 = 2 * T2 + L - 2;
+  constexpr int I2P = I2 + 1;  // odd row strides: lanes on consecutive rows use distinct banks
+  constexpr int T2P = T2 + 1;
+  constexpr int NIN = I0 * I1 * I2;
+  constexpr int NB = D >= 3 ? I0 * T1 * T2 : 1;
+  constexpr int NS = I0 * I1 * I2P > NB ? I0 * I1 * I2P : NB;
+  constexpr int P2 = 4, P1 = D >= 3 ? 2 : 4, P0 = 2;
+  static_assert(T2 % P2 == 0 && (D < 2 || T1 % P1 == 0) && (D < 3 || T0 % P0 == 0), "tile shape");
+  __shared__ float s_in[NS];  // staged window; after the axis-2 pass reused for the axis-1 output (3-D)
+  __shared__ float s_a[I0 * I1 * T2P];
+  __shared__ int s_x0[I0], s_x1[I1], s_x2[I2];
+
+  const int wg = blockIdx.x;
+  const int inst = wg / t.tiles_per_inst;
+  int rem = wg - inst * t.tiles_per_inst;
+  const int c2 = rem % t.nt[2];
+  rem /= t.nt[2];
+  const int c1 = rem % t.nt[1], c0 = rem / t.nt[1];
+  const float* src = t.in + inst * t.bs_in;
+  float* dst = t.out + inst * t.bs_out;
+  const int n0 = t.ni[0], n1 = t.ni[1], n2 = t.ni[2];
+  const int m0 = t.no[0], m1 = t.no[1], m2 = t.no[2];
+  const int o0 = T0 * c0, o1 = T1 * c1, o2 = T2 * c2;  // first output of the tile on each axis
+
+  for (int i = threadIdx.x; i < I2; i += NT) s_x2[i] = sym_ix(2 * o2 - (L - 2) + i, n2);
+  for (int i = threadIdx.x; i < I1; i += NT) s_x1[i] = D >= 2 ? sym_ix(2 * o1 - (L - 2) + i, n1) * n2 : 0;
+  for (int i = threadIdx.x; i < I0; i += NT) s_x0[i] = D >= 3 ? sym_ix(2 * o0 - (L - 2) + i, n0) * (n1 * n2) : 0;
+  __syncthreads();
+  gather_to_lds<NT, 8>(
+      NIN,
+      [&](int e) {
+        const int i2 = e % I2, r = e / I2;
+        return gld(src + s_x0[r / I1] + s_x1[r % I1] + s_x2[i2]);
+      },
+      [&](int e, float v) { s_in[(e / I2) * I2P + e % I2] = v; });
+  __syncthreads();
+
+  // axis 2: (I0 I1 rows, I2) -> (I0 I1 rows, T2)
+  analysis_pass<L, P2, false, true, NT>(
+      I0 * I1, T2 / P2, f,
+      [&](int l, int j0, float* w) {
+#pragma unroll
+        for (int j = 0; j < 2 * P2 + L - 2; ++j) w[j] = s_in[l * I2P + j0 + j];
+      },
+      [&](int l, int k, float lo, float) { s_a[l * T2P + k] = lo; });
+  __syncthreads();
+
+  if constexpr (D == 1) {
+    for (int k = threadIdx.x; k < T2; k += NT) {
+      const int g2 = o2 + k;
+      if (g2 < m2) gst(dst + g2, s_a[k]);
+    }
+  } else if constexpr (D == 2) {
+    analysis_pass<L, P1, false, true, NT>(
+        T2, T1 / P1, f,
+        [&](int c, int j0, float* w) {
+#pragma unroll
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_a[(j0 + j) * T2P + c];
+        },
+        [&](int c, int k, float lo, float) {
+          const int g1 = o1 + k, g2 = o2 + c;
+          if (g1 < m1 && g2 < m2) gst(dst + g1 * m2 + g2, lo);
+        });
+  } else {
+    float* s_b = s_in;  // (I0, T1, T2)
+    analysis_pass<L, P1, false, true, NT>(
+        I0 * T2, T1 / P1, f,
+        [&](int l, int j0, float* w) {
+          const int c = l % T2, i0 = l / T2;
+#pragma unroll
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_a[(i0 * I1 + j0 + j) * T2P + c];
+        },
+        [&](int l, int k, float lo, float) {
+          const int c = l % T2, i0 = l / T2;
+          s_b[(i0 * T1 + k) * T2 + c] = lo;
+        });
+    __syncthreads();
+    analysis_pass<L, P0, false, true, NT>(
+        T1 * T2, T0 / P0, f,
+        [&](int l, int j0, float* w) {
+#pragma unroll
+          for (int j = 0; j < 2 * P0 + L - 2; ++j) w[j] = s_b[(j0 + j) * T1 * T2 + l];
+        },
+        [&](int l, int k, float lo, float) {
+          const int c = l % T2, k1 = l / T2;
+          const int g0 = o0 + k, g1 = o1 + k1, g2 = o2 + c;
+          if (g0 < m0 && g1 < m1 && g2 < m2) gst(dst + (g0 * m1 + g1) * m2 + g2, lo);
+        });
+  }
+}
+
+// Output tile (U0, U1, U2) (even) of one synthesis level; z window J_k = U_k/2 + L/2 - 1 starting
+// at U_k c_k / 2: output i = U_k c_k + 2q + e reads z[U_k c_k/2 + q + L/2 - 1 - j] with tap
+// h[2j + e], j < L/2 (the index i + L - 2 - 2k of the left inverse).
+template <int D, int L, int U0, int U1, int U2, int NT>
+__global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
+  constexpr int H = L / 2;
+  constexpr int J0 = D >= 3 ? U0 / 2 + H - 1 : 1;
+  constexpr int J1 = D >= 2 ? U1 / 2 + H - 1 : 1;
+  constexpr int J2 = U2 / 2 + H - 1;
+  constexpr int J2P = J2 | 1;
+  constexpr int U2P = U2 + 1;
+  constexpr int NZ = J0 * J1 * J2;
+  constexpr int P2 = 4, P1 = D >= 3 ? 2 : 4, P0 = 2;
+  static_assert(U2 % (2 * P2) == 0 && (D < 2 || U1 % (2 * P1) == 0) && (D < 3 || U0 % (2 * P0) == 0), "tile shape");
+  __shared__ float s_z[J0 * J1 * J2P];
+  __shared__ float s_a[J0 * J1 * U2P];
+  __shared__ float s_b[D >= 3 ? J0 * U1 * U2 : 1];
+  __shared__ int s_x0[J0], s_x1[J1], s_x2[J2];
+
+  const int wg = blockIdx.x;
+  const int inst = wg / t.tiles_per_inst;
+  int rem = wg - inst * t.tiles_per_inst;
+  const int c2 = rem % t.nt[2];
+  rem /= t.nt[2];
+  const int c1 = rem % t.nt[1], c0 = rem / t.nt[1];
+  const float* z = t.in + inst * t.bs_in;
+  const float* same = t.same + inst * t.bs_same;  // may equal out: each output reads only its own slot
+  float* out = t.out + inst * t.bs_out;
+  const int l0 = t.ni[0], l1 = t.ni[1], l2 = t.ni[2];
+  const int m0 = t.no[0], m1 = t.no[1], m2 = t.no[2];
+  const int o0 = U0 * c0, o1 = U1 * c1, o2 = U2 * c2;  // first output of the tile on each axis
+  const int r0 = o0 / 2, r1 = o1 / 2, r2 = o2 / 2;     // first z sample of the window
+
+  for (int i = threadIdx.x; i < J2; i += NT) s_x2[i] = r2 + i < l2 ? r2 + i : -1;
+  for (int i = threadIdx.x; i < J1; i += NT) s_x1[i] = D >= 2 ? (r1 + i < l1 ? (r1 + i) * l2 : -1) : 0;
+  for (int i = threadIdx.x; i < J0; i += NT) s_x0[i] = D >= 3 ? (r0 + i < l0 ? (r0 + i) * (l1 * l2) : -1) : 0;
+  __syncthreads();
+  gather_to_lds<NT, 4>(
+      NZ,
+      [&](int e) {
+        const int x2 = s_x2[e % J2], r = e / J2;
+        const int x1 = s_x1[r % J1], x0 = s_x0[r / J1];
+        return (x0 >= 0 && x1 >= 0 && x2 >= 0) ? gld(z + x0 + x1 + x2) : 0.f;
+      },
+      [&](int e, float v) { s_z[(e / J2) * J2P + e % J2] = v; });
+  __syncthreads();
+
+  // axis 2: (J0 J1 rows, J2) -> (J0 J1 rows, U2)
+  synthesis_pass<L, P2, false, true, NT>(
+      J0 * J1, U2 / 2 / P2, f,
+      [&](int l, int j0, float* lo, float*) {
+#pragma unroll
+        for (int j = 0; j < P2 + H - 1; ++j) lo[j] = s_z[l * J2P + j0 + j];
+      },
+      [&](int l, int p, float e0, float e1) {
+        s_a[l * U2P + p] = e0;
+        s_a[l * U2P + p + 1] = e1;
+      });
+  __syncthreads();
+
+  const float alpha = t.alpha, beta = t.beta;
+  if constexpr (D == 1) {
+    for (int p = threadIdx.x; p < U2; p += NT) {
+      const int g2 = o2 + p;
+      if (g2 < m2) gst(out + g2, fmaf(alpha, gld(same + g2), beta * s_a[p]));
+    }
+  } else if constexpr (D == 2) {
+    synthesis_pass<L, P1, false, true, NT>(
+        U2, U1 / 2 / P1, f,
+        [&](int c, int j0, float* lo, float*) {
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) lo[j] = s_a[(j0 + j) * U2P + c];
+        },
+        [&](int c, int p, float e0, float e1) {
+          const int g1 = o1 + p, g2 = o2 + c;
+          if (g2 < m2) {
+            if (g1 < m1) {
+              const int o = g1 * m2 + g2;
+              gst(out + o, fmaf(alpha, gld(same + o), beta * e0));
+            }
+            if (g1 + 1 < m1) {
+              const int o = (g1 + 1) * m2 + g2;
+              gst(out + o, fmaf(alpha, gld(same + o), beta * e1));
+            }
+          }
+        });
+  } else {
+    // axis 1: lines (i0, c): (J0, J1, U2) -> (J0, U1, U2)
+    synthesis_pass<L, P1, false, true, NT>(
+        J0 * U2, U1 / 2 / P1, f,
+        [&](int l, int j0, float* lo, float*) {
+          const int c = l % U2, i0 = l / U2;
+#pragma unroll
+          for (int j = 0; j < P1 + H - 1; ++j) lo[j] = s_a[(i0 * J1 + j0 + j) * U2P + c];
+        },
+        [&](int l, int p, float e0, float e1) {
+          const int c = l % U2, i0 = l / U2;
+          s_b[(i0 * U1 + p) * U2 + c] = e0;
+          s_b[(i0 * U1 + p + 1) * U2 + c] = e1;
+        });
+    __syncthreads();
+    // axis 0: lines (p1, c): (J0, U1, U2) -> (U0, U1, U2)
+    synthesis_pass<L, P0, false, true, NT>(
+        U1 * U2, U0 / 2 / P0, f,
+        [&](int l, int j0, float* lo, float*) {
+#pragma unroll
+          for (int j = 0; j < P0 + H - 1; ++j) lo[j] = s_b[(j0 + j) * U1 * U2 + l];
+        },
+        [&](int l, int p, float e0, float e1) {
+          const int c = l % U2, p1 = l / U2;
+          const int g1 = o1 + p1, g2 = o2 + c;
+          if (g1 < m1 && g2 < m2) {
+            const int g0 = o0 + p;
+            if (g0 < m0) {
+              const int o = (g0 * m1 + g1) * m2 + g2;
+              gst(out + o, fmaf(alpha, gld(same + o), beta * e0));
+            }
+            if (g0 + 1 < m0) {
+              const int o = ((g0 + 1) * m1 + g1) * m2 + g2;
+              gst(out + o, fmaf(alpha, gld(same + o), beta * e1));
+            }
+          }
+        });
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Tile shapes per (dimensionality, taps).
+
+struct SymTiles {
+  int t[3];  // analysis output tile
+  int u[3];  // synthesis output tile
+};
+
+constexpr int kSymThreads = 256;
+
+SymTiles sym_tiles(int D, int L) {
+  if (D == 1) return {{1, 1, 256}, {1, 1, 512}};
+  if (D == 2) return {{1, 16, 32}, {1, 32, 64}};
+  if (L <= 4) return {{4, 8, 16}, {8, 8, 32}};
+  if (L <= 8) return {{4, 4, 16}, {8, 8, 32}};
+  return {{2, 4, 16}, {8, 8, 32}};
+}
+
+template <int D, int L>
+hipError_t launch_sym_level(bool up, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
+  if constexpr (D == 1) {
+    if (up) hipLaunchKernelGGL((k_sym_up<1, L, 1, 1, 512, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    else hipLaunchKernelGGL((k_sym_down<1, L, 1, 1, 256, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+  } else if constexpr (D == 2) {
+    if (up) hipLaunchKernelGGL((k_sym_up<2, L, 1, 32, 64, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    else hipLaunchKernelGGL((k_sym_down<2, L, 1, 16, 32, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+  } else {
+    if (up) {
+      hipLaunchKernelGGL((k_sym_up<3, L, 8, 8, 32, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    } else if constexpr (L <= 4) {
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 8, 16, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    } else if constexpr (L <= 8) {
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    } else {
+      hipLaunchKernelGGL((k_sym_down<3, L, 2, 4, 16, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_sym_taps(int D, bool up, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
+  if (D == 1) return launch_sym_level<1, L>(up, t, grid, f, s);
+  if (D == 2) return launch_sym_level<2, L>(up, t, grid, f, s);
+  return launch_sym_level<3, L>(up, t, grid, f, s);
+}
+
+hipError_t launch_sym(int D, int L, bool up, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
+  switch (L) {
+    case 2: return launch_sym_taps<2>(D, up, t, grid, f, s);
+    case 4: return launch_sym_taps<4>(D, up, t, grid, f, s);
+    case 6: return launch_sym_taps<6>(D, up, t, grid, f, s);
+    case 8: return launch_sym_taps<8>(D, up, t, grid, f, s);
+    case 10: return launch_sym_taps<10>(D, up, t, grid, f, s);
+    case 12: return launch_sym_taps<12>(D, up, t, grid, f, s);
+    case 14: return launch_sym_taps<14>(D, up, t, grid, f, s);
+    default: return launch_sym_taps<16>(D, up, t, grid, f, s);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Host: geometry, level lengths, workspace and the launch sequence.
+
+constexpr int kSymMaxLevels = 30;
+
+struct SymGeo {
+  int D, L, m;
+  double s;
+  int dims[kSymMaxLevels + 1][3];  // padded dims of a_0 (= x) .. a_m
+  int64_t size(int i) const { return (int64_t)dims[i][0] * dims[i][1] * dims[i][2]; }
+};
+
+es_status sym_einval(const char* fmt, long long a = 0, long long b = 0) {
+  char buf[200];
+  snprintf(buf, sizeof buf, fmt, a, b);
+  return report_error(ES_EINVAL, buf);
+}
+
+int64_t sym_len(int64_t n, int L) { return (n + L - 1) / 2; }
+
+es_status sym_geo(int ndim, const int64_t* shape, int order, int levels, double s, SymGeo* g) {
+  if (ndim < 1 || ndim > 3) return sym_einval("ndim must be 1, 2 or 3 (got %lld)", ndim);
+  if (!shape) return sym_einval("shape is NULL");
+  if (order < 1 || order > 8) return sym_einval("order must be in 1..8 (got %lld)", order);
+  if (levels < 0 || levels > kSymMaxLevels) return sym_einval("levels must be in 0..%lld (got %lld)", kSymMaxLevels, levels);
+  if (!std::isfinite(s)) return sym_einval("s must be finite");
+  g->D = ndim;
+  g->L = 2 * order;
+  g->m = levels;
+  g->s = s;
+  int64_t n[3] = {1, 1, 1};
+  for (int k = 0; k < ndim; ++k) {
+    if (shape[k] < 1 || shape[k] > (1ll << 30)) return sym_einval("shape[%lld] must be in 1..2^30 (got %lld)", k, shape[k]);
+    n[3 - ndim + k] = shape[k];
+  }
+  for (int i = 0; i <= levels; ++i) {
+    int64_t prod = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t v = i == 0 || a < 3 - ndim ? n[a] : sym_len(g->dims[i - 1][a], g->L);
+      g->dims[i][a] = (int)v;
+      prod *= v;
+    }
+    if (prod > 0x7fffffffll) return sym_einval("level %lld holds more than 2^31-1 elements per instance", i);
+  }
+  return ES_OK;
+}
+
+int64_t align64f(int64_t v) { return (v + 63) & ~(int64_t)63; }
+
+// Floats of workspace: a_1 .. a_{m-1} of every instance, each level 256-byte aligned.
+int64_t sym_ws_floats(const SymGeo& g, int64_t batch) {
+  int64_t tot = 0;
+  for (int i = 1; i < g.m; ++i) tot += align64f(batch * g.size(i));
+  return tot;
+}
+
+bool sym_filter(int L, Filter* f) {
+  double h[kMaxTaps];
+  if (!daubechies_filter(L / 2, h)) return false;
+  for (int t = 0; t < kMaxTaps; ++t) f->h[t] = f->g[t] = 0.f;
+  for (int t = 0; t < L; ++t) {
+    f->h[t] = (float)h[t];
+    f->g[t] = (float)((t & 1) ? -h[L - 1 - t] : h[L - 1 - t]);
+  }
+  return true;
+}
+
+struct SymLaunch {
+  bool up;
+  SymTask t;
+  int64_t grid;
+};
+
+// Sets the tile counts of `t` for output dims `no` and tile `tile`; returns the grid.
+int64_t sym_tiling(SymTask& t, const int tile[3], int64_t batch) {
+  int64_t per = 1;
+  for (int a = 0; a < 3; ++a) {
+    t.nt[a] = (t.no[a] + tile[a] - 1) / tile[a];
+    per *= t.nt[a];
+  }
+  t.tiles_per_inst = (int32_t)per;
+  return per * batch;
+}
+
+es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y, float* ws,
+                       std::vector<SymLaunch>* out) {
+  out->clear();
+  const SymTiles tl = sym_tiles(g.D, g.L);
+  std::vector<float*> lev(g.m + 1, nullptr);
+  lev[0] = const_cast<float*>(x);
+  int64_t off = 0;
+  for (int i = 1; i < g.m; ++i) {
+    lev[i] = ws + off;
+    off += align64f(batch * g.size(i));
+  }
+  // weights: w[i] of detail level i (1..m), w[m] = 1 = approximation weight
+  std::vector<double> w(g.m + 1, 1.0);
+  for (int i = 1; i <= g.m; ++i) w[i] = std::exp2(-2.0 * g.s * (double)(g.m - i));
+  for (int i = 1; i < g.m; ++i) {
+    SymLaunch l{};
+    l.up = false;
+    l.t.in = lev[i - 1];
+    l.t.out = lev[i];
+    l.t.same = nullptr;
+    l.t.bs_in = g.size(i - 1);
+    l.t.bs_out = g.size(i);
+    for (int a = 0; a < 3; ++a) {
+      l.t.ni[a] = g.dims[i - 1][a];
+      l.t.no[a] = g.dims[i][a];
+    }
+    l.grid = sym_tiling(l.t, tl.t, batch);
+    out->push_back(l);
+  }
+  for (int j = g.m - 1; j >= 1; --j) {
+    // z_{j-1} = c_{j-1} a_{j-1} + S_a z_j  (y = w_1 x + S_a z_1 when j = 1); z_{m-1} = c_{m-1} a_{m-1}
+    SymLaunch l{};
+    l.up = true;
+    l.t.in = lev[j];
+    l.t.same = lev[j - 1];
+    l.t.out = j == 1 ? y : lev[j - 1];
+    l.t.bs_in = g.size(j);
+    l.t.bs_same = g.size(j - 1);
+    l.t.bs_out = g.size(j - 1);
+    l.t.alpha = (float)(j == 1 ? w[1] : w[j] - w[j - 1]);
+    l.t.beta = (float)(j == g.m - 1 ? w[g.m] - w[g.m - 1] : 1.0);
+    for (int a = 0; a < 3; ++a) {
+      l.t.ni[a] = g.dims[j][a];
+      l.t.no[a] = g.dims[j - 1][a];
+    }
+    l.grid = sym_tiling(l.t, tl.u, batch);
+    out->push_back(l);
+  }
+  for (const SymLaunch& l : *out)
+    if (l.grid > 0x7fffffffll) return sym_einval("a level needs more than 2^31-1 work-groups (%lld)", l.grid);
+  return ES_OK;
+}
+
+}  // namespace
+
+}  // namespace es
+
+using namespace es;
+
+extern "C" {
+
+size_t es_sym_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels) {
+  SymGeo g;
+  if (sym_geo(ndim, shape, order, levels, 0.0, &g) != ES_OK || batch <= 0) return 0;
+  return (size_t)sym_ws_floats(g, batch) * sizeof(float);
+}
+
+es_status es_sym_band_lengths(int64_t n, int order, int levels, int64_t* lengths) {
+  if (!lengths) return sym_einval("lengths is NULL");
+  SymGeo g;
+  es_status st = sym_geo(1, &n, order, levels, 0.0, &g);
+  if (st != ES_OK) return st;
+  for (int i = 1; i <= levels; ++i) lengths[i - 1] = g.dims[i][2];
+  return ES_OK;
+}
+
+es_status es_sym_cov_apply(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                           const float* x, float* y, void* ws, size_t ws_bytes, void* stream) {
+  SymGeo g;
+  es_status st = sym_geo(ndim, shape, order, levels, s, &g);
+  if (st != ES_OK) return st;
+  if (batch < 0) return sym_einval("batch must be >= 0");
+  if (batch == 0) return ES_OK;
+  const int64_t N = g.size(0);
+  if (N > INT64_MAX / 4 / batch) return sym_einval("batch * size overflows");
+  if (!x || !y) return sym_einval("input and output pointers must be non-NULL");
+  if (((uintptr_t)x & 15) || ((uintptr_t)y & 15)) return sym_einval("input and output must be 16-byte aligned");
+  const size_t io = (size_t)(batch * N) * sizeof(float);
+  const char *px = (const char*)x, *py = (const char*)y;
+  if (px < py + io && py < px + io) return sym_einval("input and output overlap");
+  const size_t need = (size_t)sym_ws_floats(g, batch) * sizeof(float);
+  if (need) {
+    if (!ws) return report_error(ES_EWORKSPACE, "workspace required (es_sym_workspace_bytes), got NULL");
+    if (ws_bytes < need) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "workspace of %zu bytes required, got %zu", need, ws_bytes);
+      return report_error(ES_EWORKSPACE, buf);
+    }
+    if ((uintptr_t)ws & 255) return sym_einval("workspace must be 256-byte aligned");
+    const char* pw = (const char*)ws;
+    if ((pw < px + io && px < pw + need) || (pw < py + io && py < pw + need))
+      return sym_einval("workspace overlaps input or output");
+  }
+  std::vector<SymLaunch> seq;
+  if ((st = sym_schedule(g, batch, x, y, (float*)ws, &seq)) != ES_OK) return st;
+  Filter f;
+  if (!sym_filter(g.L, &f)) return report_error(ES_EUNSUPPORTED, "filter derivation failed");
+  if ((st = device_check()) != ES_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  hipError_t he;
+  if (g.m <= 1) {  // every weight is 1: the identity
+    if ((he = launch_copy(x, y, batch * N, hs)) != hipSuccess) return report_error(ES_EDEVICE, hipGetErrorString(he));
+    return ES_OK;
+  }
+  for (const SymLaunch& l : seq)
+    if ((he = launch_sym(g.D, g.L, l.up, l.t, l.grid, f, hs)) != hipSuccess)
+      return report_error(ES_EDEVICE, hipGetErrorString(he));
+  return ES_OK;
+}
+
+}  // extern "C"

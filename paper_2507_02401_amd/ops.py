@@ -128,6 +128,35 @@ def fft_cov_apply(x, ndim, s, period=1.0, out=None, workspace=None):
     return out
 
 
+def sym_band_lengths(n, order, levels):
+    """Band lengths l_1 .. l_levels of one axis of length n in the non-periodic transform."""
+    lib = load()
+    out = (ctypes.c_int64 * max(1, int(levels)))()
+    check(lib.es_sym_band_lengths(int(n), int(order), int(levels), out))
+    return [int(out[i]) for i in range(int(levels))]
+
+
+def sym_cov_apply(x, ndim, order, levels, s, out=None, workspace=None):
+    """y = W^{-1} D_2s W x with the non-periodic (half-point symmetric extension) DWT of Sec. 4;
+    any side lengths.  Not symmetric (W^{-1} is not W^T)."""
+    grid, batch = _split(x, ndim)
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of the input's shape")
+    lib = load()
+    shp = shape_arg(grid)
+    need = int(lib.es_sym_workspace_bytes(ndim, shp, batch, int(order), int(levels)))
+    ws = _ws(need, x.device, workspace)
+    with torch.cuda.device(x.device):
+        stream = torch.cuda.current_stream(x.device).cuda_stream
+        st = lib.es_sym_cov_apply(ndim, shp, batch, int(order), int(levels), float(s), x.data_ptr(),
+                                  out.data_ptr(), ws.data_ptr() if ws is not None else None, need, stream)
+    check(st)
+    return out
+
+
 def plain_op(op, x, ndim, order, levels, s, out=None):
     """Reference variant: one launch per 1-D pass per level per instance."""
     grid, batch = _split(x, ndim)

@@ -1,0 +1,109 @@
+"""GPU: the non-periodic operator W^{-1} D_2s W (half-point symmetric extension, Sec. 4) vs the FP64
+oracle's full filter bank and left inverse, on ragged and odd sides, every order, 1-3 D; identity
+cases; constants; the full 64 x 1024^2 geometry on sampled images."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2507_02401_amd as es
+from oracle import symdwt
+from tests.gpu_util import TOL, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+CASES = [
+    # shape, batch, order, levels, s
+    ((1,), 3, 8, 4, 1.5),
+    ((2,), 2, 1, 3, 1.0),
+    ((5,), 4, 4, 5, 1.5),
+    ((47,), 2, 8, 3, 1.0),
+    ((300,), 2, 5, 4, 1.0),
+    ((1000,), 3, 3, 6, 0.75),
+    ((5184,), 1, 8, 5, 1.5),
+    ((1, 1), 2, 2, 2, 1.0),
+    ((2, 3), 3, 8, 3, 1.5),
+    ((31, 29), 1, 7, 3, 1.5),
+    ((37, 53), 2, 4, 4, 1.5),
+    ((64, 64), 2, 8, 5, 1.0),
+    ((100, 33), 1, 6, 3, -0.5),
+    ((128, 128), 1, 4, 5, 1.0),
+    ((513, 257), 1, 8, 7, 1.5),
+    ((1, 5, 2), 2, 3, 2, 1.0),
+    ((6, 6, 6), 1, 1, 2, 1.0),
+    ((7, 9, 8), 2, 5, 3, 1.0),
+    ((9, 10, 11), 2, 4, 3, 2.0),
+    ((12, 11, 10), 1, 7, 2, 1.0),
+    ((16, 16, 16), 1, 8, 3, 1.5),
+    ((20, 13, 7), 1, 2, 4, 0.5),
+    ((33, 40, 47), 1, 6, 2, 1.0),
+]
+
+
+def _ids(c):
+    return f"{'x'.join(map(str, c[0]))}-b{c[1]}-db{c[2]}-m{c[3]}-s{c[4]}"
+
+
+def _input(shape, batch, seed):
+    return np.random.default_rng(seed).standard_normal((batch,) + shape).astype(np.float32)
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_sym_cov_parity(case):
+    shape, batch, order, levels, s = case
+    x = _input(shape, batch, sum(shape) * 131 + order)
+    say("sym_cov", shape, batch, order, levels, s)
+    xt = torch.from_numpy(x).to(DEV)
+    got = es.sym_cov_apply(xt, len(shape), order, levels, s).cpu().numpy()
+    assert np.array_equal(xt.cpu().numpy(), x), "the input was modified"
+    for b in range(batch):
+        ref = symdwt.sym_cov_apply(x[b].astype(np.float64), order, levels, s)
+        err = rel_l2(got[b], ref)
+        assert err < TOL, (b, err)
+
+
+@pytest.mark.parametrize("levels,s", [(0, 1.5), (1, 1.5), (4, 0.0)])
+def test_sym_identity_cases_are_exact(levels, s):
+    """levels <= 1 (every weight 1) and s = 0 (every c_i = 0, w_1 = 1) give x bit for bit."""
+    x = _input((45, 70), 2, 7)
+    say("sym identity", levels, s)
+    y = es.sym_cov_apply(torch.from_numpy(x).to(DEV), 2, 6, levels, s).cpu().numpy()
+    assert np.array_equal(y, x)
+
+
+@pytest.mark.parametrize("shape,order,levels", [((77,), 8, 5), ((50, 61), 4, 4), ((14, 15, 16), 2, 3)])
+def test_sym_constants_are_kept(shape, order, levels):
+    """The symmetric extension of a constant is constant, every detail band vanishes, so the operator
+    returns the constant for every s."""
+    x = np.full((1,) + shape, 0.75, dtype=np.float32)
+    say("sym constant", shape, order, levels)
+    y = es.sym_cov_apply(torch.from_numpy(x).to(DEV), len(shape), order, levels, 1.5).cpu().numpy()
+    assert np.max(np.abs(y - 0.75)) < 2e-6
+
+
+def test_sym_deterministic_and_batch_independent():
+    shape = (123, 91)
+    x = _input(shape, 3, 3)
+    say("sym determinism", shape)
+    xt = torch.from_numpy(x).to(DEV)
+    a = es.sym_cov_apply(xt, 2, 8, 5, 1.5)
+    b = es.sym_cov_apply(xt, 2, 8, 5, 1.5)
+    one = es.sym_cov_apply(xt[1:2].clone(), 2, 8, 5, 1.5)
+    assert torch.equal(a, b)
+    assert torch.equal(a[1:2], one)
+
+
+def test_sym_full_size_64x1024_sampled():
+    """64 x 1024^2, db8, 7 levels, s = 1.5 (the batch geometry of the periodic workload), images
+    0 and 63 against the oracle."""
+    import inputs
+    d = inputs.image_batch(seed=0)
+    x = d["x"]
+    say("sym full size", x.shape)
+    xt = torch.from_numpy(x).to(DEV)
+    y = es.sym_cov_apply(xt, 2, 8, 7, 1.5)
+    torch.cuda.synchronize()
+    for b in (0, 63):
+        ref = symdwt.sym_cov_apply(x[b].astype(np.float64), 8, 7, 1.5)
+        err = rel_l2(y[b].cpu().numpy(), ref)
+        assert err < TOL, (b, err)

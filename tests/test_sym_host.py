@@ -1,0 +1,87 @@
+"""Host-side checks of the non-periodic entry points (no device call): book-keeping band lengths
+against the oracle, workspace sizes, and argument validation before any launch."""
+import numpy as np
+import pytest
+
+from oracle import symdwt
+from paper_2507_02401_amd import _lib
+
+FAKE_IN, FAKE_OUT, FAKE_WS = 0x100000, 0x900000, 0x2000000
+
+
+@pytest.mark.parametrize("order", range(1, 9))
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 14, 15, 16, 100, 1023, 1024, 5184])
+def test_band_lengths_match_oracle(lib, order, n):
+    levels = 9
+    out = (_lib.ctypes.c_int64 * levels)()
+    assert lib.es_sym_band_lengths(n, order, levels, out) == _lib.ES_OK
+    assert list(out) == symdwt.sym_lengths(n, 2 * order, levels)
+
+
+def test_band_lengths_fixed_point_and_errors(lib):
+    """Lengths settle at L - 1, where floor((l + L - 1) / 2) = l."""
+    out = (_lib.ctypes.c_int64 * 30)()
+    assert lib.es_sym_band_lengths(1 << 20, 4, 30, out) == _lib.ES_OK
+    assert list(out)[-1] == 7
+    assert lib.es_sym_band_lengths(8, 4, 3, None) == _lib.ES_EINVAL
+    assert lib.es_sym_band_lengths(0, 4, 3, out) == _lib.ES_EINVAL
+    assert lib.es_sym_band_lengths(8, 9, 3, out) == _lib.ES_EINVAL
+    assert lib.es_sym_band_lengths(8, 4, 31, out) == _lib.ES_EINVAL
+
+
+def _ws(lib, shape, batch, order, levels):
+    return lib.es_sym_workspace_bytes(len(shape), _lib.shape_arg(shape), batch, order, levels)
+
+
+@pytest.mark.parametrize("shape,batch,order,levels", [
+    ((1024, 1024), 64, 8, 7), ((37, 53), 3, 2, 4), ((9, 10, 11), 2, 4, 3), ((5,), 7, 8, 6), ((64,), 1, 1, 1),
+    ((64,), 1, 3, 0)])
+def test_workspace_is_the_level_arrays(lib, shape, batch, order, levels):
+    """a_1 .. a_{m-1} of every instance, each level rounded up to 64 floats."""
+    dims = [list(shape)]
+    for _ in range(levels):
+        dims.append([symdwt.sym_length(v, 2 * order) for v in dims[-1]])
+    tot = sum((batch * int(np.prod(dims[i])) + 63) // 64 * 64 for i in range(1, levels))
+    assert _ws(lib, shape, batch, order, levels) == 4 * tot
+
+
+def test_workspace_zero_for_invalid(lib):
+    assert _ws(lib, (0, 4), 1, 4, 2) == 0
+    assert _ws(lib, (8, 8), 0, 4, 2) == 0
+    assert _ws(lib, (8, 8), 1, 9, 2) == 0
+
+
+def _call(lib, ndim=2, shape=(37, 53), batch=1, order=4, levels=3, s=1.0, x=FAKE_IN, y=FAKE_OUT, ws=FAKE_WS,
+          ws_bytes=1 << 30):
+    return lib.es_sym_cov_apply(ndim, _lib.shape_arg(shape), batch, order, levels, s, x, y, ws, ws_bytes, None)
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(ndim=0), _lib.ES_EINVAL),
+    (dict(ndim=4, shape=(8, 8, 8, 8)), _lib.ES_EINVAL),
+    (dict(order=0), _lib.ES_EINVAL),
+    (dict(order=9), _lib.ES_EINVAL),
+    (dict(levels=-1), _lib.ES_EINVAL),
+    (dict(levels=31), _lib.ES_EINVAL),
+    (dict(shape=(0, 64)), _lib.ES_EINVAL),
+    (dict(shape=(1 << 31, 2)), _lib.ES_EINVAL),
+    (dict(shape=(1 << 16, 1 << 16), levels=1), _lib.ES_EINVAL),
+    (dict(s=float("nan")), _lib.ES_EINVAL),
+    (dict(s=float("-inf")), _lib.ES_EINVAL),
+    (dict(batch=-1), _lib.ES_EINVAL),
+    (dict(x=0), _lib.ES_EINVAL),
+    (dict(y=0), _lib.ES_EINVAL),
+    (dict(x=FAKE_IN + 4), _lib.ES_EINVAL),
+    (dict(y=FAKE_IN + 64), _lib.ES_EINVAL),
+    (dict(ws=0), _lib.ES_EWORKSPACE),
+    (dict(ws_bytes=16), _lib.ES_EWORKSPACE),
+    (dict(ws=FAKE_WS + 16), _lib.ES_EINVAL),
+    (dict(ws=FAKE_IN), _lib.ES_EINVAL),
+])
+def test_validation_before_any_device_call(lib, kw, status):
+    assert _call(lib, **kw) == status
+    assert len(lib.es_last_error()) > 0
+
+
+def test_batch_zero_is_a_noop(lib):
+    assert _call(lib, batch=0, x=0, y=0, ws=0) == _lib.ES_OK
