@@ -426,6 +426,9 @@ def main():
                     help="combine two rocprofv3 --pmc runs into the committed traffic file and exit")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run one 1 GiB device copy (known bytes) for counter calibration")
+    ap.add_argument("--sym-only", action="store_true",
+                    help="time only the non-periodic transform (sym_cov_apply) on the same batch (for profiling) "
+                         "and exit")
     ap.add_argument("--fourier-only", action="store_true",
                     help="time only the Fourier form (fft_cov_apply) on the same batch (for profiling) and exit")
     ap.add_argument("--ragged-seed", type=int, default=None,
@@ -490,6 +493,24 @@ def main():
                           "eager_ms": round(1e3 * te, 3), "voxels_per_s_graph": round(nvr / tg, 1),
                           "graph_equals_eager": same}), flush=True)
         plan.close()
+        return
+
+    if args.sym_only:
+        sws = torch.empty(max(1, lib.es_sym_workspace_bytes(2, _lib.shape_arg(grid), IMAGES, ORDER, LEVELS)),
+                          dtype=torch.uint8,
+                          device=dev)
+        for _ in range(args.warmup):
+            es.sym_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=sws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            es.sym_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=sws)
+        torch.cuda.synchronize()
+        tsym = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"workload": f"sym_cov_apply: {IMAGES} images {SIDE}x{SIDE}, db{ORDER}, {LEVELS} levels, "
+                                      f"s={S}, half-point symmetric extension",
+                          "ms": round(1e3 * tsym, 4), "voxels_per_s": round(voxels / tsym, 1),
+                          "band_lengths": es.sym_band_lengths(SIDE, ORDER, LEVELS)}), flush=True)
         return
 
     if args.fourier_only:

@@ -50,6 +50,12 @@ DEVI int sym_ix(int j, int n) {
   return j < n ? j : p - 1 - j;
 }
 
+typedef float f2v_t __attribute__((ext_vector_type(2)));
+DEVI float2 gld2(const float* p) {
+  const f2v_t v = *(const GAS f2v_t*)p;
+  return make_float2(v.x, v.y);
+}
+
 struct SymTask {
   const float* in;    // down: a_{i-1}; up: the coarser array z
   const float* same;  // up: the array combined with weight alpha (may equal out)
@@ -62,22 +68,27 @@ struct SymTask {
   float alpha, beta;
 };
 
-// Output tile (T0, T1, T2) of one analysis level; input window I_k = 2 T_k + L - 2.
+// Output tile (T0, T1, T2) of one analysis level; input window I_k = 2 T_k + L - 2 starting at
+// 2 o_k - (L - 2) (o_k the tile's first output).  The staged rows are filtered along axis 2 with
+// the periodic kernels' in-place row pass (16-byte LDS windows, results written back over the
+// staging buffer as rows of T2), then along axes 1 and 0.
 template <int D, int L, int T0, int T1, int T2, int NT>
 __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
   constexpr int I0 = D >= 3 ? 2 * T0 + L - 2 : 1;
   constexpr int I1 = D >= 2 ? 2 * T1 + L - 2 : 1;
   constexpr int I2 = 2 * T2 + L - 2;
-  constexpr int I2P = I2 + 1;  // odd row strides: lanes on consecutive rows use distinct banks
-  constexpr int T2P = T2 + 1;
-  constexpr int NIN = I0 * I1 * I2;
+  constexpr int I2P = (I2 + 3) & ~3;
+  constexpr int NROW = I0 * I1;
   constexpr int NB = D >= 3 ? I0 * T1 * T2 : 1;
-  constexpr int NS = I0 * I1 * I2P > NB ? I0 * I1 * I2P : NB;
-  constexpr int P2 = 4, P1 = D >= 3 ? 2 : 4, P0 = 2;
-  static_assert(T2 % P2 == 0 && (D < 2 || T1 % P1 == 0) && (D < 3 || T0 % P0 == 0), "tile shape");
-  __shared__ float s_in[NS];  // staged window; after the axis-2 pass reused for the axis-1 output (3-D)
-  __shared__ float s_a[I0 * I1 * T2P];
-  __shared__ int s_x0[I0], s_x1[I1], s_x2[I2];
+  constexpr int P1 = D >= 3 ? 2 : 4, P0 = 2;
+  // the window start 2 o_2 - (L - 2) is SH floats past a 16-byte boundary (T2 even)
+  constexpr int SH = (L - 2) & 3 ? 4 - ((L - 2) & 3) : 0;
+  constexpr int NVL = (SH + I2 + 3) / 4;  // 16-byte groups loaded per row
+  constexpr int NLD = NROW * NVL, ITL = (NLD + NT - 1) / NT;
+  static_assert(T2 % 4 == 0 && (D < 2 || T1 % P1 == 0) && (D < 3 || T0 % P0 == 0), "tile shape");
+  __shared__ __attribute__((aligned(16))) float s_in[NROW * I2P];
+  __shared__ float s_b[NB];
+  __shared__ int s_row[NROW], s_x2[I2];
 
   const int wg = blockIdx.x;
   const int inst = wg / t.tiles_per_inst;
@@ -91,53 +102,83 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
   const int m0 = t.no[0], m1 = t.no[1], m2 = t.no[2];
   const int o0 = T0 * c0, o1 = T1 * c1, o2 = T2 * c2;  // first output of the tile on each axis
 
-  for (int i = threadIdx.x; i < I2; i += NT) s_x2[i] = sym_ix(2 * o2 - (L - 2) + i, n2);
-  for (int i = threadIdx.x; i < I1; i += NT) s_x1[i] = D >= 2 ? sym_ix(2 * o1 - (L - 2) + i, n1) * n2 : 0;
-  for (int i = threadIdx.x; i < I0; i += NT) s_x0[i] = D >= 3 ? sym_ix(2 * o0 - (L - 2) + i, n0) * (n1 * n2) : 0;
+  // staged row r = (i0, i1): offset of its reflected source row; along axis 2 the window runs
+  // from base2, through a table of reflected columns only where it reaches past an end
+  for (int r = threadIdx.x; r < NROW; r += NT) {
+    const int i1 = r % I1, i0 = r / I1;
+    s_row[r] = (D >= 3 ? sym_ix(2 * o0 - (L - 2) + i0, n0) * (n1 * n2) : 0) +
+               (D >= 2 ? sym_ix(2 * o1 - (L - 2) + i1, n1) * n2 : 0);
+  }
+  const int base2 = 2 * o2 - (L - 2), a2 = base2 - SH;
+  const bool vec = (n2 & 3) == 0 && a2 >= 0 && a2 + 4 * NVL <= n2;  // the same for the whole work-group
+  const bool inner = base2 >= 0 && base2 + I2 <= n2;
+  if (!inner)
+    for (int i = threadIdx.x; i < I2; i += NT) s_x2[i] = sym_ix(base2 + i, n2);
   __syncthreads();
-  gather_to_lds<NT, 8>(
-      NIN,
-      [&](int e) {
-        const int i2 = e % I2, r = e / I2;
-        return gld(src + s_x0[r / I1] + s_x1[r % I1] + s_x2[i2]);
-      },
-      [&](int e, float v) { s_in[(e / I2) * I2P + e % I2] = v; });
+  if (vec) {
+    // 16-byte loads from the aligned start a2 (row offsets are multiples of n2), all issued before
+    // the first LDS store; group v of a row lands at LDS positions 4v - SH .. 4v - SH + 3
+    float4 v[ITL];
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
+      const int r = q / NVL, g = q - r * NVL;
+      v[it] = gld4(src + s_row[r] + a2 + 4 * g);
+    }
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = int(threadIdx.x) + it * NT;
+      if (q < NLD) {
+        const int r = q / NVL, g = q - r * NVL;
+        float* row = s_in + r * I2P;
+        if constexpr (SH == 0) {
+          *reinterpret_cast<float4*>(row + 4 * g) = v[it];
+        } else {
+          if (g > 0) *reinterpret_cast<float2*>(row + 4 * g - 2) = make_float2(v[it].x, v[it].y);
+          if (4 * g + 2 <= I2P) *reinterpret_cast<float2*>(row + 4 * g) = make_float2(v[it].z, v[it].w);
+        }
+      }
+    }
+  } else {
+    gather_to_lds<NT, 8>(
+        NROW * I2,
+        [&](int e) {
+          const int r = e / I2, i2 = e - r * I2;
+          return gld(src + s_row[r] + (inner ? base2 + i2 : s_x2[i2]));
+        },
+        [&](int e, float x) {
+          const int r = e / I2;
+          s_in[r * I2P + e - r * I2] = x;
+        });
+  }
   __syncthreads();
 
-  // axis 2: (I0 I1 rows, I2) -> (I0 I1 rows, T2)
-  analysis_pass<L, P2, false, true, NT>(
-      I0 * I1, T2 / P2, f,
-      [&](int l, int j0, float* w) {
-#pragma unroll
-        for (int j = 0; j < 2 * P2 + L - 2; ++j) w[j] = s_in[l * I2P + j0 + j];
-      },
-      [&](int l, int k, float lo, float) { s_a[l * T2P + k] = lo; });
-  __syncthreads();
+  // axis 2: (NROW, I2) -> (NROW, T2), written back over the staging buffer
+  row_pass_inplace<L, 4, NROW, T2, I2P, NT, false>(s_in, f);
 
   if constexpr (D == 1) {
     for (int k = threadIdx.x; k < T2; k += NT) {
       const int g2 = o2 + k;
-      if (g2 < m2) gst(dst + g2, s_a[k]);
+      if (g2 < m2) gst(dst + g2, s_in[k]);
     }
   } else if constexpr (D == 2) {
     analysis_pass<L, P1, false, true, NT>(
         T2, T1 / P1, f,
         [&](int c, int j0, float* w) {
 #pragma unroll
-          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_a[(j0 + j) * T2P + c];
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_in[(j0 + j) * T2 + c];
         },
         [&](int c, int k, float lo, float) {
           const int g1 = o1 + k, g2 = o2 + c;
           if (g1 < m1 && g2 < m2) gst(dst + g1 * m2 + g2, lo);
         });
   } else {
-    float* s_b = s_in;  // (I0, T1, T2)
     analysis_pass<L, P1, false, true, NT>(
         I0 * T2, T1 / P1, f,
         [&](int l, int j0, float* w) {
           const int c = l % T2, i0 = l / T2;
 #pragma unroll
-          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_a[(i0 * I1 + j0 + j) * T2P + c];
+          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_in[(i0 * I1 + j0 + j) * T2 + c];
         },
         [&](int l, int k, float lo, float) {
           const int c = l % T2, i0 = l / T2;
@@ -168,7 +209,7 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
   constexpr int J1 = D >= 2 ? U1 / 2 + H - 1 : 1;
   constexpr int J2 = U2 / 2 + H - 1;
   constexpr int J2P = J2 | 1;
-  constexpr int U2P = U2 + 1;
+  constexpr int U2P = D == 2 ? U2 + 4 : U2 + 1;  // 2-D: rows of whole 16-byte groups for the last pass
   constexpr int NZ = J0 * J1 * J2;
   constexpr int P2 = 4, P1 = D >= 3 ? 2 : 4, P0 = 2;
   static_assert(U2 % (2 * P2) == 0 && (D < 2 || U1 % (2 * P1) == 0) && (D < 3 || U0 % (2 * P0) == 0), "tile shape");
@@ -190,6 +231,22 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
   const int m0 = t.no[0], m1 = t.no[1], m2 = t.no[2];
   const int o0 = U0 * c0, o1 = U1 * c1, o2 = U2 * c2;  // first output of the tile on each axis
   const int r0 = o0 / 2, r1 = o1 / 2, r2 = o2 / 2;     // first z sample of the window
+
+  // 2-D tiles whose columns lie inside a row length divisible by 4: the last pass gives each lane
+  // four adjacent columns of one output row pair (16-byte LDS reads, loads and stores), and the
+  // lane's `same` values are loaded first so that their latency overlaps the staging of z
+  constexpr int C4 = U2 / 4, NT2 = C4 * (U1 / 2);
+  const bool fast = D == 2 && (m2 & 3) == 0 && o2 + U2 <= m2;
+  float4 xs0 = make_float4(0.f, 0.f, 0.f, 0.f), xs1 = xs0;
+  if constexpr (D == 2) {
+    static_assert(NT2 <= NT, "one task per lane");
+    if (fast && threadIdx.x < NT2) {
+      const int c4 = threadIdx.x % C4, ch = threadIdx.x / C4;
+      const int g1 = o1 + 2 * ch, g2 = o2 + 4 * c4;
+      if (g1 < m1) xs0 = gld4(same + g1 * m2 + g2);
+      if (g1 + 1 < m1) xs1 = gld4(same + (g1 + 1) * m2 + g2);
+    }
+  }
 
   for (int i = threadIdx.x; i < J2; i += NT) s_x2[i] = r2 + i < l2 ? r2 + i : -1;
   for (int i = threadIdx.x; i < J1; i += NT) s_x1[i] = D >= 2 ? (r1 + i < l1 ? (r1 + i) * l2 : -1) : 0;
@@ -225,6 +282,32 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
       if (g2 < m2) gst(out + g2, fmaf(alpha, gld(same + g2), beta * s_a[p]));
     }
   } else if constexpr (D == 2) {
+    if (fast) {
+      if (threadIdx.x < NT2) {
+        // the arithmetic of synthesis_pass per output (oldest window sample first)
+        const int c4 = threadIdx.x % C4, ch = threadIdx.x / C4;
+        float4 lo[H];
+#pragma unroll
+        for (int j = 0; j < H; ++j) lo[j] = *reinterpret_cast<const float4*>(s_a + (ch + j) * U2P + 4 * c4);
+        float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0;
+#pragma unroll
+        for (int j = H - 1; j >= 0; --j) {
+          const float4 v = lo[H - 1 - j];
+          e0.x = fmaf(f.h[2 * j], v.x, e0.x); e1.x = fmaf(f.h[2 * j + 1], v.x, e1.x);
+          e0.y = fmaf(f.h[2 * j], v.y, e0.y); e1.y = fmaf(f.h[2 * j + 1], v.y, e1.y);
+          e0.z = fmaf(f.h[2 * j], v.z, e0.z); e1.z = fmaf(f.h[2 * j + 1], v.z, e1.z);
+          e0.w = fmaf(f.h[2 * j], v.w, e0.w); e1.w = fmaf(f.h[2 * j + 1], v.w, e1.w);
+        }
+        const int g1 = o1 + 2 * ch, g2 = o2 + 4 * c4;
+        if (g1 < m1)
+          gst4(out + g1 * m2 + g2, make_float4(fmaf(alpha, xs0.x, beta * e0.x), fmaf(alpha, xs0.y, beta * e0.y),
+                                               fmaf(alpha, xs0.z, beta * e0.z), fmaf(alpha, xs0.w, beta * e0.w)));
+        if (g1 + 1 < m1)
+          gst4(out + (g1 + 1) * m2 + g2, make_float4(fmaf(alpha, xs1.x, beta * e1.x), fmaf(alpha, xs1.y, beta * e1.y),
+                                                     fmaf(alpha, xs1.z, beta * e1.z), fmaf(alpha, xs1.w, beta * e1.w)));
+      }
+      return;
+    }
     synthesis_pass<L, P1, false, true, NT>(
         U2, U1 / 2 / P1, f,
         [&](int c, int j0, float* lo, float*) {
@@ -296,7 +379,7 @@ constexpr int kSymThreads = 256;
 
 SymTiles sym_tiles(int D, int L) {
   if (D == 1) return {{1, 1, 256}, {1, 1, 512}};
-  if (D == 2) return {{1, 16, 32}, {1, 32, 64}};
+  if (D == 2) return {{1, 16, 64}, {1, 32, 64}};
   if (L <= 4) return {{4, 8, 16}, {8, 8, 32}};
   if (L <= 8) return {{4, 4, 16}, {8, 8, 32}};
   return {{2, 4, 16}, {8, 8, 32}};
@@ -309,7 +392,7 @@ hipError_t launch_sym_level(bool up, const SymTask& t, int64_t grid, const Filte
     else hipLaunchKernelGGL((k_sym_down<1, L, 1, 1, 256, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
   } else if constexpr (D == 2) {
     if (up) hipLaunchKernelGGL((k_sym_up<2, L, 1, 32, 64, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
-    else hipLaunchKernelGGL((k_sym_down<2, L, 1, 16, 32, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    else hipLaunchKernelGGL((k_sym_down<2, L, 1, 16, 64, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
   } else {
     if (up) {
       hipLaunchKernelGGL((k_sym_up<3, L, 8, 8, 32, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);

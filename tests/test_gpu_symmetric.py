@@ -28,6 +28,9 @@ CASES = [
     ((64, 64), 2, 8, 5, 1.0),
     ((100, 33), 1, 6, 3, -0.5),
     ((128, 128), 1, 4, 5, 1.0),
+    ((45, 128), 2, 4, 3, 1.5),
+    ((100, 256), 1, 8, 4, 1.0),
+    ((66, 392), 1, 2, 3, 0.5),
     ((513, 257), 1, 8, 7, 1.5),
     ((1, 5, 2), 2, 3, 2, 1.0),
     ((6, 6, 6), 1, 1, 2, 1.0),
