@@ -23,6 +23,7 @@ Everything is done in mpmath at 60 significant digits and rounded once to
 float64 at the end.
 """
 
+import threading
 from functools import lru_cache
 
 import mpmath as mp
@@ -39,8 +40,19 @@ def _convolve(p, q):
     return out
 
 
-@lru_cache(maxsize=None)
+# mpmath's working precision is process-wide state: a derivation running in one thread while
+# another enters or leaves its own precision block would run at the wrong precision.  Callers
+# that map the oracle over a pool of threads therefore derive each filter under this lock.
+_MP_LOCK = threading.Lock()
+
+
 def _lowpass_mp(order):
+    with _MP_LOCK:
+        return _lowpass_mp_cached(order)
+
+
+@lru_cache(maxsize=None)
+def _lowpass_mp_cached(order):
     if not (1 <= order <= MAX_ORDER):
         raise ValueError(f"order must be in 1..{MAX_ORDER}, got {order}")
     with mp.workdps(60):
