@@ -262,9 +262,17 @@ def other_workloads(args, es, inputs, torch, np):
     outs = [torch.empty_like(a) for a in ins]
     plan = es.RaggedPlan(descs, es.OP_COV)
     nvr = sum(a.numel() for a in ins)
+    tg0 = _time(lambda: plan(ins, outs, graph=True), torch, reps)
+    te0 = _time(lambda: plan(ins, outs, graph=False), torch, reps)
+    launches0 = plan.num_launches
+    # the plan's autotuner: coarse fusion depth, then the tile choice of every merged launch
+    t0 = time.perf_counter()
+    plan.autotune(ins, outs, reps=2)
+    t_tune = time.perf_counter() - t0
     tg = _time(lambda: plan(ins, outs, graph=True), torch, reps)
     te = _time(lambda: plan(ins, outs, graph=False), torch, reps)
     launches = plan.num_launches
+    tcfg = plan.config()
     plan.close()
     # the same plan run persistently (one launch per dimensionality and filter length, per-XCD
     # work-item queues), after its autotuner chose the coarse fusion depth and the pipeline lag
@@ -286,6 +294,8 @@ def other_workloads(args, es, inputs, torch, np):
         "voxels": nvr, "launches_per_call": launches, "graph_ms": round(1e3 * tg, 3),
         "voxels_per_s_graph": round(nvr / tg, 1), "effective_GBps_graph": round(8 * nvr / tg / 1e9, 1),
         "eager_plan_ms": round(1e3 * te, 3),
+        "untuned": {"graph_ms": round(1e3 * tg0, 3), "eager_ms": round(1e3 * te0, 3), "launches_per_call": launches0},
+        "tuned_coarse_limit": tcfg[0], "autotune_s": round(t_tune, 2),
         "persistent_graph_ms": round(1e3 * tpg, 3), "persistent_launches": plaunch,
         "persistent_config": {"coarse_limit": pcfg[0], "lag": pcfg[1], "work_items": pcfg[2]},
         "plain_per_instance_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tg, 2)}

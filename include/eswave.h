@@ -277,18 +277,24 @@ int32_t es_plan_is_persistent(const es_plan* plan);
  * run persistently. */
 es_status es_plan_errors(es_plan* plan, void* stream);
 
-/* Chooses a persistent plan's coarse fusion depth (largest block its coarse step takes: 2048 or
- * 512 floats) and the pipeline lag of its item order by timing each candidate (eager launches,
- * HIP events on `stream`, synchronising; fastest of three rounds of `reps` executions) on the
- * caller's buffers, then rebuilds the plan with the fastest (the captured graph is rebuilt on
- * the next es_plan_execute).  Leaves a correct result of the last candidate in `out`; a no-op
- * for plans that do not run persistently.  The coarse fusion depth changes the summation order,
- * so results of different choices agree to rounding only. */
+/* Tunes the plan on the caller's buffers by timing candidates (eager launches, HIP events on
+ * `stream`, synchronising; fastest of three rounds of `reps` executions), keeps the fastest and
+ * leaves the tuned plan's result in `out`; the captured graph is rebuilt on the next
+ * es_plan_execute.
+ *   Phase-merged plans: (1) for matern_cov_apply / matern_sample, the coarse fusion depth (largest
+ *   block the coarse-level kernel takes: 16384, 4096 or 1024 floats), each candidate a plan rebuilt
+ *   with that limit and timed as a whole; (2) the tile choice of every merged launch (tile variant,
+ *   and kernel family where a level has two), launches with the most work-groups first, each
+ *   candidate timed inside the whole plan.
+ *   Persistent plans: the coarse fusion depth (2048 or 512 floats) and the pipeline lag of the item
+ *   order.
+ * Tile choices give identical results; the coarse fusion depth changes the summation order, so
+ * results of different depths agree to rounding only.  Same pointer rules as es_plan_execute. */
 es_status es_plan_autotune(es_plan* plan, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
                            int32_t reps, void* stream);
 
-/* The persistent configuration in use: coarse limit (floats), pipeline lag, work items per
- * execution (-1 / -1.0 / 0 for plans that do not run persistently). */
+/* The configuration in use: coarse limit (floats; -1 for a phase-merged plan on the default limit),
+ * pipeline lag and work items per execution (-1.0 and 0 for plans that do not run persistently). */
 es_status es_plan_config(const es_plan* plan, int64_t* coarse_limit, double* lag, int64_t* items);
 
 /* Host-only plan checks (instrumentation; no device call, usable without a GPU).

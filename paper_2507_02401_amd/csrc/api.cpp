@@ -290,8 +290,12 @@ thread_local int64_t g_variant_batch = 0;
 // the small class: equal on 64 x 1024^2 db8, 2 % faster on 256 x 512^2 db6, 14 % on 16 x 256^2
 // db4.  The choice depends on the geometry only, never on the batch, so an instance gives the
 // same bits in any batch.  ESWAVE_TAIL_MAX overrides (capped at the large class).
+// Ragged plans whose coarse fusion depth was tuned (es_plan_autotune) set g_lp_coarse while their
+// schedules are frozen.
+thread_local int64_t g_lp_coarse = -1;
 int64_t lp_tail_limit(const Geo&) {
   if (g_mode.persist) return std::min<int64_t>(g_mode.coarse_limit, kPCoarseMax);
+  if (g_lp_coarse >= 0) return std::min<int64_t>(g_lp_coarse, kCoarseMaxBlockBig);
   const char* e = getenv("ESWAVE_TAIL_MAX");
   if (e && *e) return std::min<int64_t>(atoll(e), kCoarseMaxBlockBig);
   return kCoarseMaxBlockBig;
@@ -1178,6 +1182,7 @@ struct es_plan {
   std::vector<hipStream_t> cap_streams;
   std::vector<hipEvent_t> cap_events;
   std::vector<int> identity_inst;  // instances whose op is the identity (plain copy)
+  int64_t lp_coarse = -1;          // phase-merged cov / sample: largest coarse block (-1: the default)
   std::vector<std::vector<Launch>> frozen;  // per instance: its schedule at creation (sentinel pointers)
   bool host_only = false;                   // es_plan_create_host: tables only, no device resources
   // persistent execution (cov / sample): one launch per dimensionality over a work-item queue
@@ -1615,7 +1620,7 @@ void plan_layout(es_plan* p, bool persist) {
 
 // Host part of plan creation: geometries, workspace offsets, frozen schedules, launch groups and
 // host tables (no device call).
-es_status plan_build(const es_desc* descs, int32_t count, int op, es_plan** out) {
+es_status plan_build(const es_desc* descs, int32_t count, int op, es_plan** out, int64_t lp_coarse = -1) {
   *out = nullptr;
   if (count < 0 || (count > 0 && !descs)) return fail(ES_EINVAL, "descs must hold count >= 0 entries");
   if (op < 0 || op > 3) return fail(ES_EINVAL, "unknown op %d", op);
@@ -1665,8 +1670,11 @@ es_status plan_build(const es_desc* descs, int32_t count, int op, es_plan** out)
     }
     plan_layout(p, false);  // phase-merged after all: in-place level arrays
   }
+  p->lp_coarse = lp_coarse;
   for (int k = 0; k < count; ++k) {
+    g_lp_coarse = lp_coarse;
     st = instance_schedule_frozen(p, k, &scs[k]);
+    g_lp_coarse = -1;
     if (st != ES_OK) { delete p; return st; }
     if (scs[k].identity) { p->identity_inst.push_back(k); continue; }
     p->frozen[k] = scs[k].launches;
@@ -1878,6 +1886,140 @@ es_status persistent_rebuild(es_plan* p) {
   persistent_tables(p);
   p->tables_valid = false;
   return persistent_alloc(p);
+}
+
+// Device task tables of a phase-merged plan.
+es_status plan_alloc_tables(es_plan* p) {
+  const size_t nt = p->h_tasks.size(), ntail = p->h_tails.size();
+  if (nt && hipMalloc(&p->d_tasks, nt * sizeof(Task)) != hipSuccess) return fail(ES_ENOMEM, "task table allocation failed");
+  if (ntail && hipMalloc(&p->d_tails, ntail * sizeof(TailTask)) != hipSuccess)
+    return fail(ES_ENOMEM, "tail table allocation failed");
+  return ES_OK;
+}
+
+// Best of three rounds of `reps` eager executions (after one warm execution), in ms.
+es_status plan_time_eager(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes, int reps,
+                          hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* best) {
+  es_status st = es_plan_execute_eager(p, in, out, ws, ws_bytes, s);
+  *best = 1e30f;
+  for (int round = 0; round < 3 && st == ES_OK; ++round) {
+    if (hipEventRecord(e0, s) != hipSuccess) return fail(ES_EDEVICE, "hipEventRecord");
+    for (int r = 0; r < reps && st == ES_OK; ++r) st = es_plan_execute_eager(p, in, out, ws, ws_bytes, s);
+    float ms = 0.f;
+    if (st == ES_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      st = fail(ES_EDEVICE, "event timing failed");
+    if (st == ES_OK) *best = std::min(*best, ms);
+  }
+  return st;
+}
+
+// Tuning of a phase-merged plan.
+//  1. Coarse fusion depth (cov / sample): the largest block the coarse-level kernel takes, among
+//     16384, 4096 and 1024 floats; each candidate is a plan rebuilt with that limit and timed as a
+//     whole (it changes the launch count and the summation order: results agree to rounding).
+//  2. Tile choice of every launch group (tile variant, and kernel family where a level has two),
+//     greedily in decreasing order of work-groups, each candidate timed inside the whole plan
+//     (bit-identical results).  A candidate whose tiles fail the host footprint checks is skipped.
+es_status plan_autotune_merged(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
+                               int reps, hipStream_t s) {
+  ES_HIP(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  plan_drop_graph(p);  // re-captured by the next es_plan_execute
+  p->tables_valid = false;
+  hipEvent_t e0, e1;
+  ES_HIP(hipEventCreate(&e0), "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(ES_EDEVICE, "hipEventCreate"); }
+  es_status st = ES_OK;
+  bool has_tail = false;
+  for (const PlanGroup& gr : p->groups) has_tail = has_tail || gr.proto.is_tail;
+  if ((p->op == ES_OP_COV || p->op == ES_OP_SAMPLE) && has_tail) {
+    const int n = (int)p->geos.size();
+    std::vector<es_desc> descs(n);
+    for (int k = 0; k < n; ++k) {
+      const Geo& g = p->geos[k];
+      es_desc d{};
+      d.ndim = g.D;
+      d.order = g.L / 2;
+      for (int a = 0; a < g.D; ++a) d.shape[a] = g.n[3 - g.D + a];
+      d.levels = g.m;
+      d.s = g.s;
+      descs[k] = d;
+    }
+    float t_cur = 0.f;
+    st = plan_time_eager(p, in, out, ws, ws_bytes, reps, s, e0, e1, &t_cur);
+    const int64_t cands[] = {kCoarseMaxBlockBig, kCoarseMaxBlock, kCoarseMaxBlock / 4};
+    for (int64_t c : cands) {
+      if (st != ES_OK) break;
+      if (c == (p->lp_coarse < 0 ? kCoarseMaxBlockBig : p->lp_coarse)) continue;
+      es_plan* q = nullptr;
+      st = plan_build(descs.data(), n, p->op, &q, c);
+      if (st != ES_OK) break;
+      q->device = p->device;
+      st = plan_alloc_tables(q);
+      float t = 0.f;
+      if (st == ES_OK) st = plan_time_eager(q, in, out, ws, ws_bytes, reps, s, e0, e1, &t);
+      if (st == ES_OK && t < t_cur) {
+        t_cur = t;
+        std::swap(*p, *q);  // p takes the faster plan; q now holds the previous one
+      }
+      if (hipDeviceSynchronize() != hipSuccess && st == ES_OK) st = fail(ES_EDEVICE, "hipDeviceSynchronize");
+      es_plan_destroy(q);
+    }
+  }
+  // 2. tile choices, groups with the most work-groups first (tables filled by the last execution)
+  if (st == ES_OK) st = es_plan_execute_eager(p, in, out, ws, ws_bytes, s);
+  std::vector<int> order;
+  for (int gi = 0; gi < (int)p->groups.size(); ++gi)
+    if (!p->groups[gi].proto.is_tail) order.push_back(gi);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return p->groups[a].total_wg > p->groups[b].total_wg; });
+  for (int gi : order) {
+    if (st != ES_OK) break;
+    PlanGroup& gr = p->groups[gi];
+    const Launch proto0 = gr.proto;
+    std::vector<Launch> keep(gr.inst.size());
+    for (size_t q = 0; q < gr.inst.size(); ++q) keep[q] = p->frozen[gr.inst[q]][gr.step[q]];
+    auto apply = [&](int c) {
+      for (size_t q = 0; q < gr.inst.size(); ++q) {
+        Launch l = keep[q];
+        apply_choice(l, p->geos[gr.inst[q]], c, 1);
+        p->frozen[gr.inst[q]][gr.step[q]] = l;
+        if (q == 0) gr.proto = l;
+      }
+      gr.proto.lds = proto0.lds;
+      p->tables_valid = false;
+    };
+    const int nc = num_choices(proto0);
+    int best = -1;
+    float t_best = 1e30f;
+    for (int c = 0; c < nc && st == ES_OK; ++c) {
+      apply(c);
+      bool same = true;  // every member must take the same kernel instantiation
+      for (size_t q = 0; q < gr.inst.size(); ++q) same = same && same_kernel(p->frozen[gr.inst[q]][gr.step[q]], gr.proto);
+      if (!same) continue;
+      float t = 0.f;
+      st = plan_time_eager(p, in, out, ws, ws_bytes, reps, s, e0, e1, &t);
+      if (st == ES_EINVAL) { st = ES_OK; continue; }  // tiles refused by the footprint checks
+      if (st == ES_OK && t < t_best) { t_best = t; best = c; }
+    }
+    if (st != ES_OK) break;
+    if (best < 0) {  // no candidate ran: keep the frozen launches
+      for (size_t q = 0; q < gr.inst.size(); ++q) p->frozen[gr.inst[q]][gr.step[q]] = keep[q];
+      gr.proto = proto0;
+      p->tables_valid = false;
+    } else {
+      apply(best);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != ES_OK) return st;
+  // the timing runs repeated in-place launches: recompute the result with the tuned plan
+  st = es_plan_execute_eager(p, in, out, ws, ws_bytes, s);
+  if (st == ES_OK) ES_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+  plan_drop_graph(p);
+  p->tables_valid = false;
+  return st;
 }
 
 }  // namespace
@@ -2092,9 +2234,8 @@ es_status es_plan_create(const es_desc* descs, int32_t count, int op, void* stre
     *out = p;
     return ES_OK;
   }
-  const size_t nt = p->h_tasks.size(), ntail = p->h_tails.size();
-  if (nt && hipMalloc(&p->d_tasks, nt * sizeof(Task)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "task table allocation failed"); }
-  if (ntail && hipMalloc(&p->d_tails, ntail * sizeof(TailTask)) != hipSuccess) { es_plan_destroy(p); return fail(ES_ENOMEM, "tail table allocation failed"); }
+  st = plan_alloc_tables(p);
+  if (st != ES_OK) { es_plan_destroy(p); return st; }
   *out = p;
   return ES_OK;
 }
@@ -2246,9 +2387,15 @@ es_status es_plan_errors(es_plan* p, void* stream) {
 es_status es_plan_autotune(es_plan* p, const float* const* in, float* const* out, void* ws, size_t ws_bytes,
                            int32_t reps, void* stream) {
   if (!p) return fail(ES_EINVAL, "plan is NULL");
-  if (!p->persistent || p->geos.empty()) return ES_OK;
+  if (p->geos.empty()) return ES_OK;
+  if (p->host_only) return fail(ES_EINVAL, "plan was created by es_plan_create_host (no device resources)");
   if (reps < 1) reps = 3;
   const hipStream_t s = (hipStream_t)stream;
+  if (!p->persistent) {
+    const es_status st0 = plan_check_io(p, in, out, ws, ws_bytes);
+    if (st0 != ES_OK) return st0;
+    return plan_autotune_merged(p, in, out, ws, ws_bytes, reps, s);
+  }
   // candidates: coarse fusion depth (largest block the coarse step takes) x pipeline lag
   const int64_t coarse[] = {kPCoarseMax, kPCoarseMax / 4};
   const double lags[] = {0.25, 1.0, 4.0, 64.0};
@@ -2293,7 +2440,8 @@ es_status es_plan_autotune(es_plan* p, const float* const* in, float* const* out
 
 es_status es_plan_config(const es_plan* p, int64_t* coarse_limit, double* lag, int64_t* items) {
   if (!p) return fail(ES_EINVAL, "plan is NULL");
-  if (coarse_limit) *coarse_limit = p->persistent ? p->coarse_limit : -1;
+  if (coarse_limit)
+    *coarse_limit = p->persistent ? p->coarse_limit : (p->lp_coarse >= 0 ? p->lp_coarse : -1);
   if (lag) *lag = p->persistent ? p->lag : -1.0;
   if (items) {
     int64_t n = 0;

@@ -257,7 +257,8 @@ class RaggedPlan:
         return ip, op
 
     def config(self):
-        """(coarse limit, pipeline lag, work items per execution) of a persistent plan."""
+        """(coarse limit, pipeline lag, work items per execution): -1 / -1.0 / 0 where they do not
+        apply (a phase-merged plan on the default coarse limit)."""
         c, l, n = ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
         check(self.lib.es_plan_config(self._p, ctypes.byref(c), ctypes.byref(l), ctypes.byref(n)))
         return int(c.value), float(l.value), int(n.value)
@@ -269,8 +270,9 @@ class RaggedPlan:
             check(self.lib.es_plan_errors(self._p, stream))
 
     def autotune(self, inputs, outputs=None, reps=3):
-        """Time the persistent plan's coarse fusion depth and pipeline lag on these buffers and keep
-        the fastest (es_plan_autotune)."""
+        """Tune the plan on these buffers and keep the fastest (es_plan_autotune): coarse fusion depth
+        and per-launch tile choices (phase-merged), or coarse fusion depth and pipeline lag
+        (persistent)."""
         if outputs is None:
             outputs = [torch.empty_like(x) for x in inputs]
         ip, op = self._ptrs(inputs, outputs)

@@ -115,3 +115,32 @@ def test_ragged_200_instances():
         ref = oracle.matern_cov_apply(d["xs"][k].astype(np.float64), o, m, s)
         assert rel_l2(outs[k].cpu().numpy(), ref) <= TOL, (k, sh, o, m, s)
     plan.close()
+
+
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_plan_autotune_phase_merged(op):
+    """es_plan_autotune on a phase-merged plan: the tuned plan (coarse fusion depth for cov / sample,
+    tile choice per merged launch) still matches the oracle, its graph replays equal its eager
+    execution bit for bit, the result left by the tuner equals both, and the chosen depth is one of
+    the candidates."""
+    gen = np.random.default_rng(20 + op)
+    xs = [gen.standard_normal(d[0]).astype(np.float32) for d in MIXED]
+    ins = [torch.from_numpy(x).to(DEV) for x in xs]
+    say("plan autotune", OP_NAMES[op])
+    plan = es.RaggedPlan(MIXED, op)
+    assert not plan.persistent
+    left = [y.cpu().numpy() for y in plan.autotune(ins, reps=2)]
+    coarse, lag, items = plan.config()
+    assert coarse in (-1, 16384, 4096, 1024) and lag == -1.0 and items == 0
+    eager = [y.cpu().numpy() for y in plan(ins, graph=False)]
+    for k, (shape, order, levels, s) in enumerate(MIXED):
+        ref = ORACLE_OPS[op](xs[k].astype(np.float64), order, levels, s)
+        assert rel_l2(eager[k], ref) <= TOL, (k, shape)
+        assert np.array_equal(left[k], eager[k]), k
+    outs = [torch.empty_like(x) for x in ins]
+    for rep in range(2):
+        plan(ins, outs, graph=True)
+        torch.cuda.synchronize()
+        for k in range(len(MIXED)):
+            assert np.array_equal(outs[k].cpu().numpy(), eager[k]), (rep, k)
+    plan.close()
