@@ -2025,6 +2025,72 @@ es_status plan_autotune_merged(es_plan* p, const float* const* in, float* const*
 }  // namespace
 
 namespace es {
+
+int64_t cov_dot_partials_max(int ndim, const int64_t* shape) {
+  if (ndim != 2 || !shape || shape[0] < 1 || shape[1] < 1) return 0;
+  int64_t best = 0;
+  for (int v = 0; v < kNumVariants; ++v) {
+    const TileShape ts = tile_shape(K_LP_UP, 2, v, kMaxTaps);  // 2-D synthesis tiles do not depend on the taps
+    best = std::max<int64_t>(best, ((shape[0] + ts.t[1] - 1) / ts.t[1]) * ((shape[1] + ts.t[2] - 1) / ts.t[2]));
+  }
+  return best;
+}
+
+es_status cov_apply_masked_dot(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                               const float* x, float* y, void* ws, size_t ws_bytes, const float* mask, float gamma,
+                               float scale, float* partials, int64_t partials_cap, int64_t* per, hipStream_t stream) {
+  Geo g;
+  es_status st = make_geo(ndim, shape, order, levels, s, &g);
+  if (st != ES_OK) return st;
+  if (ndim != 2 || levels <= 1 || batch < 1 || batch > 0x7fffffffll)
+    return fail(ES_EUNSUPPORTED, "the fused solver step needs a 2-D geometry, at least 2 levels and 1 <= batch < 2^31");
+  const size_t need = (size_t)batch * (size_t)ws_floats_per_instance(g) * sizeof(float);
+  st = check_io(x, y, batch, g.N(), ws, ws_bytes, need);
+  if (st != ES_OK) return st;
+  if (stream_count(g, batch) > 1) return fail(ES_EUNSUPPORTED, "sub-batch streams split this schedule");
+  Schedule sc;
+  st = build_schedule(ES_OP_COV, g, batch, x, y, (float*)ws, &sc);
+  if (st != ES_OK) return st;
+  if (sc.identity || sc.launches.empty()) return fail(ES_EUNSUPPORTED, "identity schedule");
+  const Launch& last = sc.launches.back();
+  if (last.is_tail || last.kind != K_LP_UP || !last.vec || last.task.out0 != y || last.task.in1 != x)
+    return fail(ES_EUNSUPPORTED, "the schedule does not end in a 2-D vector-path synthesis of x");
+  const int64_t tpi = last.task.tiles_per_inst;
+  if (!partials || tpi * batch > partials_cap) return fail(ES_EINVAL, "partial-sum buffer too small");
+  Region reg[3];
+  const int nreg = call_regions(x, y, batch * g.N() * (int64_t)sizeof(float), ws, need, reg);
+  st = check_schedule(sc, reg, nreg);
+  if (st != ES_OK) return st;
+  st = check_device();
+  if (st != ES_OK) return st;
+  for (size_t j = 0; j + 1 < sc.launches.size(); ++j) {
+    const Launch& l = sc.launches[j];
+    const int64_t total = (l.is_tail ? 1 : l.task.tiles_per_inst) * batch;
+    if (total > 0x7fffffffll) return fail(ES_EINVAL, "too many work-groups in one launch");
+    st = run_launch(l, sc.f, stream, nullptr, 1, (int)total, nullptr);
+    if (st != ES_OK) return st;
+  }
+  Task t = last.task;
+  t.in2 = mask;
+  t.bs_in2 = g.N();
+  t.gamma = mask ? gamma : 0.f;
+  t.alpha *= scale;
+  t.beta *= scale;
+  t.out1 = partials;
+  const int64_t total = tpi * batch;
+  if (total > 0x7fffffffll) return fail(ES_EINVAL, "too many work-groups in one launch");
+  TaskArgs a{};
+  a.table = nullptr;
+  a.count = 1;
+  a.total_wg = (int)total;
+  a.vec = 1;
+  a.reverse = last.reverse;
+  a.t0 = t;
+  ES_HIP(launch_lp_up_cge(last.L, last.variant, a, (int)round8(total), sc.f, stream), "fused solver step launch");
+  *per = tpi;
+  return ES_OK;
+}
+
 es_status report_error(es_status st, const char* msg) {
   g_last_error = msg;
   return st;

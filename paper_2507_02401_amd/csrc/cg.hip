@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "../../include/eswave.h"
@@ -231,7 +232,7 @@ struct CgLayout {
   size_t r, z, d, ad, part, scal, cov, total;
 };
 
-CgLayout cg_layout(int64_t n, int64_t batch, size_t cov_bytes) {
+CgLayout cg_layout(int64_t n, int64_t batch, size_t cov_bytes, int64_t parts) {
   CgLayout L;
   const size_t vec = a256((size_t)(n * batch) * sizeof(float));
   L.r = 0;
@@ -239,7 +240,7 @@ CgLayout cg_layout(int64_t n, int64_t batch, size_t cov_bytes) {
   L.d = L.z + vec;
   L.ad = L.d + vec;
   L.part = L.ad + vec;
-  L.scal = L.part + a256((size_t)(cg_parts(n) * batch) * sizeof(float));
+  L.scal = L.part + a256((size_t)(parts * batch) * sizeof(float));
   L.cov = L.scal + a256((size_t)batch * sizeof(CgScal));
   L.total = L.cov + cov_bytes;
   return L;
@@ -257,7 +258,7 @@ size_t es_tikhonov_pcg_workspace_bytes(int ndim, const int64_t* shape, int64_t b
   int64_t n = 1;
   for (int k = 0; k < ndim; ++k) n *= shape[k];
   const size_t cov = es_workspace_bytes(ndim, shape, batch, order, levels, ES_OP_COV);
-  return cg_layout(n, batch, cov).total;
+  return cg_layout(n, batch, cov, std::max(cg_parts(n), cov_dot_partials_max(ndim, shape))).total;
 }
 
 es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s, double alpha,
@@ -284,7 +285,9 @@ es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int ord
   // validates the operator arguments (order, levels, divisibility) through the workspace query
   const size_t cov = es_workspace_bytes(ndim, shape, batch, order, levels, ES_OP_COV);
   if (cov == 0 && levels > 1) return report_error(ES_EINVAL, "invalid operator arguments (order, levels, shape)");
-  const CgLayout L = cg_layout(n, batch, cov);
+  // partial sums: per-chunk (element-wise kernels) or per-tile (the fused operator steps)
+  const int64_t parts = std::max(per, cov_dot_partials_max(ndim, shape));
+  const CgLayout L = cg_layout(n, batch, cov, parts);
   if (!p || !mask || !x || !rel_residual) return report_error(ES_EINVAL, "p, mask, x and rel_residual must be non-NULL");
   if (((uintptr_t)p | (uintptr_t)mask | (uintptr_t)x) & 15) return report_error(ES_EINVAL, "p, mask and x must be 16-byte aligned");
   if (!ws || ws_bytes < L.total) {
@@ -319,9 +322,22 @@ es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int ord
     snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
     return report_error(ES_EDEVICE, msg);
   };
-  auto final_ = [&](int kind) -> es_status {
-    hipLaunchKernelGGL(k_cg_final, dim3((unsigned)batch), blk, 0, hs, kind, (int)per, part, sc, frtol);
+  auto final_ = [&](int kind, int64_t nparts) -> es_status {
+    hipLaunchKernelGGL(k_cg_final, dim3((unsigned)batch), blk, 0, hs, kind, (int)nparts, part, sc, frtol);
     return ok("CG scalar update launch");
+  };
+  // Fused operator steps (2-D grids whose operator ends in the vector-path synthesis): the last
+  // kernel of the operator also forms the mask term and the per-tile inner products, so the
+  // separate update / inner-product passes over the vectors disappear.  Falls back to the
+  // separate kernels when the schedule does not allow it.
+  const char* fz = getenv("ESWAVE_CG_FUSED");  // 0: always the separate kernels (comparison)
+  bool fused = cov_dot_partials_max(ndim, shape) > 0 && !(fz && *fz == '0');
+  // out = scale * op(in) + gamma * mask * in, and part = per-tile sums of in * out
+  auto cov_dot = [&](const float* in, float* out, double sm, const float* msk, float scale, int64_t* np) -> es_status {
+    const es_status r = cov_apply_masked_dot(ndim, shape, batch, order, levels, sm, in, out, cws, cov, msk, 1.f, scale,
+                                             part, parts * batch, np, hs);
+    if (r == ES_EUNSUPPORTED) fused = false;
+    return r;
   };
   auto cov_apply = [&](const float* in, float* out, double sm) -> es_status {
     return matern_cov_apply(ndim, shape, batch, order, levels, sm, in, out, cws, cov, stream);
@@ -329,26 +345,38 @@ es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int ord
 
   // r = b = M p, x = 0, ||b||; z = P r, d = z, rz = r . z
   hipLaunchKernelGGL(k_cg_init, grid, blk, 0, hs, n, (int)per, p, mask, x, r, part);
-  if ((st = ok("CG init launch")) != ES_OK || (st = final_(F_INIT)) != ES_OK) return st;
+  if ((st = ok("CG init launch")) != ES_OK || (st = final_(F_INIT, per)) != ES_OK) return st;
   if ((st = cov_apply(r, z, s)) != ES_OK) return st;
   hipLaunchKernelGGL(k_cg_dot, grid, blk, 0, hs, n, (int)per, r, z, d, part);
-  if ((st = ok("CG dot launch")) != ES_OK || (st = final_(F_RZ0)) != ES_OK) return st;
+  if ((st = ok("CG dot launch")) != ES_OK || (st = final_(F_RZ0, per)) != ES_OK) return st;
 
   std::vector<CgScal> host((size_t)batch);
   int it = 0;
   bool done = false;
   while (it < max_iter && !done) {
     // ad = alpha Gamma^2 d + M d, a = rz / (d . ad)
-    if ((st = cov_apply(d, ad, -s)) != ES_OK) return st;
-    hipLaunchKernelGGL(k_cg_apply, grid, blk, 0, hs, n, (int)per, (float)alpha, mask, d, ad, part);
-    if ((st = ok("CG operator update launch")) != ES_OK || (st = final_(F_A)) != ES_OK) return st;
+    int64_t np = per;
+    st = fused ? cov_dot(d, ad, -s, mask, (float)alpha, &np) : ES_EUNSUPPORTED;
+    if (st == ES_EUNSUPPORTED) {
+      np = per;
+      if ((st = cov_apply(d, ad, -s)) != ES_OK) return st;
+      hipLaunchKernelGGL(k_cg_apply, grid, blk, 0, hs, n, (int)per, (float)alpha, mask, d, ad, part);
+      st = ok("CG operator update launch");
+    }
+    if (st != ES_OK || (st = final_(F_A, np)) != ES_OK) return st;
     // x += a d, r -= a ad, rel = ||r|| / ||b||
     hipLaunchKernelGGL(k_cg_step, grid, blk, 0, hs, n, (int)per, sc, x, r, d, ad, part);
-    if ((st = ok("CG step launch")) != ES_OK || (st = final_(F_RR)) != ES_OK) return st;
+    if ((st = ok("CG step launch")) != ES_OK || (st = final_(F_RR, per)) != ES_OK) return st;
     // z = P r, beta = (r . z) / rz, d = z + beta d
-    if ((st = cov_apply(r, z, s)) != ES_OK) return st;
-    hipLaunchKernelGGL(k_cg_dot, grid, blk, 0, hs, n, (int)per, r, z, (float*)nullptr, part);
-    if ((st = ok("CG dot launch")) != ES_OK || (st = final_(F_BETA)) != ES_OK) return st;
+    np = per;
+    st = fused ? cov_dot(r, z, s, nullptr, 1.f, &np) : ES_EUNSUPPORTED;
+    if (st == ES_EUNSUPPORTED) {
+      np = per;
+      if ((st = cov_apply(r, z, s)) != ES_OK) return st;
+      hipLaunchKernelGGL(k_cg_dot, grid, blk, 0, hs, n, (int)per, r, z, (float*)nullptr, part);
+      st = ok("CG dot launch");
+    }
+    if (st != ES_OK || (st = final_(F_BETA, np)) != ES_OK) return st;
     hipLaunchKernelGGL(k_cg_dir, grid, blk, 0, hs, n, (int)per, sc, d, z);
     if ((st = ok("CG direction launch")) != ES_OK) return st;
     ++it;

@@ -219,6 +219,22 @@ hipError_t launch_norm_finalize(const float2* partials, const NormSegs& segs, fl
 // Sum of squares of each of `batch` contiguous instances of n floats (identity transform).
 hipError_t launch_sumsq(const float* x, int64_t n, int64_t batch, float* out, hipStream_t stream);
 
+// LP_UP (2-D, vector path) with the solver epilogue: args.t0.in2 = mask, t0.gamma its coefficient,
+// t0.out1 = one float per work-group (sum of same * out).  Tile variant as for K_LP_UP.
+hipError_t launch_lp_up_cge(int taps, int variant, const TaskArgs& args, int grid, const Filter& f,
+                            hipStream_t stream);
+
+// matern_cov_apply whose last launch is the 2-D vector-path synthesis with the solver epilogue:
+//   y = (scale * w_1 + gamma * mask) x + scale * A^T z_1,
+// and partials[b * per + k] = the k-th work-group's sum of x * y over instance b (per = the
+// launch's tiles per instance, written to *per).  Returns ES_EUNSUPPORTED, enqueueing nothing,
+// when the geometry's schedule does not end in such a launch (then run the steps separately).
+es_status cov_apply_masked_dot(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                               const float* x, float* y, void* ws, size_t ws_bytes, const float* mask, float gamma,
+                               float scale, float* partials, int64_t partials_cap, int64_t* per, hipStream_t stream);
+// Largest `per` cov_apply_masked_dot can produce for this grid (0 when it never applies).
+int64_t cov_dot_partials_max(int ndim, const int64_t* shape);
+
 // Host filter derivation (filters.cpp).
 bool daubechies_filter(int order, double* h_out);
 

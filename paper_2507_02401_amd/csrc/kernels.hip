@@ -58,6 +58,17 @@ __global__ void __launch_bounds__(NT) k_lp_up(TaskArgs args, Filter f) {
   lp_up_tile<D, L, U0, U1, U2, NT, VEC>(t, wg, f, sm);
 }
 
+// LP_UP with the conjugate-gradient solver's epilogue (2-D vector path): out = (alpha + gamma m)
+// same + beta A^T z, and each work-group's sum of same * out (see lp_up_tile).
+template <int L, int U1, int U2, int NT>
+__global__ void __launch_bounds__(NT) k_lp_up_cge(TaskArgs args, Filter f) {
+  __shared__ LpUpSmem<2, L, 1, U1, U2> sm;
+  const int wg = logical_wg(args.total_wg, args.reverse);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  lp_up_tile<2, L, 1, U1, U2, NT, true, true>(t, wg, f, sm);
+}
+
 // ---------------------------------------------------------------------------------------
 // LP_UP2 (2-D): two synthesis levels of the projection form in one kernel,
 //   z1  = gamma*a1 + delta*A^T z2   (level i+1, only on the halo region this tile needs)
@@ -1320,7 +1331,35 @@ hipError_t launch_plain_l(const PlainPass& p, const Filter& f, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int L, int V>
+hipError_t launch_cge_lv(const TaskArgs& a, int grid, const Filter& f, hipStream_t s) {
+  hipLaunchKernelGGL((k_lp_up_cge<L, shape_of(K_LP_UP, 2, V, L).b, shape_of(K_LP_UP, 2, V, L).c, kThreads>), dim3(grid),
+                     dim3(kThreads), 0, s, a, f);
+  return hipGetLastError();
+}
+
+template <int L>
+hipError_t launch_cge_l(int variant, const TaskArgs& a, int grid, const Filter& f, hipStream_t s) {
+  if (variant == 0) return launch_cge_lv<L, 0>(a, grid, f, s);
+  if (variant == 2) return launch_cge_lv<L, 2>(a, grid, f, s);
+  return launch_cge_lv<L, 1>(a, grid, f, s);
+}
+
 }  // namespace
+
+hipError_t launch_lp_up_cge(int taps, int variant, const TaskArgs& a, int grid, const Filter& f, hipStream_t s) {
+  switch (taps) {
+    case 2: return launch_cge_l<2>(variant, a, grid, f, s);
+    case 4: return launch_cge_l<4>(variant, a, grid, f, s);
+    case 6: return launch_cge_l<6>(variant, a, grid, f, s);
+    case 8: return launch_cge_l<8>(variant, a, grid, f, s);
+    case 10: return launch_cge_l<10>(variant, a, grid, f, s);
+    case 12: return launch_cge_l<12>(variant, a, grid, f, s);
+    case 14: return launch_cge_l<14>(variant, a, grid, f, s);
+    case 16: return launch_cge_l<16>(variant, a, grid, f, s);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArgs& args, int grid, const Filter& f,
                         hipStream_t stream) {

@@ -233,7 +233,10 @@ struct LpUpSmem {
 };
 
 // One LP_UP tile: work-group index `wg` of task `t`.
-template <int D, int L, int U0, int U1, int U2, int NT, bool VEC>
+// CGE (2-D vector path only; the conjugate-gradient solver's operator step): the output is
+// out = (alpha + gamma * m) * same + beta * (A^T z) with m = in2 (a per-element mask), and the
+// work-group's compensated sum of same * out goes to out1[wg - tile_begin] (one float).
+template <int D, int L, int U0, int U1, int U2, int NT, bool VEC, bool CGE = false>
 DEVI void lp_up_tile(const Task& t, int wg, const Filter& f, LpUpSmem<D, L, U0, U1, U2>& sm) {
   using G = UpGeom<D, L, U0, U1, U2>;
   constexpr int H = G::H;
@@ -258,7 +261,10 @@ DEVI void lp_up_tile(const Task& t, int wg, const Filter& f, LpUpSmem<D, L, U0, 
   constexpr int C4 = U2 / 4, PQ = 2;
   constexpr bool FAST2 = D == 2 && VEC && (U1 / 2) % PQ == 0;
   constexpr int NT2 = C4 * (U1 / 2 / PQ), IT2 = (NT2 + NT - 1) / NT;
+  static_assert(!CGE || FAST2, "the solver epilogue exists on the 2-D vector path only");
   float4 xs[FAST2 ? IT2 : 1][FAST2 ? 2 * PQ : 1];
+  float4 ms[CGE ? IT2 : 1][CGE ? 2 * PQ : 1];
+  const float* mask = CGE && t.in2 ? t.in2 + tl.inst * t.bs_in2 : nullptr;  // the same for the whole launch
   if constexpr (FAST2) {
 #pragma unroll
     for (int it = 0; it < IT2; ++it) {
@@ -268,10 +274,13 @@ DEVI void lp_up_tile(const Task& t, int wg, const Filter& f, LpUpSmem<D, L, U0, 
 #pragma unroll
       for (int r = 0; r < 2 * PQ; ++r) {
         const int g1 = tl.c1 * U1 + 2 * PQ * ch + r;
-        xs[it][r] = (task < NT2 && g1 < b1 && g2 < b2) ? gld4(same + g1 * b2 + g2) : make_float4(0.f, 0.f, 0.f, 0.f);
+        const bool in = task < NT2 && g1 < b1 && g2 < b2;
+        xs[it][r] = in ? gld4(same + g1 * b2 + g2) : make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (CGE) ms[it][r] = in && mask ? gld4(mask + g1 * b2 + g2) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
   }
+  KSum cg_acc;
 
   for (int i = threadIdx.x; i < G::NROW; i += NT) {
     const int i1 = i % G::J1, i0 = i / G::J1;
@@ -328,12 +337,27 @@ DEVI void lp_up_tile(const Task& t, int wg, const Filter& f, LpUpSmem<D, L, U0, 
           const int g1 = tl.c1 * U1 + 2 * (PQ * ch + q);
           if (g1 < b1 && g2 < b2) {
             const float4 s0 = xs[it][2 * q], s1 = xs[it][2 * q + 1];
-            const float4 y0 = make_float4(fmaf(alpha, s0.x, beta * e0.x), fmaf(alpha, s0.y, beta * e0.y),
-                                          fmaf(alpha, s0.z, beta * e0.z), fmaf(alpha, s0.w, beta * e0.w));
-            const float4 y1 = make_float4(fmaf(alpha, s1.x, beta * e1.x), fmaf(alpha, s1.y, beta * e1.y),
-                                          fmaf(alpha, s1.z, beta * e1.z), fmaf(alpha, s1.w, beta * e1.w));
-            gst4(out + g1 * b2 + g2, y0);
-            gst4(out + (g1 + 1) * b2 + g2, y1);
+            if constexpr (CGE) {
+              const float gm = t.gamma;
+              const float4 m0 = ms[it][2 * q], m1 = ms[it][2 * q + 1];
+              const float4 y0 = make_float4(
+                  fmaf(fmaf(gm, m0.x, alpha), s0.x, beta * e0.x), fmaf(fmaf(gm, m0.y, alpha), s0.y, beta * e0.y),
+                  fmaf(fmaf(gm, m0.z, alpha), s0.z, beta * e0.z), fmaf(fmaf(gm, m0.w, alpha), s0.w, beta * e0.w));
+              const float4 y1 = make_float4(
+                  fmaf(fmaf(gm, m1.x, alpha), s1.x, beta * e1.x), fmaf(fmaf(gm, m1.y, alpha), s1.y, beta * e1.y),
+                  fmaf(fmaf(gm, m1.z, alpha), s1.z, beta * e1.z), fmaf(fmaf(gm, m1.w, alpha), s1.w, beta * e1.w));
+              gst4(out + g1 * b2 + g2, y0);
+              gst4(out + (g1 + 1) * b2 + g2, y1);
+              cg_acc.add(s0.x * y0.x); cg_acc.add(s0.y * y0.y); cg_acc.add(s0.z * y0.z); cg_acc.add(s0.w * y0.w);
+              cg_acc.add(s1.x * y1.x); cg_acc.add(s1.y * y1.y); cg_acc.add(s1.z * y1.z); cg_acc.add(s1.w * y1.w);
+            } else {
+              const float4 y0 = make_float4(fmaf(alpha, s0.x, beta * e0.x), fmaf(alpha, s0.y, beta * e0.y),
+                                            fmaf(alpha, s0.z, beta * e0.z), fmaf(alpha, s0.w, beta * e0.w));
+              const float4 y1 = make_float4(fmaf(alpha, s1.x, beta * e1.x), fmaf(alpha, s1.y, beta * e1.y),
+                                            fmaf(alpha, s1.z, beta * e1.z), fmaf(alpha, s1.w, beta * e1.w));
+              gst4(out + g1 * b2 + g2, y0);
+              gst4(out + (g1 + 1) * b2 + g2, y1);
+            }
           }
         }
       }
@@ -384,6 +408,11 @@ DEVI void lp_up_tile(const Task& t, int wg, const Filter& f, LpUpSmem<D, L, U0, 
             gst(out + o + b2, fmaf(alpha, s1, beta * e1));
           }
         });
+  }
+  if constexpr (CGE) {
+    __shared__ float2 cg_sum;
+    store_wg_sum<NT>(cg_acc, &cg_sum);  // every thread; thread 0 holds the pair
+    if (threadIdx.x == 0) gst(t.out1 + (wg - t.tile_begin), cg_sum.x + cg_sum.y);
   }
 }
 

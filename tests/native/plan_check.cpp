@@ -20,6 +20,7 @@
 // The launchers live in the HIP kernels; the host-only paths never reach them.
 namespace es {
 hipError_t launch_level(int, int, int, int, const TaskArgs&, int, const Filter&, hipStream_t) { abort(); }
+hipError_t launch_lp_up_cge(int, int, const TaskArgs&, int, const Filter&, hipStream_t) { abort(); }
 hipError_t launch_tail(int, int, int, const TailArgs&, int, size_t, const Filter&, hipStream_t) { abort(); }
 hipError_t launch_plain_pass(const PlainPass&, int, const Filter&, hipStream_t) { abort(); }
 hipError_t launch_block_copy(const float*, float*, const int*, const int*, const int*, hipStream_t) { abort(); }
