@@ -245,9 +245,11 @@ def other_workloads(args, es, inputs, torch, np):
         "fwd_bwd_ms": round(1e3 * tf, 3), "voxels_per_s_fwd_bwd": round(nv / tf, 1),
         "adjoint_plus_apply_ms": round(1e3 * to, 3),
         "effective_GBps_adjoint_plus_apply": round(16 * nv / to / 1e9, 1),
+        "frac_of_hbm_peak_whole_op": round(16 * nv / to / 1e9 / HBM_PEAK_GBPS, 4),
         "adjoint_plus_apply_ms_median_hot": round(1e3 * _time_hot(op_pair, torch, 7), 3),
         "adjoint_plus_apply_ms_median_cold": round(1e3 * to_cold, 3),
         "effective_GBps_cold": round(16 * nv / to_cold / 1e9, 1),
+        "frac_of_hbm_peak_whole_op_cold": round(16 * nv / to_cold / 1e9 / HBM_PEAK_GBPS, 4),
         "plain_pair_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tf, 2)}
     del xv, yv
 
@@ -293,6 +295,7 @@ def other_workloads(args, es, inputs, torch, np):
     out["ragged_200_seed1_cov"] = {
         "voxels": nvr, "launches_per_call": launches, "graph_ms": round(1e3 * tg, 3),
         "voxels_per_s_graph": round(nvr / tg, 1), "effective_GBps_graph": round(8 * nvr / tg / 1e9, 1),
+        "frac_of_hbm_peak_whole_op": round(8 * nvr / tg / 1e9 / HBM_PEAK_GBPS, 4),
         "eager_plan_ms": round(1e3 * te, 3),
         "untuned": {"graph_ms": round(1e3 * tg0, 3), "eager_ms": round(1e3 * te0, 3), "launches_per_call": launches0},
         "tuned_coarse_limit": tcfg[0], "autotune_s": round(t_tune, 2),
@@ -359,6 +362,7 @@ def other_workloads(args, es, inputs, torch, np):
         "fwd_bwd_ms": round(1e3 * tf, 3), "voxels_per_s_fwd_bwd": round(ns / tf, 1),
         "two_sampler_calls_ms": round(1e3 * to, 3),
         "effective_GBps_two_calls": round(16 * ns / to / 1e9, 1),
+        "frac_of_hbm_peak_whole_op": round(16 * ns / to / 1e9 / HBM_PEAK_GBPS, 4),
         "plain_fwd_bwd_ms": round(1e3 * tp, 3), "speedup_vs_plain": round(tp / tf, 2)}
     return out
 
@@ -675,6 +679,7 @@ def main():
         pending["norm"] = es.hs_norm_sq(x, 2, ORDER, LEVELS, S, workspace=nws)[i_s].item()
         result["hs_norm_sq"] = {"ms": round(1e3 * tn, 4), "voxels_per_s": round(voxels / tn, 1),
                                 "effective_GBps": round(4.0 * voxels / tn / 1e9, 1),
+                                "frac_of_hbm_peak_whole_op": round(4.0 * voxels / tn / 1e9 / HBM_PEAK_GBPS, 4),
                                 "unfused_ms": round(1e3 * tu, 4), "rel_err_vs_fp64_oracle_image5": None}
         # Tikhonov reconstruction with the H^s prior: mask Bernoulli(0.3), PCG to 1e-5
         print("[bench] Tikhonov PCG", file=sys.stderr, flush=True)
@@ -705,6 +710,8 @@ def main():
         pending["fft"] = es.fft_cov_apply(x, 2, S, out=y, workspace=fws)[i_s].double().cpu().numpy()
         result["fft_cov_apply"] = {
             "ms": round(1e3 * tf, 4), "ms_in_place": round(1e3 * tfi, 4), "voxels_per_s": round(voxels / tf, 1),
+            "effective_GBps": round(8.0 * voxels / tf / 1e9, 1),
+            "frac_of_hbm_peak_whole_op": round(8.0 * voxels / tf / 1e9 / HBM_PEAK_GBPS, 4),
             "wavelet_cov_ms": round(1e3 * elapsed / args.steps, 4),
             "wavelet_speedup": round(tf / (elapsed / args.steps), 2),
             "spectral_pass_bytes": 2 * 8 * IMAGES * SIDE * (SIDE // 2 + 1),
