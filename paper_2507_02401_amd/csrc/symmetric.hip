@@ -63,6 +63,8 @@ struct SymTask {
   int64_t bs_in, bs_same, bs_out;  // per-instance strides in floats (contiguous instances)
   int32_t ni[3];                   // padded dims of `in` (1-D: (1,1,n), 2-D: (1,n0,n1))
   int32_t no[3];                   // padded dims of `out` (and `same`)
+  int32_t si[2];                   // strides (floats) of axes 0 and 1 of `in`
+  int32_t so[2];                   // strides of axes 0 and 1 of `out` and `same`
   int32_t nt[3];                   // tiles per axis
   int32_t tiles_per_inst;
   float alpha, beta;
@@ -106,17 +108,18 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
   // from base2, through a table of reflected columns only where it reaches past an end
   for (int r = threadIdx.x; r < NROW; r += NT) {
     const int i1 = r % I1, i0 = r / I1;
-    s_row[r] = (D >= 3 ? sym_ix(2 * o0 - (L - 2) + i0, n0) * (n1 * n2) : 0) +
-               (D >= 2 ? sym_ix(2 * o1 - (L - 2) + i1, n1) * n2 : 0);
+    s_row[r] = (D >= 3 ? sym_ix(2 * o0 - (L - 2) + i0, n0) * t.si[0] : 0) +
+               (D >= 2 ? sym_ix(2 * o1 - (L - 2) + i1, n1) * t.si[1] : 0);
   }
   const int base2 = 2 * o2 - (L - 2), a2 = base2 - SH;
-  const bool vec = (n2 & 3) == 0 && a2 >= 0 && a2 + 4 * NVL <= n2;  // the same for the whole work-group
+  // rows start at multiples of 4 floats (and so do instances): 16-byte loads inside the row
+  const bool vec = ((t.si[0] | t.si[1] | t.bs_in) & 3) == 0 && a2 >= 0 && a2 + 4 * NVL <= n2;
   const bool inner = base2 >= 0 && base2 + I2 <= n2;
   if (!inner)
     for (int i = threadIdx.x; i < I2; i += NT) s_x2[i] = sym_ix(base2 + i, n2);
   __syncthreads();
   if (vec) {
-    // 16-byte loads from the aligned start a2 (row offsets are multiples of n2), all issued before
+    // 16-byte loads from the aligned start a2 (row offsets are multiples of 4), all issued before
     // the first LDS store; group v of a row lands at LDS positions 4v - SH .. 4v - SH + 3
     float4 v[ITL];
 #pragma unroll
@@ -170,7 +173,7 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
         },
         [&](int c, int k, float lo, float) {
           const int g1 = o1 + k, g2 = o2 + c;
-          if (g1 < m1 && g2 < m2) gst(dst + g1 * m2 + g2, lo);
+          if (g1 < m1 && g2 < m2) gst(dst + g1 * t.so[1] + g2, lo);
         });
   } else {
     analysis_pass<L, P1, false, true, NT>(
@@ -194,7 +197,7 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
         [&](int l, int k, float lo, float) {
           const int c = l % T2, k1 = l / T2;
           const int g0 = o0 + k, g1 = o1 + k1, g2 = o2 + c;
-          if (g0 < m0 && g1 < m1 && g2 < m2) gst(dst + (g0 * m1 + g1) * m2 + g2, lo);
+          if (g0 < m0 && g1 < m1 && g2 < m2) gst(dst + g0 * t.so[0] + g1 * t.so[1] + g2, lo);
         });
   }
 }
@@ -236,21 +239,22 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
   // four adjacent columns of one output row pair (16-byte LDS reads, loads and stores), and the
   // lane's `same` values are loaded first so that their latency overlaps the staging of z
   constexpr int C4 = U2 / 4, NT2 = C4 * (U1 / 2);
-  const bool fast = D == 2 && (m2 & 3) == 0 && o2 + U2 <= m2;
+  const int so0 = t.so[0], so1 = t.so[1];
+  const bool fast = D == 2 && ((so1 | t.bs_out | t.bs_same) & 3) == 0 && o2 + U2 <= m2;
   float4 xs0 = make_float4(0.f, 0.f, 0.f, 0.f), xs1 = xs0;
   if constexpr (D == 2) {
     static_assert(NT2 <= NT, "one task per lane");
     if (fast && threadIdx.x < NT2) {
       const int c4 = threadIdx.x % C4, ch = threadIdx.x / C4;
       const int g1 = o1 + 2 * ch, g2 = o2 + 4 * c4;
-      if (g1 < m1) xs0 = gld4(same + g1 * m2 + g2);
-      if (g1 + 1 < m1) xs1 = gld4(same + (g1 + 1) * m2 + g2);
+      if (g1 < m1) xs0 = gld4(same + g1 * so1 + g2);
+      if (g1 + 1 < m1) xs1 = gld4(same + (g1 + 1) * so1 + g2);
     }
   }
 
   for (int i = threadIdx.x; i < J2; i += NT) s_x2[i] = r2 + i < l2 ? r2 + i : -1;
-  for (int i = threadIdx.x; i < J1; i += NT) s_x1[i] = D >= 2 ? (r1 + i < l1 ? (r1 + i) * l2 : -1) : 0;
-  for (int i = threadIdx.x; i < J0; i += NT) s_x0[i] = D >= 3 ? (r0 + i < l0 ? (r0 + i) * (l1 * l2) : -1) : 0;
+  for (int i = threadIdx.x; i < J1; i += NT) s_x1[i] = D >= 2 ? (r1 + i < l1 ? (r1 + i) * t.si[1] : -1) : 0;
+  for (int i = threadIdx.x; i < J0; i += NT) s_x0[i] = D >= 3 ? (r0 + i < l0 ? (r0 + i) * t.si[0] : -1) : 0;
   __syncthreads();
   gather_to_lds<NT, 4>(
       NZ,
@@ -300,10 +304,10 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
         }
         const int g1 = o1 + 2 * ch, g2 = o2 + 4 * c4;
         if (g1 < m1)
-          gst4(out + g1 * m2 + g2, make_float4(fmaf(alpha, xs0.x, beta * e0.x), fmaf(alpha, xs0.y, beta * e0.y),
+          gst4(out + g1 * so1 + g2, make_float4(fmaf(alpha, xs0.x, beta * e0.x), fmaf(alpha, xs0.y, beta * e0.y),
                                                fmaf(alpha, xs0.z, beta * e0.z), fmaf(alpha, xs0.w, beta * e0.w)));
         if (g1 + 1 < m1)
-          gst4(out + (g1 + 1) * m2 + g2, make_float4(fmaf(alpha, xs1.x, beta * e1.x), fmaf(alpha, xs1.y, beta * e1.y),
+          gst4(out + (g1 + 1) * so1 + g2, make_float4(fmaf(alpha, xs1.x, beta * e1.x), fmaf(alpha, xs1.y, beta * e1.y),
                                                      fmaf(alpha, xs1.z, beta * e1.z), fmaf(alpha, xs1.w, beta * e1.w)));
       }
       return;
@@ -318,11 +322,11 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
           const int g1 = o1 + p, g2 = o2 + c;
           if (g2 < m2) {
             if (g1 < m1) {
-              const int o = g1 * m2 + g2;
+              const int o = g1 * so1 + g2;
               gst(out + o, fmaf(alpha, gld(same + o), beta * e0));
             }
             if (g1 + 1 < m1) {
-              const int o = (g1 + 1) * m2 + g2;
+              const int o = (g1 + 1) * so1 + g2;
               gst(out + o, fmaf(alpha, gld(same + o), beta * e1));
             }
           }
@@ -355,11 +359,11 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
           if (g1 < m1 && g2 < m2) {
             const int g0 = o0 + p;
             if (g0 < m0) {
-              const int o = (g0 * m1 + g1) * m2 + g2;
+              const int o = g0 * so0 + g1 * so1 + g2;
               gst(out + o, fmaf(alpha, gld(same + o), beta * e0));
             }
             if (g0 + 1 < m0) {
-              const int o = ((g0 + 1) * m1 + g1) * m2 + g2;
+              const int o = (g0 + 1) * so0 + g1 * so1 + g2;
               gst(out + o, fmaf(alpha, gld(same + o), beta * e1));
             }
           }
@@ -437,6 +441,11 @@ struct SymGeo {
   double s;
   int dims[kSymMaxLevels + 1][3];  // padded dims of a_0 (= x) .. a_m
   int64_t size(int i) const { return (int64_t)dims[i][0] * dims[i][1] * dims[i][2]; }
+  // Row pitch of level i: the caller's arrays (level 0, and y) are contiguous; the level arrays in
+  // the workspace start every row at a multiple of 4 floats, so that interior tiles of every level
+  // take the 16-byte paths.
+  int pitch(int i) const { return i == 0 ? dims[0][2] : (dims[i][2] + 3) & ~3; }
+  int64_t stored(int i) const { return (int64_t)dims[i][0] * dims[i][1] * pitch(i); }
 };
 
 es_status sym_einval(const char* fmt, long long a = 0, long long b = 0) {
@@ -469,7 +478,8 @@ es_status sym_geo(int ndim, const int64_t* shape, int order, int levels, double 
       g->dims[i][a] = (int)v;
       prod *= v;
     }
-    if (prod > 0x7fffffffll) return sym_einval("level %lld holds more than 2^31-1 elements per instance", i);
+    if (prod > 0x7fffffffll || g->stored(i) > 0x7fffffffll)
+      return sym_einval("level %lld holds more than 2^31-1 elements per instance", i);
   }
   return ES_OK;
 }
@@ -479,7 +489,7 @@ int64_t align64f(int64_t v) { return (v + 63) & ~(int64_t)63; }
 // Floats of workspace: a_1 .. a_{m-1} of every instance, each level 256-byte aligned.
 int64_t sym_ws_floats(const SymGeo& g, int64_t batch) {
   int64_t tot = 0;
-  for (int i = 1; i < g.m; ++i) tot += align64f(batch * g.size(i));
+  for (int i = 1; i < g.m; ++i) tot += align64f(batch * g.stored(i));
   return tot;
 }
 
@@ -520,7 +530,7 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
   int64_t off = 0;
   for (int i = 1; i < g.m; ++i) {
     lev[i] = ws + off;
-    off += align64f(batch * g.size(i));
+    off += align64f(batch * g.stored(i));
   }
   // weights: w[i] of detail level i (1..m), w[m] = 1 = approximation weight
   std::vector<double> w(g.m + 1, 1.0);
@@ -531,12 +541,16 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
     l.t.in = lev[i - 1];
     l.t.out = lev[i];
     l.t.same = nullptr;
-    l.t.bs_in = g.size(i - 1);
-    l.t.bs_out = g.size(i);
+    l.t.bs_in = g.stored(i - 1);
+    l.t.bs_out = g.stored(i);
     for (int a = 0; a < 3; ++a) {
       l.t.ni[a] = g.dims[i - 1][a];
       l.t.no[a] = g.dims[i][a];
     }
+    l.t.si[1] = g.pitch(i - 1);
+    l.t.si[0] = g.dims[i - 1][1] * g.pitch(i - 1);
+    l.t.so[1] = g.pitch(i);
+    l.t.so[0] = g.dims[i][1] * g.pitch(i);
     l.grid = sym_tiling(l.t, tl.t, batch);
     out->push_back(l);
   }
@@ -547,15 +561,19 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
     l.t.in = lev[j];
     l.t.same = lev[j - 1];
     l.t.out = j == 1 ? y : lev[j - 1];
-    l.t.bs_in = g.size(j);
-    l.t.bs_same = g.size(j - 1);
-    l.t.bs_out = g.size(j - 1);
+    l.t.bs_in = g.stored(j);
+    l.t.bs_same = g.stored(j - 1);
+    l.t.bs_out = g.stored(j - 1);  // y has the layout of x
     l.t.alpha = (float)(j == 1 ? w[1] : w[j] - w[j - 1]);
     l.t.beta = (float)(j == g.m - 1 ? w[g.m] - w[g.m - 1] : 1.0);
     for (int a = 0; a < 3; ++a) {
       l.t.ni[a] = g.dims[j][a];
       l.t.no[a] = g.dims[j - 1][a];
     }
+    l.t.si[1] = g.pitch(j);
+    l.t.si[0] = g.dims[j][1] * g.pitch(j);
+    l.t.so[1] = g.pitch(j - 1);
+    l.t.so[0] = g.dims[j - 1][1] * g.pitch(j - 1);
     l.grid = sym_tiling(l.t, tl.u, batch);
     out->push_back(l);
   }

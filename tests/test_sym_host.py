@@ -37,11 +37,15 @@ def _ws(lib, shape, batch, order, levels):
     ((1024, 1024), 64, 8, 7), ((37, 53), 3, 2, 4), ((9, 10, 11), 2, 4, 3), ((5,), 7, 8, 6), ((64,), 1, 1, 1),
     ((64,), 1, 3, 0)])
 def test_workspace_is_the_level_arrays(lib, shape, batch, order, levels):
-    """a_1 .. a_{m-1} of every instance, each level rounded up to 64 floats."""
+    """a_1 .. a_{m-1} of every instance, rows padded to a multiple of 4 floats, each level rounded
+    up to 64 floats."""
     dims = [list(shape)]
     for _ in range(levels):
         dims.append([symdwt.sym_length(v, 2 * order) for v in dims[-1]])
-    tot = sum((batch * int(np.prod(dims[i])) + 63) // 64 * 64 for i in range(1, levels))
+
+    def stored(d):
+        return int(np.prod(d[:-1])) * ((d[-1] + 3) // 4 * 4)
+    tot = sum((batch * stored(dims[i]) + 63) // 64 * 64 for i in range(1, levels))
     assert _ws(lib, shape, batch, order, levels) == 4 * tot
 
 
