@@ -174,3 +174,97 @@ def sym_cov_apply(x, order, levels, s, tau=2.0):
     w = level_weights(levels, s, tau)
     scaled = [{k: w[i] * v for k, v in lev.items()} for i, lev in enumerate(details)]
     return sym_idwt(approx, scaled, h, x.shape)
+
+
+# ---- transpose of the operator (the backward of a loss through sym_cov_apply) -------------------
+#
+# (W^{-1} D W)^T = W^T D W^{-T}.  The adjoint of each 1-D step is written out from its definition:
+# the analysis gathers x_ext[2k + t - (L - 2)], so its adjoint scatter-adds h[t] a[k] + g[t] d[k]
+# into x[sym_index(2k + t - (L - 2))]; the synthesis reads a[k] with tap h[i + L - 2 - 2k], so its
+# adjoint is a[k] = sum_i h[i + L - 2 - 2k] x[i] over 0 <= i < n, i.e. the analysis sum with the
+# signal extended by zeros instead of by reflection.
+
+def sym_analysis_axis_adjoint(a, d, h, axis, n):
+    """Adjoint of `sym_analysis_axis` along `axis` (output length n there)."""
+    a = np.asarray(a, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    g = quadrature_highpass(h)
+    L = h.size
+    am = np.moveaxis(a, axis, 0)
+    dm = np.moveaxis(d, axis, 0)
+    k = np.arange(am.shape[0])
+    x = np.zeros((n,) + am.shape[1:])
+    for t in range(L):
+        np.add.at(x, sym_index(2 * k + t - (L - 2), n), h[t] * am + g[t] * dm)
+    return np.moveaxis(x, 0, axis)
+
+
+def sym_synthesis_axis_adjoint(x, h, axis, l):
+    """Adjoint of `sym_synthesis_axis` along `axis`: the two bands, each of length l there."""
+    x = np.asarray(x, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    g = quadrature_highpass(h)
+    L = h.size
+    xm = np.moveaxis(x, axis, 0)
+    n = xm.shape[0]
+    a = np.zeros((l,) + xm.shape[1:])
+    d = np.zeros_like(a)
+    for k in range(l):
+        for t in range(L):
+            i = 2 * k + t - (L - 2)
+            if 0 <= i < n:
+                a[k] += h[t] * xm[i]
+                d[k] += g[t] * xm[i]
+    return np.moveaxis(a, 0, axis), np.moveaxis(d, 0, axis)
+
+
+def _unbands_adjoint(y, h, shapes_band):
+    """Adjoint of `_unbands`: y (a block) -> the 2^d bands, keyed by high-pass pattern."""
+    ndim = np.ndim(y)
+    cur = {(): np.asarray(y, dtype=np.float64)}
+    for ax in range(ndim):  # _unbands runs the axes in reverse order: its adjoint forward
+        nxt = {}
+        for key, arr in cur.items():
+            a, d = sym_synthesis_axis_adjoint(arr, h, ax, shapes_band[ax])
+            nxt[key + (0,)] = a
+            nxt[key + (1,)] = d
+        cur = nxt
+    return cur
+
+
+def _bands_adjoint(bands, h, shape):
+    """Adjoint of `_bands`: the 2^d bands -> a block of `shape`."""
+    ndim = len(shape)
+    cur = dict(bands)
+    for ax in range(ndim - 1, -1, -1):
+        nxt = {}
+        for key in {k[:ax] for k in cur}:
+            nxt[key] = sym_analysis_axis_adjoint(cur[key + (0,)], cur[key + (1,)], h, ax, shape[ax])
+        cur = nxt
+    return cur[()]
+
+
+def sym_cov_apply_transpose(y, order, levels, s, tau=2.0):
+    """(W^{-1} D W)^T y = W^T D W^{-T} y for the symmetric-extension transform of Sec. 4."""
+    y = np.asarray(y, dtype=np.float64)
+    h = daubechies_lowpass(order)
+    L = h.size
+    shapes = [tuple(int(v) for v in y.shape)]
+    for _ in range(levels):
+        shapes.append(tuple(sym_length(v, L) for v in shapes[-1]))
+    w = level_weights(levels, s, tau)
+    low = (0,) * y.ndim
+    # W^{-T}: the synthesis ran levels m..1 on the way up; its adjoint runs levels 1..m down
+    cur = y
+    details = []
+    for lev in range(1, levels + 1):
+        bands = _unbands_adjoint(cur, h, shapes[lev])
+        details.append({k: w[lev - 1] * v for k, v in bands.items() if k != low})
+        cur = bands[low]
+    # W^T: the analysis ran levels 1..m; its adjoint runs m..1 back up
+    for lev in range(levels, 0, -1):
+        bands = dict(details[lev - 1])
+        bands[low] = cur
+        cur = _bands_adjoint(bands, h, shapes[lev - 1])
+    return cur

@@ -160,3 +160,40 @@ def test_projection_form_equals_definition():
         z = c[i - 1] * a[i] + lowsyn(z, a[i].shape)
     y = w[0] * x + lowsyn(z, x.shape)
     np.testing.assert_allclose(y, symdwt.sym_cov_apply(x, order, levels, s), atol=1e-12)
+
+
+@pytest.mark.parametrize("order", [1, 2, 4, 8])
+@pytest.mark.parametrize("n", [1, 3, 8, 13])
+def test_step_adjoints(order, n):
+    """<A x, (a, d)> = <x, A^T (a, d)> and <S (a, d), x> = <(a, d), S^T x> for one step."""
+    h = oracle.daubechies_lowpass(order)
+    l = symdwt.sym_length(n, h.size)
+    r = _rng("adj", order, n)
+    x, a, d = r.standard_normal((n, 3)), r.standard_normal((l, 3)), r.standard_normal((l, 3))
+    fa, fd = symdwt.sym_analysis_axis(x, h, 0)
+    lhs = np.sum(fa * a) + np.sum(fd * d)
+    rhs = np.sum(x * symdwt.sym_analysis_axis_adjoint(a, d, h, 0, n))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+    s = symdwt.sym_synthesis_axis(a, d, h, 0, n)
+    ta, td = symdwt.sym_synthesis_axis_adjoint(x, h, 0, l)
+    assert abs(np.sum(s * x) - (np.sum(a * ta) + np.sum(d * td))) <= 1e-12 * max(1.0, abs(np.sum(s * x)))
+
+
+@pytest.mark.parametrize("shape", [(5,), (9,), (4, 6), (3, 2, 5)])
+@pytest.mark.parametrize("order", [1, 2, 4])
+@pytest.mark.parametrize("levels", [0, 1, 2, 3])
+def test_transpose_is_the_dense_transpose(shape, order, levels):
+    """sym_cov_apply_transpose against the transpose of the operator's dense matrix, built column by
+    column from sym_cov_apply (brute force; the operator is not symmetric)."""
+    N = int(np.prod(shape))
+    cols = []
+    tcols = []
+    for c in range(N):
+        e = np.zeros(N)
+        e[c] = 1.0
+        cols.append(symdwt.sym_cov_apply(e.reshape(shape), order, levels, 1.5).ravel())
+        tcols.append(symdwt.sym_cov_apply_transpose(e.reshape(shape), order, levels, 1.5).ravel())
+    T, TT = np.array(cols).T, np.array(tcols).T
+    np.testing.assert_allclose(TT, T.T, rtol=0, atol=1e-12)
+    if levels >= 2 and order > 1 and max(shape) > 2:
+        assert np.abs(T - T.T).max() > 1e-6  # not symmetric: the transpose is a different operator
