@@ -723,6 +723,10 @@ def main():
         sws = torch.empty(max(1, lib.es_sym_workspace_bytes(2, shp, IMAGES, ORDER, LEVELS)), dtype=torch.uint8,
                           device=dev)
         tsym = _time(lambda: es.sym_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=sws), torch, reps)
+        tws = torch.empty(max(1, lib.es_sym_transpose_workspace_bytes(2, shp, IMAGES, ORDER, LEVELS)),
+                          dtype=torch.uint8, device=dev)
+        tsymT = _time(lambda: es.sym_cov_apply_transpose(x, 2, ORDER, LEVELS, S, out=y, workspace=tws), torch, reps)
+        del tws
         pending["sym"] = es.sym_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=sws)[i_s].double().cpu().numpy()
         lens = [SIDE] + es.sym_band_lengths(SIDE, ORDER, LEVELS)
         area = [IMAGES * v * v for v in lens]
@@ -736,6 +740,7 @@ def main():
             "frac_of_hbm_peak_whole_op": round(8.0 * voxels / tsym / 1e9 / HBM_PEAK_GBPS, 4),
             "schedule_bytes": sched, "schedule_GBps": round(sched / tsym / 1e9, 1),
             "band_lengths": lens[1:], "launches": 2 * (LEVELS - 1),
+            "transpose_ms": round(1e3 * tsymT, 4), "transpose_launches": 3 * (LEVELS - 1),
             "periodic_cov_ms": round(1e3 * elapsed / args.steps, 4),
             "rel_l2_vs_fp64_oracle_image5": None}
         del sws

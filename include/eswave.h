@@ -219,6 +219,15 @@ es_status es_sym_cov_apply(int ndim, const int64_t* shape, int64_t batch, int or
                            const float* x, float* y, void* ws, size_t ws_bytes, void* stream);
 /* Workspace bytes of es_sym_cov_apply (0 for invalid arguments or batch <= 0). */
 size_t es_sym_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
+/* x_b = (W^{-1} D_{2s} W)^T y_b = W^T D_{2s} W^{-T} y_b: the transpose of es_sym_cov_apply (the
+ * operator is not symmetric), for gradients of losses through it.  Evaluated as
+ * w_1 y + sum_i c_i (A^T)^i (S_a^T)^i y with S_a^T the analysis sum over the signal extended by
+ * zeros and A^T the synthesis onto the extension positions -(L-2) .. 2l-1 folded back onto the
+ * samples they reflect to.  Arguments as for es_sym_cov_apply (y in, x out); the workspace is
+ * es_sym_transpose_workspace_bytes(...) bytes (the level arrays and one extended level). */
+es_status es_sym_cov_apply_transpose(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                                     const float* y, float* x, void* ws, size_t ws_bytes, void* stream);
+size_t es_sym_transpose_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
 /* Band lengths l_1 .. l_levels of one axis of length n (host array of `levels` entries). */
 es_status es_sym_band_lengths(int64_t n, int order, int levels, int64_t* lengths);
 

@@ -9,10 +9,10 @@ non-periodic (symmetric-extension) transform of Sec. 4 with its book-keeping ban
 from ._lib import (OP_ADJOINT, OP_APPLY, OP_COV, OP_SAMPLE, EswaveError, load)
 from .ops import (RaggedPlan, apply_op, autotune, es_adjoint, es_apply, fft_cov_apply, hs_norm_sq, matern_cov_apply,
                   matern_depth, matern_parameters, matern_sample, matern_to_s, plain_op, sym_band_lengths,
-                  sym_cov_apply, workspace_bytes)
+                  sym_cov_apply, sym_cov_apply_transpose, workspace_bytes)
 from . import autograd
 
 __all__ = ["autotune", "OP_ADJOINT", "OP_APPLY", "OP_COV", "OP_SAMPLE", "EswaveError", "load", "RaggedPlan", "apply_op",
            "es_adjoint", "es_apply", "fft_cov_apply", "hs_norm_sq", "matern_cov_apply", "matern_depth", "matern_parameters",
            "matern_sample", "matern_to_s",
-           "plain_op", "sym_band_lengths", "sym_cov_apply", "workspace_bytes", "autograd"]
+           "plain_op", "sym_band_lengths", "sym_cov_apply", "sym_cov_apply_transpose", "workspace_bytes", "autograd"]

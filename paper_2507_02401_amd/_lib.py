@@ -47,6 +47,8 @@ SIGNATURES = [
     ("es_fft_release_plans", ctypes.c_int, []),
     ("es_sym_cov_apply", ctypes.c_int, _OP_ARGS),
     ("es_sym_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    ("es_sym_cov_apply_transpose", ctypes.c_int, _OP_ARGS),
+    ("es_sym_transpose_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
     ("es_sym_band_lengths", ctypes.c_int, [ctypes.c_int64, ctypes.c_int, ctypes.c_int, _i64p]),
     ("es_plan_create", ctypes.c_int, [ctypes.POINTER(EsDesc), ctypes.c_int32, ctypes.c_int, _fp, ctypes.POINTER(ctypes.c_void_p)]),
     ("es_plan_execute", ctypes.c_int, [_fp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), _fp, ctypes.c_size_t, _fp]),

@@ -1,8 +1,10 @@
-"""torch.autograd.Function forms of the four operators, the squared H^s norm and the Fourier form.
+"""torch.autograd.Function forms of the four operators, the squared H^s norm, the Fourier form and the
+non-periodic operator.
 
 Every operator is linear, so the backward pass is the adjoint applied to the incoming
 gradient: es_adjoint^T = es_apply (synthesis instead of analysis, same level weights),
-es_apply^T = es_adjoint, and the covariance and the sampler are symmetric.  Only the scalar
+es_apply^T = es_adjoint, and the covariance and the sampler are symmetric; the non-periodic
+operator W^{-1} D W is not, and its backward is its transpose.  Only the scalar
 arguments are saved.
 """
 import torch
@@ -108,3 +110,37 @@ def matern_cov(x, ndim, order, levels, s):
 
 def matern_sample(xi, ndim, order, levels, s):
     return MaternSampleFn.apply(xi, ndim, order, levels, s)
+
+
+class SymCovFn(torch.autograd.Function):
+    """W^{-1} D_2s W with the non-periodic transform; backward: its transpose W^T D_2s W^{-T}."""
+
+    @staticmethod
+    def forward(ctx, x, ndim, order, levels, s):
+        ctx.args = (ndim, order, levels, s)
+        return ops.sym_cov_apply(x, ndim, order, levels, s)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ops.sym_cov_apply_transpose(g.contiguous(), *ctx.args), None, None, None, None
+
+
+class SymCovTFn(torch.autograd.Function):
+    """The transpose of SymCovFn; backward: the operator itself."""
+
+    @staticmethod
+    def forward(ctx, y, ndim, order, levels, s):
+        ctx.args = (ndim, order, levels, s)
+        return ops.sym_cov_apply_transpose(y, ndim, order, levels, s)
+
+    @staticmethod
+    def backward(ctx, g):
+        return ops.sym_cov_apply(g.contiguous(), *ctx.args), None, None, None, None
+
+
+def sym_cov_apply(x, ndim, order, levels, s):
+    return SymCovFn.apply(x, ndim, order, levels, s)
+
+
+def sym_cov_apply_transpose(y, ndim, order, levels, s):
+    return SymCovTFn.apply(y, ndim, order, levels, s)

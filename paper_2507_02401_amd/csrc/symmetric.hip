@@ -67,14 +67,31 @@ struct SymTask {
   int32_t so[2];                   // strides of axes 0 and 1 of `out` and `same`
   int32_t nt[3];                   // tiles per axis
   int32_t tiles_per_inst;
-  float alpha, beta;
+  int32_t zshift;                  // synthesis: the z window starts zshift samples before o/2
+  float alpha, beta;               // synthesis: same == nullptr drops the alpha term
 };
+
+// Sign-correct integer division rounding down / up (b > 0).
+DEVI int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+DEVI int ceil_div(int a, int b) { return -floor_div(-a, b); }
+
+// Calls f(p) for every position p in [lo, hi] of the half-point symmetric extension of a length-n
+// axis that reflects to sample j: p = j + 2n t and p = -1 - j + 2n t.
+template <class F>
+DEVI void for_images(int j, int n, int lo, int hi, F f) {
+  const int P = 2 * n;
+  for (int t = ceil_div(lo - j, P), te = floor_div(hi - j, P); t <= te; ++t) f(j + P * t);
+  const int q = -1 - j;
+  for (int t = ceil_div(lo - q, P), te = floor_div(hi - q, P); t <= te; ++t) f(q + P * t);
+}
 
 // Output tile (T0, T1, T2) of one analysis level; input window I_k = 2 T_k + L - 2 starting at
 // 2 o_k - (L - 2) (o_k the tile's first output).  The staged rows are filtered along axis 2 with
 // the periodic kernels' in-place row pass (16-byte LDS windows, results written back over the
 // staging buffer as rows of T2), then along axes 1 and 0.
-template <int D, int L, int T0, int T1, int T2, int NT>
+// ZX: the signal is extended by zeros instead of by reflection -- the transpose S_a^T of the
+// synthesis's low-pass half (used by the transposed operator).
+template <int D, int L, int T0, int T1, int T2, int NT, bool ZX>
 __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
   constexpr int I0 = D >= 3 ? 2 * T0 + L - 2 : 1;
   constexpr int I1 = D >= 2 ? 2 * T1 + L - 2 : 1;
@@ -108,15 +125,23 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
   // from base2, through a table of reflected columns only where it reaches past an end
   for (int r = threadIdx.x; r < NROW; r += NT) {
     const int i1 = r % I1, i0 = r / I1;
-    s_row[r] = (D >= 3 ? sym_ix(2 * o0 - (L - 2) + i0, n0) * t.si[0] : 0) +
-               (D >= 2 ? sym_ix(2 * o1 - (L - 2) + i1, n1) * t.si[1] : 0);
+    const int j0 = 2 * o0 - (L - 2) + i0, j1 = 2 * o1 - (L - 2) + i1;
+    if constexpr (ZX) {  // -1: a row outside the signal (zeros)
+      const bool ok = (D < 3 || (j0 >= 0 && j0 < n0)) && (D < 2 || (j1 >= 0 && j1 < n1));
+      s_row[r] = ok ? (D >= 3 ? j0 * t.si[0] : 0) + (D >= 2 ? j1 * t.si[1] : 0) : -1;
+    } else {
+      s_row[r] = (D >= 3 ? sym_ix(j0, n0) * t.si[0] : 0) + (D >= 2 ? sym_ix(j1, n1) * t.si[1] : 0);
+    }
   }
   const int base2 = 2 * o2 - (L - 2), a2 = base2 - SH;
   // rows start at multiples of 4 floats (and so do instances): 16-byte loads inside the row
   const bool vec = ((t.si[0] | t.si[1] | t.bs_in) & 3) == 0 && a2 >= 0 && a2 + 4 * NVL <= n2;
   const bool inner = base2 >= 0 && base2 + I2 <= n2;
   if (!inner)
-    for (int i = threadIdx.x; i < I2; i += NT) s_x2[i] = sym_ix(base2 + i, n2);
+    for (int i = threadIdx.x; i < I2; i += NT) {
+      const int j = base2 + i;
+      s_x2[i] = ZX ? (j >= 0 && j < n2 ? j : -1) : sym_ix(j, n2);
+    }
   __syncthreads();
   if (vec) {
     // 16-byte loads from the aligned start a2 (row offsets are multiples of 4), all issued before
@@ -126,7 +151,7 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
     for (int it = 0; it < ITL; ++it) {
       const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
       const int r = q / NVL, g = q - r * NVL;
-      v[it] = gld4(src + s_row[r] + a2 + 4 * g);
+      v[it] = !ZX || s_row[r] >= 0 ? gld4(src + s_row[r] + a2 + 4 * g) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int it = 0; it < ITL; ++it) {
@@ -147,7 +172,8 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
         NROW * I2,
         [&](int e) {
           const int r = e / I2, i2 = e - r * I2;
-          return gld(src + s_row[r] + (inner ? base2 + i2 : s_x2[i2]));
+          const int c = inner ? base2 + i2 : s_x2[i2];
+          return !ZX || (s_row[r] >= 0 && c >= 0) ? gld(src + s_row[r] + c) : 0.f;
         },
         [&](int e, float x) {
           const int r = e / I2;
@@ -228,12 +254,16 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
   rem /= t.nt[2];
   const int c1 = rem % t.nt[1], c0 = rem / t.nt[1];
   const float* z = t.in + inst * t.bs_in;
-  const float* same = t.same + inst * t.bs_same;  // may equal out: each output reads only its own slot
+  // may equal out: each output reads only its own slot; null (the extended synthesis of the
+  // transposed operator): no alpha term
+  const bool has_same = t.same != nullptr;
+  const float* same = has_same ? t.same + inst * t.bs_same : nullptr;
   float* out = t.out + inst * t.bs_out;
   const int l0 = t.ni[0], l1 = t.ni[1], l2 = t.ni[2];
   const int m0 = t.no[0], m1 = t.no[1], m2 = t.no[2];
   const int o0 = U0 * c0, o1 = U1 * c1, o2 = U2 * c2;  // first output of the tile on each axis
-  const int r0 = o0 / 2, r1 = o1 / 2, r2 = o2 / 2;     // first z sample of the window
+  const int zs = t.zshift;
+  const int r0 = o0 / 2 - zs, r1 = o1 / 2 - zs, r2 = o2 / 2 - zs;  // first z sample of the window
 
   // 2-D tiles whose columns lie inside a row length divisible by 4: the last pass gives each lane
   // four adjacent columns of one output row pair (16-byte LDS reads, loads and stores), and the
@@ -244,7 +274,7 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
   float4 xs0 = make_float4(0.f, 0.f, 0.f, 0.f), xs1 = xs0;
   if constexpr (D == 2) {
     static_assert(NT2 <= NT, "one task per lane");
-    if (fast && threadIdx.x < NT2) {
+    if (fast && has_same && threadIdx.x < NT2) {
       const int c4 = threadIdx.x % C4, ch = threadIdx.x / C4;
       const int g1 = o1 + 2 * ch, g2 = o2 + 4 * c4;
       if (g1 < m1) xs0 = gld4(same + g1 * so1 + g2);
@@ -252,9 +282,10 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
     }
   }
 
-  for (int i = threadIdx.x; i < J2; i += NT) s_x2[i] = r2 + i < l2 ? r2 + i : -1;
-  for (int i = threadIdx.x; i < J1; i += NT) s_x1[i] = D >= 2 ? (r1 + i < l1 ? (r1 + i) * t.si[1] : -1) : 0;
-  for (int i = threadIdx.x; i < J0; i += NT) s_x0[i] = D >= 3 ? (r0 + i < l0 ? (r0 + i) * t.si[0] : -1) : 0;
+  auto inz = [](int k, int l) { return k >= 0 && k < l; };
+  for (int i = threadIdx.x; i < J2; i += NT) s_x2[i] = inz(r2 + i, l2) ? r2 + i : -1;
+  for (int i = threadIdx.x; i < J1; i += NT) s_x1[i] = D >= 2 ? (inz(r1 + i, l1) ? (r1 + i) * t.si[1] : -1) : 0;
+  for (int i = threadIdx.x; i < J0; i += NT) s_x0[i] = D >= 3 ? (inz(r0 + i, l0) ? (r0 + i) * t.si[0] : -1) : 0;
   __syncthreads();
   gather_to_lds<NT, 4>(
       NZ,
@@ -283,7 +314,7 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
   if constexpr (D == 1) {
     for (int p = threadIdx.x; p < U2; p += NT) {
       const int g2 = o2 + p;
-      if (g2 < m2) gst(out + g2, fmaf(alpha, gld(same + g2), beta * s_a[p]));
+      if (g2 < m2) gst(out + g2, fmaf(alpha, has_same ? gld(same + g2) : 0.f, beta * s_a[p]));
     }
   } else if constexpr (D == 2) {
     if (fast) {
@@ -323,11 +354,11 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
           if (g2 < m2) {
             if (g1 < m1) {
               const int o = g1 * so1 + g2;
-              gst(out + o, fmaf(alpha, gld(same + o), beta * e0));
+              gst(out + o, fmaf(alpha, has_same ? gld(same + o) : 0.f, beta * e0));
             }
             if (g1 + 1 < m1) {
               const int o = (g1 + 1) * so1 + g2;
-              gst(out + o, fmaf(alpha, gld(same + o), beta * e1));
+              gst(out + o, fmaf(alpha, has_same ? gld(same + o) : 0.f, beta * e1));
             }
           }
         });
@@ -360,11 +391,11 @@ __global__ void __launch_bounds__(NT) k_sym_up(SymTask t, Filter f) {
             const int g0 = o0 + p;
             if (g0 < m0) {
               const int o = g0 * so0 + g1 * so1 + g2;
-              gst(out + o, fmaf(alpha, gld(same + o), beta * e0));
+              gst(out + o, fmaf(alpha, has_same ? gld(same + o) : 0.f, beta * e0));
             }
             if (g0 + 1 < m0) {
               const int o = (g0 + 1) * so0 + g1 * so1 + g2;
-              gst(out + o, fmaf(alpha, gld(same + o), beta * e1));
+              gst(out + o, fmaf(alpha, has_same ? gld(same + o) : 0.f, beta * e1));
             }
           }
         });
@@ -389,45 +420,97 @@ SymTiles sym_tiles(int D, int L) {
   return {{2, 4, 16}, {8, 8, 32}};
 }
 
-template <int D, int L>
+// Fold of the transposed operator's extended synthesis (A^T = fold o zero-padded synthesis onto
+// the extension): out[j] = alpha * same[j] + beta * sum of v over every extension position that
+// reflects to j, per present axis over [-(L - 2), 2 l - 1] (v's index p + (L - 2)).
+struct SymFold {
+  const float* v;
+  const float* same;  // may equal out
+  float* out;
+  int64_t bs_v, bs_out, total;  // per-instance strides; batch * outputs per instance
+  int32_t sv[2], so[2];         // strides of axes 0 and 1 of v and of out / same
+  int32_t no[3];                // output dims (padded)
+  int32_t nl[3];                // coefficient lengths l (padded)
+  int32_t ext;                  // L - 2
+  int32_t present[3];           // 1 for the axes of the grid
+  float alpha, beta;
+};
+
+__global__ void __launch_bounds__(256) k_sym_fold(SymFold F) {
+  const int64_t per = (int64_t)F.no[0] * F.no[1] * F.no[2];
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < F.total; e += (int64_t)gridDim.x * 256) {
+    const int64_t inst = e / per;
+    int r = (int)(e - inst * per);
+    const int j2 = r % F.no[2];
+    r /= F.no[2];
+    const int j1 = r % F.no[1], j0 = r / F.no[1];
+    const float* v = F.v + inst * F.bs_v;
+    auto range = [&](int a, int& lo, int& hi) {
+      lo = F.present[a] ? -F.ext : 0;
+      hi = F.present[a] ? 2 * F.nl[a] - 1 : 0;
+    };
+    int lo0, hi0, lo1, hi1, lo2, hi2;
+    range(0, lo0, hi0);
+    range(1, lo1, hi1);
+    range(2, lo2, hi2);
+    const int e0 = F.present[0] ? F.ext : 0, e1 = F.present[1] ? F.ext : 0, e2 = F.present[2] ? F.ext : 0;
+    float acc = 0.f;
+    for_images(j0, F.no[0], lo0, hi0, [&](int p0) {
+      for_images(j1, F.no[1], lo1, hi1, [&](int p1) {
+        const float* row = v + (p0 + e0) * F.sv[0] + (p1 + e1) * F.sv[1] + e2;
+        for_images(j2, F.no[2], lo2, hi2, [&](int p2) { acc += gld(row + p2); });
+      });
+    });
+    const int64_t o = inst * F.bs_out + (int64_t)j0 * F.so[0] + (int64_t)j1 * F.so[1] + j2;
+    const float sv = F.same ? gld(F.same + o) : 0.f;
+    gst(F.out + o, fmaf(F.alpha, sv, F.beta * acc));
+  }
+}
+
+template <int D, int L, bool ZX>
 hipError_t launch_sym_level(bool up, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
   if constexpr (D == 1) {
     if (up) hipLaunchKernelGGL((k_sym_up<1, L, 1, 1, 512, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
-    else hipLaunchKernelGGL((k_sym_down<1, L, 1, 1, 256, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    else hipLaunchKernelGGL((k_sym_down<1, L, 1, 1, 256, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
   } else if constexpr (D == 2) {
     if (up) hipLaunchKernelGGL((k_sym_up<2, L, 1, 32, 64, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
-    else hipLaunchKernelGGL((k_sym_down<2, L, 1, 16, 64, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    else hipLaunchKernelGGL((k_sym_down<2, L, 1, 16, 64, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
   } else {
     if (up) {
       hipLaunchKernelGGL((k_sym_up<3, L, 8, 8, 32, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     } else if constexpr (L <= 4) {
-      hipLaunchKernelGGL((k_sym_down<3, L, 4, 8, 16, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 8, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     } else if constexpr (L <= 8) {
-      hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     } else {
-      hipLaunchKernelGGL((k_sym_down<3, L, 2, 4, 16, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+      hipLaunchKernelGGL((k_sym_down<3, L, 2, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     }
   }
   return hipGetLastError();
 }
 
 template <int L>
-hipError_t launch_sym_taps(int D, bool up, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
-  if (D == 1) return launch_sym_level<1, L>(up, t, grid, f, s);
-  if (D == 2) return launch_sym_level<2, L>(up, t, grid, f, s);
-  return launch_sym_level<3, L>(up, t, grid, f, s);
+hipError_t launch_sym_taps(int D, bool up, bool zx, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
+  if (zx) {
+    if (D == 1) return launch_sym_level<1, L, true>(up, t, grid, f, s);
+    if (D == 2) return launch_sym_level<2, L, true>(up, t, grid, f, s);
+    return launch_sym_level<3, L, true>(up, t, grid, f, s);
+  }
+  if (D == 1) return launch_sym_level<1, L, false>(up, t, grid, f, s);
+  if (D == 2) return launch_sym_level<2, L, false>(up, t, grid, f, s);
+  return launch_sym_level<3, L, false>(up, t, grid, f, s);
 }
 
-hipError_t launch_sym(int D, int L, bool up, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
+hipError_t launch_sym(int D, int L, bool up, bool zx, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
   switch (L) {
-    case 2: return launch_sym_taps<2>(D, up, t, grid, f, s);
-    case 4: return launch_sym_taps<4>(D, up, t, grid, f, s);
-    case 6: return launch_sym_taps<6>(D, up, t, grid, f, s);
-    case 8: return launch_sym_taps<8>(D, up, t, grid, f, s);
-    case 10: return launch_sym_taps<10>(D, up, t, grid, f, s);
-    case 12: return launch_sym_taps<12>(D, up, t, grid, f, s);
-    case 14: return launch_sym_taps<14>(D, up, t, grid, f, s);
-    default: return launch_sym_taps<16>(D, up, t, grid, f, s);
+    case 2: return launch_sym_taps<2>(D, up, zx, t, grid, f, s);
+    case 4: return launch_sym_taps<4>(D, up, zx, t, grid, f, s);
+    case 6: return launch_sym_taps<6>(D, up, zx, t, grid, f, s);
+    case 8: return launch_sym_taps<8>(D, up, zx, t, grid, f, s);
+    case 10: return launch_sym_taps<10>(D, up, zx, t, grid, f, s);
+    case 12: return launch_sym_taps<12>(D, up, zx, t, grid, f, s);
+    case 14: return launch_sym_taps<14>(D, up, zx, t, grid, f, s);
+    default: return launch_sym_taps<16>(D, up, zx, t, grid, f, s);
   }
 }
 
@@ -486,12 +569,6 @@ es_status sym_geo(int ndim, const int64_t* shape, int order, int levels, double 
 
 int64_t align64f(int64_t v) { return (v + 63) & ~(int64_t)63; }
 
-// Floats of workspace: a_1 .. a_{m-1} of every instance, each level 256-byte aligned.
-int64_t sym_ws_floats(const SymGeo& g, int64_t batch) {
-  int64_t tot = 0;
-  for (int i = 1; i < g.m; ++i) tot += align64f(batch * g.stored(i));
-  return tot;
-}
 
 bool sym_filter(int L, Filter* f) {
   double h[kMaxTaps];
@@ -505,8 +582,10 @@ bool sym_filter(int L, Filter* f) {
 }
 
 struct SymLaunch {
-  bool up;
+  int kind;  // 0 analysis level, 1 synthesis level, 2 fold (transposed operator)
+  bool zx;   // analysis with zero extension (S_a^T)
   SymTask t;
+  SymFold fold;
   int64_t grid;
 };
 
@@ -521,7 +600,34 @@ int64_t sym_tiling(SymTask& t, const int tile[3], int64_t batch) {
   return per * batch;
 }
 
-es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y, float* ws,
+// The transposed operator's extended synthesis of level i: every present axis runs over the
+// extension positions -(L - 2) .. 2 l_i - 1, rows padded to a multiple of 4 floats.
+struct ExtDims {
+  int d[3], pitch;
+  int64_t stored() const { return (int64_t)d[0] * d[1] * pitch; }
+};
+ExtDims ext_dims(const SymGeo& g, int i) {
+  ExtDims e;
+  for (int a = 0; a < 3; ++a) e.d[a] = a < 3 - g.D ? 1 : 2 * g.dims[i][a] + g.L - 2;
+  e.pitch = (e.d[2] + 3) & ~3;
+  return e;
+}
+
+// Floats of workspace: a_1 .. a_{m-1} of every instance (each level 256-byte aligned), and for
+// the transposed operator the extended synthesis of the finest level after them.
+int64_t sym_ws_floats(const SymGeo& g, int64_t batch, bool transpose) {
+  int64_t tot = 0;
+  for (int i = 1; i < g.m; ++i) tot += align64f(batch * g.stored(i));
+  if (transpose && g.m >= 2) tot += align64f(batch * ext_dims(g, 1).stored());
+  return tot;
+}
+
+// Launch sequence.  Forward (x -> y = W^{-1} D W x): a_i = A a_{i-1}, then
+// z_{j-1} = c_{j-1} a_{j-1} + S_a z_j (y = w_1 x + S_a z_1), z over a in place.
+// Transposed (x -> y = (W^{-1} D W)^T x = w_1 x + sum_i c_i (A^T)^i (S_a^T)^i x): b_i = S_a^T b_{i-1}
+// (zero-extended analysis), then u_{j-1} = c_{j-1} b_{j-1} + A^T u_j with A^T = fold o extended
+// synthesis (y = w_1 x + A^T u_1).
+es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y, float* ws, bool transpose,
                        std::vector<SymLaunch>* out) {
   out->clear();
   const SymTiles tl = sym_tiles(g.D, g.L);
@@ -532,12 +638,18 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
     lev[i] = ws + off;
     off += align64f(batch * g.stored(i));
   }
+  float* vext = ws + off;  // transposed operator only
+  auto strides = [&](int i, int32_t st[2]) {
+    st[1] = g.pitch(i);
+    st[0] = g.dims[i][1] * g.pitch(i);
+  };
   // weights: w[i] of detail level i (1..m), w[m] = 1 = approximation weight
   std::vector<double> w(g.m + 1, 1.0);
   for (int i = 1; i <= g.m; ++i) w[i] = std::exp2(-2.0 * g.s * (double)(g.m - i));
   for (int i = 1; i < g.m; ++i) {
     SymLaunch l{};
-    l.up = false;
+    l.kind = 0;
+    l.zx = transpose;
     l.t.in = lev[i - 1];
     l.t.out = lev[i];
     l.t.same = nullptr;
@@ -547,38 +659,136 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
       l.t.ni[a] = g.dims[i - 1][a];
       l.t.no[a] = g.dims[i][a];
     }
-    l.t.si[1] = g.pitch(i - 1);
-    l.t.si[0] = g.dims[i - 1][1] * g.pitch(i - 1);
-    l.t.so[1] = g.pitch(i);
-    l.t.so[0] = g.dims[i][1] * g.pitch(i);
+    strides(i - 1, l.t.si);
+    strides(i, l.t.so);
     l.grid = sym_tiling(l.t, tl.t, batch);
     out->push_back(l);
   }
   for (int j = g.m - 1; j >= 1; --j) {
-    // z_{j-1} = c_{j-1} a_{j-1} + S_a z_j  (y = w_1 x + S_a z_1 when j = 1); z_{m-1} = c_{m-1} a_{m-1}
+    const double alpha = j == 1 ? w[1] : w[j] - w[j - 1];
+    const double beta = j == g.m - 1 ? w[g.m] - w[g.m - 1] : 1.0;
+    float* dst = j == 1 ? y : lev[j - 1];
+    if (!transpose) {
+      // z_{j-1} = c_{j-1} a_{j-1} + S_a z_j  (y = w_1 x + S_a z_1); z_{m-1} = c_{m-1} a_{m-1}
+      SymLaunch l{};
+      l.kind = 1;
+      l.t.in = lev[j];
+      l.t.same = lev[j - 1];
+      l.t.out = dst;
+      l.t.bs_in = g.stored(j);
+      l.t.bs_same = g.stored(j - 1);
+      l.t.bs_out = g.stored(j - 1);  // y has the layout of x
+      l.t.alpha = (float)alpha;
+      l.t.beta = (float)beta;
+      for (int a = 0; a < 3; ++a) {
+        l.t.ni[a] = g.dims[j][a];
+        l.t.no[a] = g.dims[j - 1][a];
+      }
+      strides(j, l.t.si);
+      strides(j - 1, l.t.so);
+      l.grid = sym_tiling(l.t, tl.u, batch);
+      out->push_back(l);
+      continue;
+    }
+    // transposed: v = beta * (zero-padded synthesis of u_j onto the extension), then
+    // u_{j-1} = c_{j-1} b_{j-1} + fold(v)
+    const ExtDims E = ext_dims(g, j);
     SymLaunch l{};
-    l.up = true;
+    l.kind = 1;
     l.t.in = lev[j];
-    l.t.same = lev[j - 1];
-    l.t.out = j == 1 ? y : lev[j - 1];
+    l.t.same = nullptr;
+    l.t.out = vext;
     l.t.bs_in = g.stored(j);
-    l.t.bs_same = g.stored(j - 1);
-    l.t.bs_out = g.stored(j - 1);  // y has the layout of x
-    l.t.alpha = (float)(j == 1 ? w[1] : w[j] - w[j - 1]);
-    l.t.beta = (float)(j == g.m - 1 ? w[g.m] - w[g.m - 1] : 1.0);
+    l.t.bs_out = E.stored();
+    l.t.zshift = g.L / 2 - 1;
+    l.t.alpha = 0.f;
+    l.t.beta = (float)beta;
     for (int a = 0; a < 3; ++a) {
       l.t.ni[a] = g.dims[j][a];
-      l.t.no[a] = g.dims[j - 1][a];
+      l.t.no[a] = E.d[a];
     }
-    l.t.si[1] = g.pitch(j);
-    l.t.si[0] = g.dims[j][1] * g.pitch(j);
-    l.t.so[1] = g.pitch(j - 1);
-    l.t.so[0] = g.dims[j - 1][1] * g.pitch(j - 1);
+    strides(j, l.t.si);
+    l.t.so[1] = E.pitch;
+    l.t.so[0] = E.d[1] * E.pitch;
     l.grid = sym_tiling(l.t, tl.u, batch);
     out->push_back(l);
+    SymLaunch fl{};
+    fl.kind = 2;
+    SymFold& F = fl.fold;
+    F.v = vext;
+    F.same = lev[j - 1];
+    F.out = dst;
+    F.bs_v = E.stored();
+    F.bs_out = g.stored(j - 1);
+    F.total = batch * g.size(j - 1);
+    F.sv[1] = E.pitch;
+    F.sv[0] = E.d[1] * E.pitch;
+    strides(j - 1, F.so);
+    for (int a = 0; a < 3; ++a) {
+      F.no[a] = g.dims[j - 1][a];
+      F.nl[a] = g.dims[j][a];
+      F.present[a] = a >= 3 - g.D;
+    }
+    F.ext = g.L - 2;
+    F.alpha = (float)alpha;
+    F.beta = 1.f;
+    fl.grid = std::min<int64_t>((F.total + 255) / 256, 1 << 20);
+    out->push_back(fl);
   }
   for (const SymLaunch& l : *out)
     if (l.grid > 0x7fffffffll) return sym_einval("a level needs more than 2^31-1 work-groups (%lld)", l.grid);
+  return ES_OK;
+}
+
+es_status sym_run(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s, const float* x,
+                  float* y, void* ws, size_t ws_bytes, void* stream, bool transpose) {
+  SymGeo g;
+  es_status st = sym_geo(ndim, shape, order, levels, s, &g);
+  if (st != ES_OK) return st;
+  if (batch < 0) return sym_einval("batch must be >= 0");
+  if (batch == 0) return ES_OK;
+  const int64_t N = g.size(0);
+  if (N > INT64_MAX / 4 / batch) return sym_einval("batch * size overflows");
+  if (transpose && g.m >= 2 && ext_dims(g, 1).stored() > 0x7fffffffll)
+    return sym_einval("the extended level holds more than 2^31-1 elements per instance");
+  if (!x || !y) return sym_einval("input and output pointers must be non-NULL");
+  if (((uintptr_t)x & 15) || ((uintptr_t)y & 15)) return sym_einval("input and output must be 16-byte aligned");
+  const size_t io = (size_t)(batch * N) * sizeof(float);
+  const char *px = (const char*)x, *py = (const char*)y;
+  if (px < py + io && py < px + io) return sym_einval("input and output overlap");
+  const size_t need = (size_t)sym_ws_floats(g, batch, transpose) * sizeof(float);
+  if (need) {
+    if (!ws) return report_error(ES_EWORKSPACE, "workspace required (es_sym_workspace_bytes), got NULL");
+    if (ws_bytes < need) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "workspace of %zu bytes required, got %zu", need, ws_bytes);
+      return report_error(ES_EWORKSPACE, buf);
+    }
+    if ((uintptr_t)ws & 255) return sym_einval("workspace must be 256-byte aligned");
+    const char* pw = (const char*)ws;
+    if ((pw < px + io && px < pw + need) || (pw < py + io && py < pw + need))
+      return sym_einval("workspace overlaps input or output");
+  }
+  std::vector<SymLaunch> seq;
+  if ((st = sym_schedule(g, batch, x, y, (float*)ws, transpose, &seq)) != ES_OK) return st;
+  Filter f;
+  if (!sym_filter(g.L, &f)) return report_error(ES_EUNSUPPORTED, "filter derivation failed");
+  if ((st = device_check()) != ES_OK) return st;
+  hipStream_t hs = (hipStream_t)stream;
+  hipError_t he;
+  if (g.m <= 1) {  // every weight is 1: the identity
+    if ((he = launch_copy(x, y, batch * N, hs)) != hipSuccess) return report_error(ES_EDEVICE, hipGetErrorString(he));
+    return ES_OK;
+  }
+  for (const SymLaunch& l : seq) {
+    if (l.kind == 2) {
+      hipLaunchKernelGGL(k_sym_fold, dim3((unsigned)l.grid), dim3(256), 0, hs, l.fold);
+      he = hipGetLastError();
+    } else {
+      he = launch_sym(g.D, g.L, l.kind == 1, l.zx, l.t, l.grid, f, hs);
+    }
+    if (he != hipSuccess) return report_error(ES_EDEVICE, hipGetErrorString(he));
+  }
   return ES_OK;
 }
 
@@ -593,7 +803,13 @@ extern "C" {
 size_t es_sym_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels) {
   SymGeo g;
   if (sym_geo(ndim, shape, order, levels, 0.0, &g) != ES_OK || batch <= 0) return 0;
-  return (size_t)sym_ws_floats(g, batch) * sizeof(float);
+  return (size_t)sym_ws_floats(g, batch, false) * sizeof(float);
+}
+
+size_t es_sym_transpose_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels) {
+  SymGeo g;
+  if (sym_geo(ndim, shape, order, levels, 0.0, &g) != ES_OK || batch <= 0) return 0;
+  return (size_t)sym_ws_floats(g, batch, true) * sizeof(float);
 }
 
 es_status es_sym_band_lengths(int64_t n, int order, int levels, int64_t* lengths) {
@@ -607,46 +823,12 @@ es_status es_sym_band_lengths(int64_t n, int order, int levels, int64_t* lengths
 
 es_status es_sym_cov_apply(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
                            const float* x, float* y, void* ws, size_t ws_bytes, void* stream) {
-  SymGeo g;
-  es_status st = sym_geo(ndim, shape, order, levels, s, &g);
-  if (st != ES_OK) return st;
-  if (batch < 0) return sym_einval("batch must be >= 0");
-  if (batch == 0) return ES_OK;
-  const int64_t N = g.size(0);
-  if (N > INT64_MAX / 4 / batch) return sym_einval("batch * size overflows");
-  if (!x || !y) return sym_einval("input and output pointers must be non-NULL");
-  if (((uintptr_t)x & 15) || ((uintptr_t)y & 15)) return sym_einval("input and output must be 16-byte aligned");
-  const size_t io = (size_t)(batch * N) * sizeof(float);
-  const char *px = (const char*)x, *py = (const char*)y;
-  if (px < py + io && py < px + io) return sym_einval("input and output overlap");
-  const size_t need = (size_t)sym_ws_floats(g, batch) * sizeof(float);
-  if (need) {
-    if (!ws) return report_error(ES_EWORKSPACE, "workspace required (es_sym_workspace_bytes), got NULL");
-    if (ws_bytes < need) {
-      char buf[160];
-      snprintf(buf, sizeof buf, "workspace of %zu bytes required, got %zu", need, ws_bytes);
-      return report_error(ES_EWORKSPACE, buf);
-    }
-    if ((uintptr_t)ws & 255) return sym_einval("workspace must be 256-byte aligned");
-    const char* pw = (const char*)ws;
-    if ((pw < px + io && px < pw + need) || (pw < py + io && py < pw + need))
-      return sym_einval("workspace overlaps input or output");
-  }
-  std::vector<SymLaunch> seq;
-  if ((st = sym_schedule(g, batch, x, y, (float*)ws, &seq)) != ES_OK) return st;
-  Filter f;
-  if (!sym_filter(g.L, &f)) return report_error(ES_EUNSUPPORTED, "filter derivation failed");
-  if ((st = device_check()) != ES_OK) return st;
-  hipStream_t hs = (hipStream_t)stream;
-  hipError_t he;
-  if (g.m <= 1) {  // every weight is 1: the identity
-    if ((he = launch_copy(x, y, batch * N, hs)) != hipSuccess) return report_error(ES_EDEVICE, hipGetErrorString(he));
-    return ES_OK;
-  }
-  for (const SymLaunch& l : seq)
-    if ((he = launch_sym(g.D, g.L, l.up, l.t, l.grid, f, hs)) != hipSuccess)
-      return report_error(ES_EDEVICE, hipGetErrorString(he));
-  return ES_OK;
+  return sym_run(ndim, shape, batch, order, levels, s, x, y, ws, ws_bytes, stream, false);
+}
+
+es_status es_sym_cov_apply_transpose(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                                     const float* y, float* x, void* ws, size_t ws_bytes, void* stream) {
+  return sym_run(ndim, shape, batch, order, levels, s, y, x, ws, ws_bytes, stream, true);
 }
 
 }  // extern "C"

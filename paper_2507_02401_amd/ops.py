@@ -138,7 +138,16 @@ def sym_band_lengths(n, order, levels):
 
 def sym_cov_apply(x, ndim, order, levels, s, out=None, workspace=None):
     """y = W^{-1} D_2s W x with the non-periodic (half-point symmetric extension) DWT of Sec. 4;
-    any side lengths.  Not symmetric (W^{-1} is not W^T)."""
+    any side lengths.  Not symmetric (W^{-1} is not W^T): its transpose is sym_cov_apply_transpose."""
+    return _sym(x, ndim, order, levels, s, out, workspace, False)
+
+
+def sym_cov_apply_transpose(y, ndim, order, levels, s, out=None, workspace=None):
+    """x = (W^{-1} D_2s W)^T y, the transpose of sym_cov_apply."""
+    return _sym(y, ndim, order, levels, s, out, workspace, True)
+
+
+def _sym(x, ndim, order, levels, s, out, workspace, transpose):
     grid, batch = _split(x, ndim)
     x = x.contiguous()
     if out is None:
@@ -147,12 +156,14 @@ def sym_cov_apply(x, ndim, order, levels, s, out=None, workspace=None):
         raise ValueError("out must be a contiguous float32 tensor of the input's shape")
     lib = load()
     shp = shape_arg(grid)
-    need = int(lib.es_sym_workspace_bytes(ndim, shp, batch, int(order), int(levels)))
+    size = lib.es_sym_transpose_workspace_bytes if transpose else lib.es_sym_workspace_bytes
+    fn = lib.es_sym_cov_apply_transpose if transpose else lib.es_sym_cov_apply
+    need = int(size(ndim, shp, batch, int(order), int(levels)))
     ws = _ws(need, x.device, workspace)
     with torch.cuda.device(x.device):
         stream = torch.cuda.current_stream(x.device).cuda_stream
-        st = lib.es_sym_cov_apply(ndim, shp, batch, int(order), int(levels), float(s), x.data_ptr(),
-                                  out.data_ptr(), ws.data_ptr() if ws is not None else None, need, stream)
+        st = fn(ndim, shp, batch, int(order), int(levels), float(s), x.data_ptr(), out.data_ptr(),
+                ws.data_ptr() if ws is not None else None, need, stream)
     check(st)
     return out
 

@@ -110,3 +110,56 @@ def test_sym_full_size_64x1024_sampled():
         ref = symdwt.sym_cov_apply(x[b].astype(np.float64), 8, 7, 1.5)
         err = rel_l2(y[b].cpu().numpy(), ref)
         assert err < TOL, (b, err)
+
+
+TCASES = [c for c in CASES if int(np.prod(c[0])) <= 300_000] + [((300, 517), 1, 4, 5, 1.0)]
+
+
+@pytest.mark.parametrize("case", TCASES, ids=_ids)
+def test_sym_transpose_parity(case):
+    """The transpose (W^{-1} D W)^T against the oracle's, built from the exact adjoints of its
+    steps (pinned by dense brute force)."""
+    shape, batch, order, levels, s = case
+    y = _input(shape, batch, sum(shape) * 7 + order)
+    say("sym_cov transpose", shape, batch, order, levels, s)
+    got = es.sym_cov_apply_transpose(torch.from_numpy(y).to(DEV), len(shape), order, levels, s).cpu().numpy()
+    for b in range(batch):
+        ref = symdwt.sym_cov_apply_transpose(y[b].astype(np.float64), order, levels, s)
+        err = rel_l2(got[b], ref)
+        assert err < TOL, (b, err)
+
+
+@pytest.mark.parametrize("shape,order,levels", [((1024, 1024), 8, 7), ((96, 80, 72), 4, 4), ((200_000,), 6, 9)])
+def test_sym_transpose_adjointness_large(shape, order, levels):
+    """<T x, y> = <x, T^T y> in FP64 from the GPU results, at sizes beyond the oracle's reach."""
+    x = _input(shape, 2, 1)
+    y = _input(shape, 2, 2)
+    say("sym adjointness", shape, order, levels)
+    xt, yt = torch.from_numpy(x).to(DEV), torch.from_numpy(y).to(DEV)
+    tx = es.sym_cov_apply(xt, len(shape), order, levels, 1.5).double()
+    tty = es.sym_cov_apply_transpose(yt, len(shape), order, levels, 1.5).double()
+    for b in range(2):
+        lhs = float((tx[b] * yt[b].double()).sum())
+        rhs = float((xt[b].double() * tty[b]).sum())
+        scale = float(tx[b].norm() * yt[b].double().norm())
+        assert abs(lhs - rhs) <= 1e-5 * scale, (b, lhs, rhs)
+
+
+def test_sym_autograd_backward_is_the_transpose():
+    """d/dx sum(w * T x) = T^T w (and the transpose's backward is T)."""
+    from paper_2507_02401_amd import autograd as ag
+    shape = (2, 77, 130)
+    x = torch.from_numpy(_input(shape[1:], 2, 3)).to(DEV).requires_grad_(True)
+    wgt = torch.from_numpy(_input(shape[1:], 2, 4)).to(DEV)
+    say("sym autograd")
+    (ag.sym_cov_apply(x, 2, 4, 4, 1.5) * wgt).sum().backward()
+    got = x.grad.cpu().numpy()
+    w64 = wgt.cpu().numpy().astype(np.float64)
+    for b in range(2):
+        ref = symdwt.sym_cov_apply_transpose(w64[b], 4, 4, 1.5)
+        assert rel_l2(got[b], ref) < TOL
+    y = torch.from_numpy(_input(shape[1:], 2, 5)).to(DEV).requires_grad_(True)
+    (ag.sym_cov_apply_transpose(y, 2, 4, 4, 1.5) * wgt).sum().backward()
+    for b in range(2):
+        ref = symdwt.sym_cov_apply(w64[b], 4, 4, 1.5)
+        assert rel_l2(y.grad.cpu().numpy()[b], ref) < TOL

@@ -89,3 +89,31 @@ def test_validation_before_any_device_call(lib, kw, status):
 
 def test_batch_zero_is_a_noop(lib):
     assert _call(lib, batch=0, x=0, y=0, ws=0) == _lib.ES_OK
+
+
+@pytest.mark.parametrize("shape,batch,order,levels", [((1024, 1024), 2, 8, 7), ((37, 53), 3, 2, 4), ((9, 10, 11), 2, 4, 3),
+                                                      ((5,), 7, 8, 6), ((64,), 1, 1, 1)])
+def test_transpose_workspace(lib, shape, batch, order, levels):
+    """The level arrays, then the extended synthesis of the finest level (every axis over
+    -(L-2) .. 2 l_1 - 1, rows padded to a multiple of 4 floats)."""
+    fwd = lib.es_sym_workspace_bytes(len(shape), _lib.shape_arg(shape), batch, order, levels)
+    tr = lib.es_sym_transpose_workspace_bytes(len(shape), _lib.shape_arg(shape), batch, order, levels)
+    if levels < 2:
+        assert tr == fwd == 0
+        return
+    ext = [2 * symdwt.sym_length(v, 2 * order) + 2 * order - 2 for v in shape]
+    stored = int(np.prod(ext[:-1])) * ((ext[-1] + 3) // 4 * 4)
+    assert tr == fwd + 4 * ((batch * stored + 63) // 64 * 64)
+
+
+@pytest.mark.parametrize("kw,status", [(dict(order=0), _lib.ES_EINVAL), (dict(levels=31), _lib.ES_EINVAL),
+                                       (dict(x=FAKE_IN + 4), _lib.ES_EINVAL), (dict(ws=0), _lib.ES_EWORKSPACE),
+                                       (dict(y=FAKE_IN + 64), _lib.ES_EINVAL), (dict(s=float("nan")), _lib.ES_EINVAL)])
+def test_transpose_validation_before_any_device_call(lib, kw, status):
+    args = dict(ndim=2, shape=(37, 53), batch=1, order=4, levels=3, s=1.0, x=FAKE_IN, y=FAKE_OUT, ws=FAKE_WS,
+                ws_bytes=1 << 30)
+    args.update(kw)
+    st = lib.es_sym_cov_apply_transpose(args["ndim"], _lib.shape_arg(args["shape"]), args["batch"], args["order"],
+                                        args["levels"], args["s"], args["x"], args["y"], args["ws"],
+                                        args["ws_bytes"], None)
+    assert st == status
