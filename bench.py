@@ -521,9 +521,20 @@ def main():
             es.sym_cov_apply(x, 2, ORDER, LEVELS, S, out=y, workspace=sws)
         torch.cuda.synchronize()
         tsym = (time.perf_counter() - t0) / args.steps
+        tws = torch.empty(max(1, lib.es_sym_transpose_workspace_bytes(2, _lib.shape_arg(grid), IMAGES, ORDER, LEVELS)),
+                          dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup):
+            es.sym_cov_apply_transpose(x, 2, ORDER, LEVELS, S, out=y, workspace=tws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            es.sym_cov_apply_transpose(x, 2, ORDER, LEVELS, S, out=y, workspace=tws)
+        torch.cuda.synchronize()
+        tsymT = (time.perf_counter() - t0) / args.steps
         print(json.dumps({"workload": f"sym_cov_apply: {IMAGES} images {SIDE}x{SIDE}, db{ORDER}, {LEVELS} levels, "
                                       f"s={S}, half-point symmetric extension",
                           "ms": round(1e3 * tsym, 4), "voxels_per_s": round(voxels / tsym, 1),
+                          "transpose_ms": round(1e3 * tsymT, 4),
                           "band_lengths": es.sym_band_lengths(SIDE, ORDER, LEVELS)}), flush=True)
         return
 

@@ -436,34 +436,64 @@ struct SymFold {
   float alpha, beta;
 };
 
+// Images of j along one axis.  For n >= L - 1 the extension range holds at most one position of
+// each family: j itself, -1 - j near the start, 2n - 1 - j near the end (`simple`); shorter axes
+// enumerate both families.
+template <class F>
+DEVI void visit_images(int j, int n, int lo, int hi, bool simple, F f) {
+  if (simple) {
+    f(j);
+    if (-1 - j >= lo) f(-1 - j);
+    if (2 * n - 1 - j <= hi) f(2 * n - 1 - j);
+  } else {
+    for_images(j, n, lo, hi, f);
+  }
+}
+
+// One output row (instance, j0, j1) per grid-y index; threads along the row.
 __global__ void __launch_bounds__(256) k_sym_fold(SymFold F) {
-  const int64_t per = (int64_t)F.no[0] * F.no[1] * F.no[2];
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < F.total; e += (int64_t)gridDim.x * 256) {
-    const int64_t inst = e / per;
-    int r = (int)(e - inst * per);
-    const int j2 = r % F.no[2];
-    r /= F.no[2];
-    const int j1 = r % F.no[1], j0 = r / F.no[1];
+  const int n0 = F.no[0], n1 = F.no[1], n2 = F.no[2];
+  const int64_t rows = F.total / n2;
+  int lo[3], hi[3], eo[3];
+  bool simple[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = F.present[a] ? -F.ext : 0;
+    hi[a] = F.present[a] ? 2 * F.nl[a] - 1 : 0;
+    eo[a] = F.present[a] ? F.ext : 0;
+    simple[a] = !F.present[a] || F.no[a] >= F.ext + 1;
+  }
+  const int rpi = n0 * n1;  // rows per instance; the host keeps the row count below 2^31
+  for (int r = blockIdx.y; r < (int)rows; r += gridDim.y) {
+    const int inst = r / rpi;
+    const int rr = r - inst * rpi;
+    const int j0 = rr / n1, j1 = rr - j0 * n1;
     const float* v = F.v + inst * F.bs_v;
-    auto range = [&](int a, int& lo, int& hi) {
-      lo = F.present[a] ? -F.ext : 0;
-      hi = F.present[a] ? 2 * F.nl[a] - 1 : 0;
-    };
-    int lo0, hi0, lo1, hi1, lo2, hi2;
-    range(0, lo0, hi0);
-    range(1, lo1, hi1);
-    range(2, lo2, hi2);
-    const int e0 = F.present[0] ? F.ext : 0, e1 = F.present[1] ? F.ext : 0, e2 = F.present[2] ? F.ext : 0;
-    float acc = 0.f;
-    for_images(j0, F.no[0], lo0, hi0, [&](int p0) {
-      for_images(j1, F.no[1], lo1, hi1, [&](int p1) {
-        const float* row = v + (p0 + e0) * F.sv[0] + (p1 + e1) * F.sv[1] + e2;
-        for_images(j2, F.no[2], lo2, hi2, [&](int p2) { acc += gld(row + p2); });
-      });
-    });
-    const int64_t o = inst * F.bs_out + (int64_t)j0 * F.so[0] + (int64_t)j1 * F.so[1] + j2;
-    const float sv = F.same ? gld(F.same + o) : 0.f;
-    gst(F.out + o, fmaf(F.alpha, sv, F.beta * acc));
+    const int64_t orow = inst * F.bs_out + (int64_t)j0 * F.so[0] + (int64_t)j1 * F.so[1];
+    // four outputs per thread and pass, every load of the pass issued before its stores
+    constexpr int U = 4;
+    for (int base = threadIdx.x; base < n2; base += U * 256) {
+      float acc[U], sv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j2 = base + u * 256;
+        acc[u] = 0.f;
+        sv[u] = 0.f;
+        if (j2 < n2) {
+          visit_images(j0, n0, lo[0], hi[0], simple[0], [&](int p0) {
+            visit_images(j1, n1, lo[1], hi[1], simple[1], [&](int p1) {
+              const float* row = v + (p0 + eo[0]) * F.sv[0] + (p1 + eo[1]) * F.sv[1] + eo[2];
+              visit_images(j2, n2, lo[2], hi[2], simple[2], [&](int p2) { acc[u] += gld(row + p2); });
+            });
+          });
+          if (F.same) sv[u] = gld(F.same + orow + j2);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j2 = base + u * 256;
+        if (j2 < n2) gst(F.out + orow + j2, fmaf(F.alpha, sv[u], F.beta * acc[u]));
+      }
+    }
   }
 }
 
@@ -732,7 +762,7 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
     F.ext = g.L - 2;
     F.alpha = (float)alpha;
     F.beta = 1.f;
-    fl.grid = std::min<int64_t>((F.total + 255) / 256, 1 << 20);
+    fl.grid = 0;  // 2-D grid, see the launch
     out->push_back(fl);
   }
   for (const SymLaunch& l : *out)
@@ -751,6 +781,8 @@ es_status sym_run(int ndim, const int64_t* shape, int64_t batch, int order, int 
   if (N > INT64_MAX / 4 / batch) return sym_einval("batch * size overflows");
   if (transpose && g.m >= 2 && ext_dims(g, 1).stored() > 0x7fffffffll)
     return sym_einval("the extended level holds more than 2^31-1 elements per instance");
+  if (transpose && batch * (N / g.dims[0][2]) > 0x7fffffffll)
+    return sym_einval("the transposed operator handles at most 2^31-1 rows per call");
   if (!x || !y) return sym_einval("input and output pointers must be non-NULL");
   if (((uintptr_t)x & 15) || ((uintptr_t)y & 15)) return sym_einval("input and output must be 16-byte aligned");
   const size_t io = (size_t)(batch * N) * sizeof(float);
@@ -782,7 +814,10 @@ es_status sym_run(int ndim, const int64_t* shape, int64_t batch, int order, int 
   }
   for (const SymLaunch& l : seq) {
     if (l.kind == 2) {
-      hipLaunchKernelGGL(k_sym_fold, dim3((unsigned)l.grid), dim3(256), 0, hs, l.fold);
+      // one output row per work-group (rows over grid y, at most 65535 at a time, strided)
+      const int64_t rows = l.fold.total / l.fold.no[2];
+      const dim3 grid(1, (unsigned)std::min<int64_t>(rows, 65535));
+      hipLaunchKernelGGL(k_sym_fold, grid, dim3(256), 0, hs, l.fold);
       he = hipGetLastError();
     } else {
       he = launch_sym(g.D, g.L, l.kind == 1, l.zx, l.t, l.grid, f, hs);
