@@ -22,6 +22,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the one knob this script switches while the device runtime runs: created here, before any
+# device call, so that switching it replaces a value instead of adding or removing an
+# environment entry under the runtime's threads (the library reads an empty knob as absent)
+os.environ.setdefault("ESWAVE_PLAN_PERSISTENT", "")
 
 METRIC = "E_s E_s^* voxels/s + HBM GB/s, batched/autograd vs plain; FP32 err vs FP64"
 HBM_PEAK_GBPS = 8000.0
@@ -82,6 +86,35 @@ def trace_summary(path):
     for (name, wg), d in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
         lines.append(f"| `{name}` | {wg} | {len(d)} | {statistics.mean(d):.2f} | {min(d):.2f} | {max(d):.2f} |")
     return "\n".join(lines)
+
+def valu_summary(path):
+    """Per-(kernel, grid) table of a `rocprofv3 --pmc VALUBusy LDSBankConflict SQ_INSTS_VALU
+    SQ_INSTS_LDS SQ_WAVES SQ_ACTIVE_INST_LDS --output-format csv` pass over the `es` kernels: the
+    last dispatch of each shape (for a tuned sequence, the launch the autotuner kept)."""
+    import csv
+    import re
+    last = {}
+    for r in csv.DictReader(open(path)):
+        if "es::" not in r["Kernel_Name"]:
+            continue
+        wg = int(r["Grid_Size"]) // int(r["Workgroup_Size"])
+        key = (r["Kernel_Name"], wg)
+        disp = int(r["Dispatch_Id"])
+        cur = last.get(key)
+        if cur is None or disp > cur["disp"]:
+            cur = last[key] = {"disp": disp, "us": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3}
+        if disp == cur["disp"]:
+            cur[r["Counter_Name"]] = float(r["Counter_Value"])
+    lines = ["| kernel | work-groups | µs (profiled) | VALUBusy % | LDSBankConflict % | VALU instr / wave | "
+             "LDS instr / wave |", "|---|---|---|---|---|---|---|"]
+    for (name, wg), c in sorted(last.items(), key=lambda kv: -kv[1]["us"]):
+        short = re.sub(r"^void es::(\w+<[^>]*>).*$", r"\1", name)
+        w = max(c.get("SQ_WAVES", 0.0), 1.0)
+        lines.append(f"| `{short}` | {wg} | {c['us']:.1f} | {c.get('VALUBusy', 0):.1f} | "
+                     f"{c.get('LDSBankConflict', 0):.1f} | {c.get('SQ_INSTS_VALU', 0) / w:.0f} | "
+                     f"{c.get('SQ_INSTS_LDS', 0) / w:.0f} |")
+    return "\n".join(lines)
+
 
 def source_hash():
     """Hash of the level kernels' source: counter readings are only valid for the kernels they measured."""
@@ -278,9 +311,10 @@ def other_workloads(args, es, inputs, torch, np):
     plan.close()
     # the same plan run persistently (one launch per dimensionality and filter length, per-XCD
     # work-item queues), after its autotuner chose the coarse fusion depth and the pipeline lag
+    knob = os.environ["ESWAVE_PLAN_PERSISTENT"]
     os.environ["ESWAVE_PLAN_PERSISTENT"] = "1"
     pplan = es.RaggedPlan(descs, es.OP_COV)
-    os.environ.pop("ESWAVE_PLAN_PERSISTENT")
+    os.environ["ESWAVE_PLAN_PERSISTENT"] = knob
     pplan.autotune(ins, outs, reps=2)
     tpg = _time(lambda: pplan(ins, outs, graph=True), torch, reps)
     pplan.check_errors()
@@ -436,6 +470,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the other workloads")
     ap.add_argument("--no-autotune", action="store_true", help="use the heuristic tile choice")
     ap.add_argument("--trace-summary", metavar="CSV", help="summarise a rocprofv3 kernel trace and exit")
+    ap.add_argument("--valu-summary", metavar="CSV", help="summarise a rocprofv3 VALU/LDS counter pass and exit")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="combine two rocprofv3 --pmc runs into the committed traffic file and exit")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -445,12 +480,17 @@ def main():
                          "and exit")
     ap.add_argument("--fourier-only", action="store_true",
                     help="time only the Fourier form (fft_cov_apply) on the same batch (for profiling) and exit")
+    ap.add_argument("--volume-only", action="store_true",
+                    help="time only es_adjoint + es_apply of the 256^3 db4 m5 volume (for profiling) and exit")
     ap.add_argument("--ragged-seed", type=int, default=None,
                     help="time only a 200-instance ragged plan drawn with this seed (graph vs eager) and exit; "
                          "seed 0 is not accepted (that case is kept off the GPU)")
     args = ap.parse_args()
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
+        return
+    if args.valu_summary:
+        print(valu_summary(args.valu_summary))
         return
     if args.pmc_summary:
         print(json.dumps(pmc_summary(args.pmc_summary[0], args.pmc_summary[1], TRAFFIC_FILE), indent=1))
@@ -536,6 +576,33 @@ def main():
                           "ms": round(1e3 * tsym, 4), "voxels_per_s": round(voxels / tsym, 1),
                           "transpose_ms": round(1e3 * tsymT, 4),
                           "band_lengths": es.sym_band_lengths(SIDE, ORDER, LEVELS)}), flush=True)
+        return
+
+    if args.volume_only:
+        d = inputs.volume_autograd(side=256)
+        xv = torch.from_numpy(d["x"]).to(dev)
+        cv = torch.empty_like(xv)
+        yv = torch.empty_like(xv)
+        vargs = (3, d["order"], d["levels"], d["s"])
+        if not args.no_autotune:
+            es.autotune(es.OP_ADJOINT, xv, *vargs, out=cv)
+            es.autotune(es.OP_APPLY, cv, *vargs, out=yv)
+
+        def pair():
+            es.es_adjoint(xv, *vargs, out=cv)
+            es.es_apply(cv, *vargs, out=yv)
+
+        for _ in range(args.warmup):
+            pair()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pair()
+        torch.cuda.synchronize()
+        tv = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"workload": f"es_adjoint + es_apply: 256^3, db{d['order']}, {d['levels']} levels, s={d['s']}",
+                          "ms": round(1e3 * tv, 4), "effective_GBps": round(16 * xv.numel() / tv / 1e9, 1),
+                          "autotuned": not args.no_autotune}), flush=True)
         return
 
     if args.fourier_only:

@@ -210,6 +210,24 @@ DEVI void synthesis_pass(int nlines, int nch, const Filter& f, In in, Out out) {
   }
 }
 
+// N consecutive floats starting OFFS (< 4) past a 16-byte aligned LDS address, read as whole
+// 16-byte vectors: lanes whose windows start 16 bytes apart then read without bank conflicts.
+// The vectors cover at most 3 floats past the window, which the caller's row must hold.
+template <int N, int OFFS>
+DEVI void lds_window(const float* base16, float* w) {
+  static_assert(OFFS >= 0 && OFFS < 4, "offset inside the first vector");
+  constexpr int W4 = (OFFS + N + 3) / 4;
+  const float4* p = reinterpret_cast<const float4*>(base16);
+  float t[4 * W4];
+#pragma unroll
+  for (int v = 0; v < W4; ++v) {
+    const float4 x = p[v];
+    t[4 * v] = x.x; t[4 * v + 1] = x.y; t[4 * v + 2] = x.z; t[4 * v + 3] = x.w;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) w[j] = t[OFFS + j];
+}
+
 // Contiguous-dim analysis of NROW staged rows, results written back over the staging buffer
 // as rows of T2 (FB: [lo T2 | hi T2]) floats.  Each task is P consecutive outputs of one row;
 // a thread holds its results in registers across the barrier that frees the buffer.
@@ -262,6 +280,44 @@ DEVI void row_pass_inplace(float* s_in, const Filter& f) {
     }
   }
   __syncthreads();
+}
+
+// Contiguous-dim analysis of NROW staged rows of `src` into `dst`, as rows of 2 T2 floats
+// [lo T2 | hi T2].  Each task is P consecutive outputs of one row, the taps summed in the order
+// of row_pass_inplace.  No barrier: the caller orders the reads of `src` and the writes of `dst`
+// against the other threads.
+template <int L, int P, int NROW, int T2, int I2P, int NT>
+DEVI void row_pass_to(const float* src, float* dst, const Filter& f) {
+  constexpr int NCH = T2 / P;
+  constexpr int NTASK = NROW * NCH;
+  constexpr int W = 2 * P + L - 2;
+  constexpr int W4 = (W + 3) / 4;
+  static_assert(P == 4 && T2 % 4 == 0 && I2P % 4 == 0, "16-byte windows and stores");
+  for (int task = threadIdx.x; task < NTASK; task += NT) {
+    const int ch = task % NCH, l = task / NCH;
+    const float4* p = reinterpret_cast<const float4*>(src + l * I2P + 2 * P * ch);
+    float win[4 * W4];
+#pragma unroll
+    for (int v = 0; v < W4; ++v) {
+      const float4 x = p[v];
+      win[4 * v] = x.x; win[4 * v + 1] = x.y; win[4 * v + 2] = x.z; win[4 * v + 3] = x.w;
+    }
+    float lo[P], hi[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      float a = 0.f, d = 0.f;
+#pragma unroll
+      for (int t = 0; t < L; ++t) {
+        a = fmaf(f.h[t], win[2 * q + t], a);
+        d = fmaf(f.g[t], win[2 * q + t], d);
+      }
+      lo[q] = a;
+      hi[q] = d;
+    }
+    float4* o = reinterpret_cast<float4*>(dst + l * 2 * T2 + P * ch);
+    o[0] = make_float4(lo[0], lo[1], lo[2], lo[3]);
+    o[T2 / 4] = make_float4(hi[0], hi[1], hi[2], hi[3]);
+  }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -187,29 +187,31 @@ __global__ void __launch_bounds__(NT) k_lp_up2(TaskArgs args, Filter f) {
 // Streamed 3-D full-bank levels.  A work-group owns an in-plane tile (axes 1, 2) and a run of
 // R output slices along axis 0, and visits the input slices the run needs in order: each slice
 // is staged (with its in-plane halo) and filtered in-plane once, and the axis-0 filter combines
-// the filtered slices (analysis: running sums in registers; synthesis: a ring of the last L/2
-// filtered slices in LDS).  Axis-0 halos are neither re-read nor recomputed except at the start
-// of a run, and the in-plane halo is the 2-D one.  The axes are filtered in the order 2, 1, 0
+// the filtered slices in running sums each thread keeps in registers for its in-plane positions.
+// Axis-0 halos are neither re-read nor recomputed except at the start of a run, and the in-plane
+// halo is the 2-D one.  The axes are filtered in the order 2, 1, 0
 // with the same arithmetic as the plain 3-D tiles, so both give identical results.
 
-// FB_DOWN_S: in-plane tile T1 x T2 per band, R output slices.  Iteration p stages input slices
-// 2p and 2p+1 of the work-group's run (with the in-plane halo), filters both in-plane, and adds
-// them to the axis-0 sums each thread keeps in registers for its in-plane positions.  Output
-// slice k takes input slices 2k .. 2k+L-1 in that order, so after iteration p output p-(H-1)
-// is complete; the sums then shift by one output.
+// FB_DOWN_S: in-plane tile T1 x T2 per band, R output slices.  Iteration p filters input slices
+// 2p and 2p+1 of the work-group's run (staged with the in-plane halo) along axis 2 into a buffer
+// of their own.  After one barrier the next pair is staged over the first buffer while every
+// thread filters one column of both slices along axis 1 and adds the results to the axis-0 sums
+// it keeps in registers for those positions; a second barrier ends the iteration.  Output slice
+// k takes input slices 2k .. 2k+L-1 in that order, so after iteration p output p-(H-1) is
+// complete; the sums then shift by one output.
 template <int L, int R, int T1, int T2, int NT, bool VEC>
 __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
   constexpr int H = L / 2;
   constexpr int I1 = 2 * T1 + L - 2, I2 = 2 * T2 + L - 2;
   constexpr int I2P = (I2 + 3) & ~3, NV = I2P / 4;
-  constexpr int PL = 4 * T1 * T2;  // one filtered slice: rows [lo T1 | hi T1] x cols [lo T2 | hi T2]
   constexpr int T2x = 2 * T2;
-  constexpr int P1 = T1 % 4 == 0 ? 4 : 2;
-  constexpr int NP = R + H - 1;  // iterations
-  constexpr int QT = PL / NT;    // in-plane positions per thread
-  static_assert(PL % NT == 0, "positions must divide evenly among the threads");
+  constexpr int P1 = 2 * T1 * T2 / NT;  // axis-1 outputs per band of one thread (one column)
+  constexpr int W1 = 2 * P1 + L - 2;
+  constexpr int QT = 2 * P1;            // in-plane positions per thread: rows [lo P1 | hi P1]
+  constexpr int NP = R + H - 1;         // iterations
+  static_assert(P1 >= 1 && P1 * NT == 2 * T1 * T2 && T1 % P1 == 0, "one axis-1 task per thread");
   __shared__ __attribute__((aligned(16))) float s_in[2 * I1 * I2P];
-  __shared__ float s_pl[2 * PL];
+  __shared__ __attribute__((aligned(16))) float s_r[2 * I1 * T2x];  // rows (e, i1): [lo T2 | hi T2]
   __shared__ int s_row[I1];
   __shared__ int s_col[NV];
 
@@ -224,25 +226,55 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
   const int h0 = b0 >> 1, h1 = b1 >> 1, h2 = b2 >> 1;
   const int k0 = R * tl.c0, o1 = 2 * T1 * tl.c1, o2 = 2 * T2 * tl.c2;
   const float alpha = t.alpha, beta = t.beta;
+  const int c = threadIdx.x % T2x, kc = threadIdx.x / T2x;  // this thread's column and row chunk
+  const int e2 = c >= T2, g2 = T2 * tl.c2 + c - e2 * T2;
 
   for (int i = threadIdx.x; i < I1; i += NT) s_row[i] = pmod(o1 + i, b1) * t.st_in0[1];
   for (int i = threadIdx.x; i < NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
   __syncthreads();
 
-  // vector path: the next pair's loads are issued before this pair is filtered, so their
-  // latency overlaps the in-plane passes (row length I2P = 4 NV: LDS slot = load index)
+  // vector path: a pair's 16-byte loads are issued one iteration before it is staged, so their
+  // latency overlaps the filtering of the pair before (row length I2P = 4 NV: LDS slot = load
+  // index)
   constexpr int NLD = 2 * I1 * NV, ITL = (NLD + NT - 1) / NT;
   float4 pf[VEC ? ITL : 1];
-  auto load_pair = [&](int p) {
-    const int off0 = pmod(2 * (k0 + p), b0) * t.st_in0[0], off1 = pmod(2 * (k0 + p) + 1, b0) * t.st_in0[0];
+  // each thread's load offsets within a slice do not change along the run: computed once
+  static_assert(ITL <= 32, "one bit per load in the masks");
+  int loff[VEC ? ITL : 1];
+  unsigned lsec = 0;  // bit it: load it reads the second slice of the pair
+  if constexpr (VEC) {
 #pragma unroll
     for (int it = 0; it < ITL; ++it) {
       const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
       const int e = q >= I1 * NV, r = q - e * I1 * NV;
-      pf[it] = gld4(src + (e ? off1 : off0) + s_row[r / NV] + s_col[r % NV]);
+      loff[it] = s_row[r / NV] + s_col[r % NV];
+      lsec |= unsigned(e) << it;
+    }
+  }
+  auto load_pair = [&](int p) {
+    const float* sl0 = src + pmod(2 * (k0 + p), b0) * t.st_in0[0];
+    const float* sl1 = src + pmod(2 * (k0 + p) + 1, b0) * t.st_in0[0];
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) pf[it] = gld4(((lsec >> it) & 1 ? sl1 : sl0) + loff[it]);
+  };
+  auto stage_pair = [&](int p) {
+    if constexpr (VEC) {
+      float4* d4 = reinterpret_cast<float4*>(s_in);
+#pragma unroll
+      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        stage_rows<NT, I1, NV, false>(src + pmod(2 * (k0 + p) + e, b0) * t.st_in0[0], s_row, s_col,
+                                      s_in + e * I1 * I2P, I2P, b2);
     }
   };
   if constexpr (VEC) load_pair(0);
+  stage_pair(0);
+  __syncthreads();
+  if constexpr (VEC) {
+    if (NP > 1) load_pair(1);
+  }
 
   float alo[H][QT], ahi[H][QT];
 #pragma unroll
@@ -252,37 +284,36 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
   KSum nsq;  // squared-norm mode: this thread's compensated sum
 
   for (int p = 0; p < NP; ++p) {
-    if constexpr (VEC) {
-      float4* d4 = reinterpret_cast<float4*>(s_in);
-#pragma unroll
-      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
-      __syncthreads();
-      load_pair(min(p + 1, NP - 1));
-    } else {
-#pragma unroll
-      for (int e = 0; e < 2; ++e)
-        stage_rows<NT, I1, NV, false>(src + pmod(2 * (k0 + p) + e, b0) * t.st_in0[0], s_row, s_col,
-                                      s_in + e * I1 * I2P, I2P, b2);
-      __syncthreads();
-    }
-    row_pass_inplace<L, 4, 2 * I1, T2, I2P, NT, true>(s_in, f);  // rows (e, i1) of [lo T2 | hi T2]
-    analysis_pass<L, P1, true, true, NT>(
-        2 * T2x, T1 / P1, f,
-        [&](int l, int j0, float* w) {
-          const int e = l / T2x, c = l - e * T2x;
-#pragma unroll
-          for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_in[(e * I1 + j0 + j) * T2x + c];
-        },
-        [&](int l, int k, float lo, float hi) {
-          const int e = l / T2x, c = l - e * T2x;
-          s_pl[e * PL + k * T2x + c] = lo;
-          s_pl[e * PL + (T1 + k) * T2x + c] = hi;
-        });
+    row_pass_to<L, 4, 2 * I1, T2, I2P, NT>(s_in, s_r, f);  // rows (e, i1) -> [lo T2 | hi T2]
     __syncthreads();
+    if (p + 1 < NP) {
+      stage_pair(p + 1);
+      if constexpr (VEC) {
+        if (p + 2 < NP) load_pair(p + 2);
+      }
+    }
+    // axis 1 of both slices at column c, output rows P1 kc .. P1 kc + P1 - 1 of each band
+    float x[2][QT];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      float win[W1];
+#pragma unroll
+      for (int j = 0; j < W1; ++j) win[j] = s_r[(e * I1 + 2 * P1 * kc + j) * T2x + c];
+#pragma unroll
+      for (int q = 0; q < P1; ++q) {
+        float lo = 0.f, hi = 0.f;
+#pragma unroll
+        for (int tt = 0; tt < L; ++tt) {
+          lo = fmaf(f.h[tt], win[2 * q + tt], lo);
+          hi = fmaf(f.g[tt], win[2 * q + tt], hi);
+        }
+        x[e][q] = lo;
+        x[e][P1 + q] = hi;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < QT; ++u) {
-      const int q = threadIdx.x + u * NT;
-      const float x0 = s_pl[q], x1 = s_pl[PL + q];
+      const float x0 = x[0][u], x1 = x[1][u];
 #pragma unroll
       for (int j = 0; j < H; ++j) {  // output p - j takes taps 2j, 2j+1
         alo[j][u] = fmaf(f.h[2 * j], x0, alo[j][u]);
@@ -292,14 +323,12 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
       }
     }
     const int g0 = k0 + p - (H - 1);  // output completed by this iteration
-    if (p >= H - 1 && g0 < h0) {
+    if (p >= H - 1 && g0 < h0 && g2 < h2) {
 #pragma unroll
       for (int u = 0; u < QT; ++u) {
-        const int q = threadIdx.x + u * NT;
-        const int r = q / T2x, c = q - r * T2x;
-        const int e1 = r >= T1, e2 = c >= T2;
-        const int g1 = T1 * tl.c1 + r - e1 * T1, g2 = T2 * tl.c2 + c - e2 * T2;
-        if (g1 < h1 && g2 < h2) {
+        const int e1 = u >= P1;
+        const int g1 = T1 * tl.c1 + P1 * kc + u - e1 * P1;
+        if (g1 < h1) {
           // band (e0, e1, e2) at half-res position (g0, g1, g2)
           const float lo = alo[H - 1][u], hi = ahi[H - 1][u];
           if ((e1 | e2) == 0) {
@@ -324,6 +353,7 @@ __global__ void __launch_bounds__(NT) k_fb_down_s(TaskArgs args, Filter f) {
       }
 #pragma unroll
     for (int u = 0; u < QT; ++u) alo[0][u] = ahi[0][u] = 0.f;
+    __syncthreads();
   }
   if (t.flags & kNormSq) store_wg_sum<NT>(nsq, reinterpret_cast<float2*>(t.out0) + (wg - t.tile_begin));
 }
@@ -383,20 +413,34 @@ __global__ void __launch_bounds__(NT) k_fb_up_s(TaskArgs args, Filter f) {
   // (row length J2P = 4 NV: LDS slot = load index)
   constexpr int NL1 = NR * 2 * NV, NLD = 2 * NL1, ITL = (NLD + NT - 1) / NT;
   float4 pf[VEC ? ITL : 1];
-  auto load_pair = [&](int p) {
-    const int s0 = pmod(q0 - (H - 1) + 2 * p, h0), s1 = pmod(q0 - (H - 1) + 2 * p + 1, h0);
+  // each thread's load offsets within a slice do not change along the run: computed once
+  static_assert(ITL <= 32, "one bit per load in the masks");
+  int loff[VEC ? ITL : 1];
+  unsigned lsec = 0, lll = 0;  // bit it: load it reads the pair's second slice / the band in0
+  if constexpr (VEC) {
 #pragma unroll
     for (int it = 0; it < ITL; ++it) {
       const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
       const int e = q >= NL1, qq = q - e * NL1;
-      const int r0g = e ? s1 : s0;
       const int v = qq % NV, re = qq / NV;  // re = row * 2 + e2
       const int e2 = re & 1, row = re >> 1;
       const int e0 = row / (2 * J1), rr = row - e0 * 2 * J1;  // rr = e1 * J1 + j1
       const bool isll = e0 == 0 && e2 == 0 && rr < J1;
-      const float* ptr = isll ? ap + r0g * t.st_in0[0] + s_rowl[rr] + s_col[v]
-                              : cp + (e0 * h0 + r0g) * t.st_in1[0] + s_rowc[rr] + s_col[e2 * NV + v];
-      float4 x = gld4(ptr);
+      loff[it] = isll ? s_rowl[rr] + s_col[v] : e0 * h0 * t.st_in1[0] + s_rowc[rr] + s_col[e2 * NV + v];
+      lsec |= unsigned(e) << it;
+      lll |= unsigned(isll) << it;
+    }
+  }
+  auto load_pair = [&](int p) {
+    const int s0 = pmod(q0 - (H - 1) + 2 * p, h0), s1 = pmod(q0 - (H - 1) + 2 * p + 1, h0);
+    const float* a0 = ap + s0 * t.st_in0[0];
+    const float* a1 = ap + s1 * t.st_in0[0];
+    const float* c0 = cp + s0 * t.st_in1[0];
+    const float* c1 = cp + s1 * t.st_in1[0];
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const bool sec = (lsec >> it) & 1, isll = (lll >> it) & 1;
+      float4 x = gld4((isll ? (sec ? a1 : a0) : (sec ? c1 : c0)) + loff[it]);
       const float sc = isll ? beta : alpha;
       x.x *= sc; x.y *= sc; x.z *= sc; x.w *= sc;
       pf[it] = x;
@@ -438,10 +482,9 @@ __global__ void __launch_bounds__(NT) k_fb_up_s(TaskArgs args, Filter f) {
     // in-plane axis 2: every staged row (e, e0, e1, j1) -> U2 full-res values
     synthesis_pass<L, P2, true, false, NT>(
         2 * NR, U2 / 2 / P2, f,
-        [&](int l, int j0, float* lo, float* hi) {
-          const float* ptr = s_in + (2 * l) * J2P + OFF + j0;
-#pragma unroll
-          for (int j = 0; j < P2 + H - 1; ++j) { lo[j] = ptr[j]; hi[j] = ptr[J2P + j]; }
+        [&](int l, int j0, float* lo, float* hi) {  // rows of J2P floats (a multiple of 4)
+          lds_window<P2 + H - 1, OFF>(s_in + (2 * l) * J2P + j0, lo);
+          lds_window<P2 + H - 1, OFF>(s_in + (2 * l + 1) * J2P + j0, hi);
         },
         [&](int l, int pp, float e0, float e1) {
           s_a[l * U2 + pp] = e0;
@@ -701,10 +744,9 @@ __global__ void __launch_bounds__(NT) k_fb_up(TaskArgs args, Filter f) {
 
   synthesis_pass<L, P2, true, false, NT>(
       NRB, U2 / 2 / P2, f,
-      [&](int l, int j0, float* lo, float* hi) {
-        const float* p = s_in + (2 * l) * G::J2P + G::OFF + j0;
-#pragma unroll
-        for (int j = 0; j < P2 + H - 1; ++j) { lo[j] = p[j]; hi[j] = p[G::J2P + j]; }
+      [&](int l, int j0, float* lo, float* hi) {  // rows of J2P floats (a multiple of 4)
+        lds_window<P2 + H - 1, G::OFF>(s_in + (2 * l) * G::J2P + j0, lo);
+        lds_window<P2 + H - 1, G::OFF>(s_in + (2 * l + 1) * G::J2P + j0, hi);
       },
       [&](int l, int p, float e0, float e1) {
         s_a[l * U2 + p] = e0;

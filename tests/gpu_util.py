@@ -24,7 +24,14 @@ def say(*a):
 
 
 class env:
-    """Temporarily set environment variables read by the library at each call."""
+    """Temporarily set environment variables read by the library at each call.
+
+    Only names the test session created before the first device call (conftest.KNOBS) may be
+    set here, and they are restored to a value, never removed: adding or removing a name can
+    reallocate the process's environment array while a runtime thread reads it (getenv), so
+    that is done only before any thread of the device runtime exists.  The library reads an
+    empty knob as an absent one.
+    """
 
     def __init__(self, **kv):
         self.kv = {k: str(v) for k, v in kv.items()}
@@ -32,12 +39,11 @@ class env:
 
     def __enter__(self):
         for k, v in self.kv.items():
-            self.old[k] = os.environ.get(k)
+            if k not in os.environ:
+                raise KeyError(f"{k} was not created before the first device call (add it to conftest.KNOBS)")
+            self.old[k] = os.environ[k]
             os.environ[k] = v
 
     def __exit__(self, *exc):
         for k, v in self.old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+            os.environ[k] = v

@@ -109,6 +109,24 @@ def test_families_bit_identical(op, shape):
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("order", [1, 3, 8])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_families_bit_identical_3d_variants(order, variant):
+    """Every streamed 3-D tile variant against the plain tiles, bit for bit: ragged in-plane
+    tiles, runs along axis 0 longer than the level, filters from 2 to 16 taps, analysis and
+    synthesis (the adjoint and the apply)."""
+    shape, levels, s = (2, 40, 24, 72), 3, 1.25
+    x = torch.from_numpy(np.random.default_rng(order * 10 + variant).standard_normal(shape).astype(np.float32)).to(DEV)
+    say("families-bits-3d", order, variant, shape)
+    for op in (0, 1):
+        outs = []
+        for knobs in (dict(ESWAVE_STREAMED=0, ESWAVE_TAIL_MAX=0),
+                      dict(ESWAVE_STREAMED=2, ESWAVE_TAIL_MAX=0, ESWAVE_FORCE_VARIANT=variant)):
+            with env(**knobs):
+                outs.append(es.apply_op(op, x, 3, order, levels, s).cpu().numpy())
+        assert np.array_equal(outs[0], outs[1]), OP_NAMES[op]
+
+
 @pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
 def test_uniform_batch(op):
     """A batch of instances in one call equals the per-instance oracle."""

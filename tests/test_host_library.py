@@ -191,3 +191,17 @@ def test_tikhonov_pcg_validates_on_host(lib):
     assert call(ws_bytes=need - 1) == _lib.ES_EWORKSPACE
     assert call(ws=WS + 16) == _lib.ES_EINVAL          # workspace alignment
     assert call(x=P + 64) == _lib.ES_EINVAL            # x overlaps p
+
+
+def test_every_library_knob_is_created_before_device_use():
+    """The test session creates every environment knob the library reads before the first device
+    call (tests switch them by replacing values only)."""
+    import re
+    import conftest
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2507_02401_amd", "csrc")
+    names = set()
+    for fn in os.listdir(csrc):
+        if fn.endswith((".cpp", ".hip", ".h")):
+            names |= set(re.findall(r'getenv\("(ESWAVE_[A-Z0-9_]+)"\)', open(os.path.join(csrc, fn)).read()))
+    assert names and names <= set(conftest.KNOBS), sorted(names - set(conftest.KNOBS))
+    assert all(k in os.environ for k in conftest.KNOBS)
