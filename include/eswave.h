@@ -224,7 +224,8 @@ size_t es_sym_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int
  * w_1 y + sum_i c_i (A^T)^i (S_a^T)^i y with S_a^T the analysis sum over the signal extended by
  * zeros and A^T the synthesis onto the extension positions -(L-2) .. 2l-1 folded back onto the
  * samples they reflect to.  Arguments as for es_sym_cov_apply (y in, x out); the workspace is
- * es_sym_transpose_workspace_bytes(...) bytes (the level arrays and one extended level). */
+ * es_sym_transpose_workspace_bytes(...) bytes (the level arrays; on 3-D grids also one extended
+ * level, since 1-D and 2-D grids fold the extension in a pass over the boundary shell only). */
 es_status es_sym_cov_apply_transpose(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
                                      const float* y, float* x, void* ws, size_t ws_bytes, void* stream);
 size_t es_sym_transpose_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);

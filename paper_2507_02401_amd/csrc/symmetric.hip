@@ -497,6 +497,159 @@ __global__ void __launch_bounds__(256) k_sym_fold(SymFold F) {
   }
 }
 
+// Boundary shell of the transposed operator on 1-D and 2-D grids.  On [0, n) the extended
+// synthesis equals the forward synthesis S, so per axis the folded synthesis is S + C, where C adds
+// at a position j the synthesis at every other image of j (nonzero only within L - 2 of an edge, or
+// everywhere on an axis shorter than L - 1: the shell).  On a 2-D grid (axis 1 = rows, axis 2 =
+// columns) A^T u = S1 S2 u + S1 (C2 u) + C1 ((S2 + C2) u): the forward up-level gives the first
+// term; two kernels add the others, times beta.  k_sym_shell_prep evaluates, per instance,
+//   Y = (S2 + C2) u  on the rows of u that the axis-1 images read (rows [0, rt) and [rb, l1)),
+//   W = C2 u         at the shell columns, on every row of u;
+// k_sym_shell then adds, at every shell position (j1, j2) once,
+//   beta * ( [j2 in shell] sum_k1 h1(j1, k1) W[k1][j2] + [j1 in shell] sum_{p1 != j1} sum_k1 h1(p1, k1) Y[k1][j2] ).
+// The synthesis at position p takes k = floor(p / 2) + i, i < L / 2, with filter index
+// L - 2 + (p & 1) - 2 i; a k outside [0, l) contributes nothing.
+struct SymShell {
+  const float* u;
+  float* out;
+  float* Y;                // rows of (S2 + C2) u, pitch n[1]
+  float* W;                // C2 u at the shell columns, pitch m2
+  int64_t bs_u, bs_out, bs_Y, bs_W;
+  int32_t su, so;          // axis-1 strides of u and out
+  int32_t n[2], l[2];      // axes 1 and 2: output (level j - 1) and input (level j) lengths
+  int32_t e0[2], e1[2];    // interior range [e0, e1) per axis: positions without another image
+  int32_t simple[2];       // axis at least L - 1 long: at most one image of each family
+  int32_t rt, rb, nY, m2;  // rows of u kept in Y: [0, rt) and [rb, l1); shell columns
+  int32_t per_prep, per_shell, slab0;  // items per instance
+  int32_t batch;           // instances of this launch (items below 2^31)
+  int32_t D;               // 1 or 2 (a 1-D grid has one row of weight 1 along axis 1)
+  int32_t ext;             // L - 2
+  float beta;
+};
+
+// One synthesis sum of the line `row` (length l) at extension position p.
+template <int L>
+DEVI float shell_taps(const float* row, int l, int p, int stride, const Filter& f) {
+  constexpr int H = L / 2;
+  const int kb = floor_div(p, 2);
+  const bool odd = p & 1;
+  float x[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) x[i] = gld(row + (int64_t)min(max(kb + i, 0), l - 1) * stride);
+  float acc = 0.f;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const int k = kb + i;
+    const float w = odd ? f.h[L - 1 - 2 * i] : f.h[L - 2 - 2 * i];
+    acc = fmaf(w, (k >= 0 && k < l) ? x[i] : 0.f, acc);
+  }
+  return acc;
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) k_sym_shell_prep(SymShell S, Filter f) {
+  const int lo2 = -S.ext, hi2 = 2 * S.l[1] - 1;
+  const int total = S.batch * S.per_prep, nYc = S.nY * S.n[1];
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const int inst = idx / S.per_prep;
+    int r = idx - inst * S.per_prep;
+    const float* u = S.u + inst * S.bs_u;
+    if (r < nYc) {  // Y: every image of column j2 (j2 itself included)
+      const int y = r / S.n[1], j2 = r - y * S.n[1];
+      const int k1 = y < S.rt ? y : S.rb + (y - S.rt);
+      const float* row = u + (int64_t)k1 * S.su;
+      float acc = 0.f;
+      visit_images(j2, S.n[1], lo2, hi2, S.simple[1], [&](int p2) { acc += shell_taps<L>(row, S.l[1], p2, 1, f); });
+      gst(S.Y + inst * S.bs_Y + r, acc);
+    } else {        // W: the images of shell column j2 other than j2
+      r -= nYc;
+      const int k1 = r / S.m2, e = r - k1 * S.m2;
+      const int j2 = e < S.e0[1] ? e : S.e1[1] + (e - S.e0[1]);
+      const float* row = u + (int64_t)k1 * S.su;
+      float acc = 0.f;
+      visit_images(j2, S.n[1], lo2, hi2, S.simple[1], [&](int p2) {
+        if (p2 != j2) acc += shell_taps<L>(row, S.l[1], p2, 1, f);
+      });
+      gst(S.W + inst * S.bs_W + r, acc);
+    }
+  }
+}
+
+template <int L, int D>
+__global__ void __launch_bounds__(256) k_sym_shell(SymShell S, Filter f) {
+  const int lo1 = -S.ext, hi1 = 2 * S.l[0] - 1;
+  const int total = S.batch * S.per_shell;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += gridDim.x * blockDim.x) {
+    const int inst = idx / S.per_shell;
+    int r = idx - inst * S.per_shell;
+    int j1, j2;
+    bool edge1, edge2;
+    if (r < S.slab0) {  // axis-1 coordinate in the shell
+      const int t1 = r / S.n[1];
+      j2 = r - t1 * S.n[1];
+      j1 = t1 < S.e0[0] ? t1 : S.e1[0] + (t1 - S.e0[0]);
+      edge1 = true;
+      edge2 = j2 < S.e0[1] || j2 >= S.e1[1];
+    } else {            // interior axis-1 coordinate, axis-2 coordinate in the shell
+      r -= S.slab0;
+      const int t1 = r / S.m2, t2 = r - t1 * S.m2;
+      j1 = S.e0[0] + t1;
+      j2 = t2 < S.e0[1] ? t2 : S.e1[1] + (t2 - S.e0[1]);
+      edge1 = false;
+      edge2 = true;
+    }
+    float* o = S.out + (int64_t)inst * S.bs_out + (int64_t)j1 * S.so + j2;
+    float corr = 0.f;
+    if (edge2) {  // S1 (C2 u) at column j2
+      const int e = j2 < S.e0[1] ? j2 : S.e0[1] + (j2 - S.e1[1]);
+      const float* col = S.W + inst * S.bs_W + e;
+      corr = D == 2 ? shell_taps<L>(col, S.l[0], j1, S.m2, f) : gld(col);
+    }
+    if (D == 2 && edge1) {  // C1 ((S2 + C2) u): the images of row j1 other than j1
+      const float* Yc = S.Y + inst * S.bs_Y + j2;
+      visit_images(j1, S.n[0], lo1, hi1, S.simple[0], [&](int p1) {
+        if (p1 == j1) return;
+        constexpr int H = L / 2;
+        const int kb = floor_div(p1, 2);
+        const bool odd = p1 & 1;
+        float x[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+          const int k = min(max(kb + i, 0), S.l[0] - 1);
+          const int y = k < S.rt ? k : (k >= S.rb ? S.rt + (k - S.rb) : 0);  // rows p1 reads are kept
+          x[i] = gld(Yc + (int64_t)y * S.n[1]);
+        }
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+          const int k = kb + i;
+          const float w = odd ? f.h[L - 1 - 2 * i] : f.h[L - 2 - 2 * i];
+          acc = fmaf(w, (k >= 0 && k < S.l[0]) ? x[i] : 0.f, acc);
+        }
+        corr += acc;
+      });
+    }
+    gst(o, fmaf(S.beta, corr, gld(o)));
+  }
+}
+
+hipError_t launch_sym_shell(int L, const SymShell& S, bool prep, unsigned grid, const Filter& f, hipStream_t s) {
+  const bool two = S.D == 2;
+  switch (L) {
+#define ES_SHELL_CASE(LL)                                                                   \
+  case LL:                                                                                  \
+    if (prep) hipLaunchKernelGGL((k_sym_shell_prep<LL>), dim3(grid), dim3(256), 0, s, S, f); \
+    else if (two) hipLaunchKernelGGL((k_sym_shell<LL, 2>), dim3(grid), dim3(256), 0, s, S, f); \
+    else hipLaunchKernelGGL((k_sym_shell<LL, 1>), dim3(grid), dim3(256), 0, s, S, f);       \
+    break;
+    ES_SHELL_CASE(2) ES_SHELL_CASE(4) ES_SHELL_CASE(6) ES_SHELL_CASE(8)
+    ES_SHELL_CASE(10) ES_SHELL_CASE(12) ES_SHELL_CASE(14) ES_SHELL_CASE(16)
+#undef ES_SHELL_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <int D, int L, bool ZX>
 hipError_t launch_sym_level(bool up, const SymTask& t, int64_t grid, const Filter& f, hipStream_t s) {
   if constexpr (D == 1) {
@@ -612,12 +765,80 @@ bool sym_filter(int L, Filter* f) {
 }
 
 struct SymLaunch {
-  int kind;  // 0 analysis level, 1 synthesis level, 2 fold (transposed operator)
+  int kind;  // 0 analysis level, 1 synthesis level, 2 fold, 3 boundary shell (transposed operator)
   bool zx;   // analysis with zero extension (S_a^T)
   SymTask t;
   SymFold fold;
+  SymShell shell;
   int64_t grid;
 };
+
+// Boundary shell of the transposed up-level j on 1-D and 2-D grids (see k_sym_shell): lengths,
+// interior ranges, kept rows and per-instance item counts; scratch = Y then W (floats).
+SymShell sym_shell(const SymGeo& g, int j, int64_t batch, const float* u, float* out, float beta, float* scratch) {
+  SymShell S{};
+  S.u = u;
+  S.out = out;
+  S.bs_u = g.stored(j);
+  S.bs_out = g.stored(j - 1);
+  S.su = g.pitch(j);
+  S.so = g.pitch(j - 1);
+  S.D = g.D;
+  S.ext = g.L - 2;
+  S.beta = beta;
+  const int H = g.L / 2;
+  for (int a = 0; a < 2; ++a) {
+    const int ax = a + 1;  // grid axes 1 and 2
+    S.n[a] = g.dims[j - 1][ax];
+    S.l[a] = g.dims[j][ax];
+    const bool present = ax >= 3 - g.D;
+    if (!present) {  // one position, no other image
+      S.e0[a] = 0;
+      S.e1[a] = 1;
+      S.simple[a] = 1;
+      continue;
+    }
+    const int n = S.n[a], l = S.l[a];
+    S.simple[a] = n >= g.L - 1;
+    if (S.simple[a]) {
+      // -1 - j lies in the extension for j <= L - 3, 2n - 1 - j for j >= 2n - 2l
+      S.e0[a] = g.L - 2;
+      S.e1[a] = std::max(S.e0[a], std::min(n, 2 * n - 2 * l));
+    } else {
+      S.e0[a] = S.e1[a] = 0;  // every position may have several images
+    }
+  }
+  if (g.D == 2) {
+    // rows of u the axis-1 images read: -(L-2) <= p1 <= -1 reads k1 <= L/2 - 2, n1 <= p1 reads
+    // k1 >= n1 / 2; a short axis keeps every row
+    const int l1 = S.l[0];
+    S.rt = S.simple[0] ? std::min(l1, H - 1) : l1;
+    S.rb = S.simple[0] ? std::max(S.rt, std::min(l1, S.n[0] / 2)) : l1;
+    S.nY = S.rt + (l1 - S.rb);
+  } else {
+    S.rt = S.rb = 1;
+    S.nY = 0;
+  }
+  S.m2 = S.n[1] - (S.e1[1] - S.e0[1]);
+  const int in1 = S.e1[0] - S.e0[0];
+  S.slab0 = (S.n[0] - in1) * S.n[1];
+  S.per_shell = S.slab0 + in1 * S.m2;
+  S.per_prep = S.nY * S.n[1] + S.l[0] * S.m2;
+  S.bs_Y = (int64_t)S.nY * S.n[1];
+  S.bs_W = (int64_t)S.l[0] * S.m2;
+  if (scratch) {
+    S.Y = scratch;
+    S.W = scratch + align64f(batch * S.bs_Y);
+  }
+  S.batch = (int32_t)std::min<int64_t>(batch, 0x7fffffff);
+  return S;
+}
+
+// Scratch floats of the shell of level j (0 where the level has no shell pass).
+int64_t sym_shell_floats(const SymGeo& g, int j, int64_t batch) {
+  const SymShell S = sym_shell(g, j, batch, nullptr, nullptr, 0.f, nullptr);
+  return align64f(batch * S.bs_Y) + align64f(batch * S.bs_W);
+}
 
 // Sets the tile counts of `t` for output dims `no` and tile `tile`; returns the grid.
 int64_t sym_tiling(SymTask& t, const int tile[3], int64_t batch) {
@@ -644,11 +865,17 @@ ExtDims ext_dims(const SymGeo& g, int i) {
 }
 
 // Floats of workspace: a_1 .. a_{m-1} of every instance (each level 256-byte aligned), and for
-// the transposed operator the extended synthesis of the finest level after them.
+// the transposed operator after them the extended synthesis of the finest level (3-D grids) or the
+// boundary-shell scratch of the largest level (1-D and 2-D grids).
 int64_t sym_ws_floats(const SymGeo& g, int64_t batch, bool transpose) {
   int64_t tot = 0;
   for (int i = 1; i < g.m; ++i) tot += align64f(batch * g.stored(i));
-  if (transpose && g.m >= 2) tot += align64f(batch * ext_dims(g, 1).stored());
+  if (transpose && g.m >= 2 && g.D == 3) tot += align64f(batch * ext_dims(g, 1).stored());
+  if (transpose && g.D <= 2) {  // the boundary-shell scratch, one level at a time
+    int64_t sh = 0;
+    for (int j = 1; j < g.m; ++j) sh = std::max(sh, sym_shell_floats(g, j, batch));
+    tot += sh;
+  }
   return tot;
 }
 
@@ -668,7 +895,7 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
     lev[i] = ws + off;
     off += align64f(batch * g.stored(i));
   }
-  float* vext = ws + off;  // transposed operator only
+  float* vext = ws + off;  // transposed operator only: extended level (3-D) or shell scratch
   auto strides = [&](int i, int32_t st[2]) {
     st[1] = g.pitch(i);
     st[0] = g.dims[i][1] * g.pitch(i);
@@ -720,7 +947,35 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
       out->push_back(l);
       continue;
     }
-    // transposed: v = beta * (zero-padded synthesis of u_j onto the extension), then
+    if (g.D <= 2) {
+      // transposed, 1-D and 2-D: the forward up-level (u_{j-1} = c_{j-1} b_{j-1} + beta S u_j on
+      // [0, n)), then the boundary shell adds beta times the extension images
+      SymLaunch l{};
+      l.kind = 1;
+      l.t.in = lev[j];
+      l.t.same = lev[j - 1];
+      l.t.out = dst;
+      l.t.bs_in = g.stored(j);
+      l.t.bs_same = g.stored(j - 1);
+      l.t.bs_out = g.stored(j - 1);
+      l.t.alpha = (float)alpha;
+      l.t.beta = (float)beta;
+      for (int a = 0; a < 3; ++a) {
+        l.t.ni[a] = g.dims[j][a];
+        l.t.no[a] = g.dims[j - 1][a];
+      }
+      strides(j, l.t.si);
+      strides(j - 1, l.t.so);
+      l.grid = sym_tiling(l.t, tl.u, batch);
+      out->push_back(l);
+      SymLaunch sl{};
+      sl.kind = 3;
+      sl.shell = sym_shell(g, j, batch, lev[j], dst, (float)beta, vext);
+      sl.grid = 0;  // sized at the launch
+      out->push_back(sl);
+      continue;
+    }
+    // transposed, 3-D: v = beta * (zero-padded synthesis of u_j onto the extension), then
     // u_{j-1} = c_{j-1} b_{j-1} + fold(v)
     const ExtDims E = ext_dims(g, j);
     SymLaunch l{};
@@ -779,10 +1034,12 @@ es_status sym_run(int ndim, const int64_t* shape, int64_t batch, int order, int 
   if (batch == 0) return ES_OK;
   const int64_t N = g.size(0);
   if (N > INT64_MAX / 4 / batch) return sym_einval("batch * size overflows");
-  if (transpose && g.m >= 2 && ext_dims(g, 1).stored() > 0x7fffffffll)
+  if (transpose && g.D == 3 && g.m >= 2 && ext_dims(g, 1).stored() > 0x7fffffffll)
     return sym_einval("the extended level holds more than 2^31-1 elements per instance");
-  if (transpose && batch * (N / g.dims[0][2]) > 0x7fffffffll)
+  if (transpose && g.D == 3 && batch * (N / g.dims[0][2]) > 0x7fffffffll)
     return sym_einval("the transposed operator handles at most 2^31-1 rows per call");
+  if (transpose && g.D <= 2 && N > 0x3fffffffll)
+    return sym_einval("the transposed operator handles at most 2^30 samples per instance on 1-D and 2-D grids");
   if (!x || !y) return sym_einval("input and output pointers must be non-NULL");
   if (((uintptr_t)x & 15) || ((uintptr_t)y & 15)) return sym_einval("input and output must be 16-byte aligned");
   const size_t io = (size_t)(batch * N) * sizeof(float);
@@ -819,6 +1076,26 @@ es_status sym_run(int ndim, const int64_t* shape, int64_t batch, int order, int 
       const dim3 grid(1, (unsigned)std::min<int64_t>(rows, 65535));
       hipLaunchKernelGGL(k_sym_fold, grid, dim3(256), 0, hs, l.fold);
       he = hipGetLastError();
+    } else if (l.kind == 3) {
+      // preparation, then the shell, per chunk of instances with fewer than 2^31 items (32-bit
+      // indices in the kernels; each item count per instance is below 2^31 by the size check)
+      he = hipSuccess;
+      for (int pass = 0; pass < 2 && he == hipSuccess; ++pass) {
+        const int64_t per = pass == 0 ? l.shell.per_prep : l.shell.per_shell;
+        if (per == 0) continue;
+        const int64_t chunk = std::max<int64_t>(1, 0x7fffffffll / per);
+        for (int64_t i0 = 0; i0 < batch && he == hipSuccess; i0 += chunk) {
+          SymShell S = l.shell;
+          const int64_t nb = std::min(chunk, batch - i0);
+          S.u += i0 * S.bs_u;
+          S.out += i0 * S.bs_out;
+          S.Y += i0 * S.bs_Y;
+          S.W += i0 * S.bs_W;
+          S.batch = (int32_t)nb;
+          const unsigned grid = (unsigned)std::min<int64_t>((nb * per + 255) / 256, 16384);
+          he = launch_sym_shell(g.L, S, pass == 0, grid, f, hs);
+        }
+      }
     } else {
       he = launch_sym(g.D, g.L, l.kind == 1, l.zx, l.t, l.grid, f, hs);
     }

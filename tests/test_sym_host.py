@@ -91,15 +91,46 @@ def test_batch_zero_is_a_noop(lib):
     assert _call(lib, batch=0, x=0, y=0, ws=0) == _lib.ES_OK
 
 
+def _shell_scratch_floats(shape, batch, order, levels):
+    """Largest boundary-shell scratch over the up-levels of a 1-D or 2-D transposed operator: the
+    rows of u that the axis-1 images read (all columns), then the shell columns of every row."""
+    L, H = 2 * order, order
+    dims = [tuple(shape)]
+    for _ in range(levels):
+        dims.append(tuple(symdwt.sym_length(v, L) for v in dims[-1]))
+    dims = [((1,) + d) if len(shape) == 1 else d for d in dims]
+    best = 0
+    for j in range(1, levels):
+        (n1, n2), (l1, l2) = dims[j - 1], dims[j]
+        if n2 >= L - 1:
+            e0, e1 = L - 2, max(L - 2, min(n2, 2 * n2 - 2 * l2))
+        else:
+            e0 = e1 = 0
+        m2 = n2 - (e1 - e0)
+        if len(shape) == 2:
+            rt = min(l1, H - 1) if n1 >= L - 1 else l1
+            rb = max(rt, min(l1, n1 // 2)) if n1 >= L - 1 else l1
+            ny = rt + (l1 - rb)
+        else:
+            ny = 0
+        a64 = lambda v: (v + 63) // 64 * 64
+        best = max(best, a64(batch * ny * n2) + a64(batch * l1 * m2))
+    return best
+
+
 @pytest.mark.parametrize("shape,batch,order,levels", [((1024, 1024), 2, 8, 7), ((37, 53), 3, 2, 4), ((9, 10, 11), 2, 4, 3),
                                                       ((5,), 7, 8, 6), ((64,), 1, 1, 1)])
 def test_transpose_workspace(lib, shape, batch, order, levels):
-    """The level arrays, then the extended synthesis of the finest level (every axis over
-    -(L-2) .. 2 l_1 - 1, rows padded to a multiple of 4 floats)."""
+    """The level arrays; on 3-D grids then the extended synthesis of the finest level (every axis
+    over -(L-2) .. 2 l_1 - 1, rows padded to a multiple of 4 floats), on 1-D and 2-D grids the
+    boundary-shell scratch of the largest level."""
     fwd = lib.es_sym_workspace_bytes(len(shape), _lib.shape_arg(shape), batch, order, levels)
     tr = lib.es_sym_transpose_workspace_bytes(len(shape), _lib.shape_arg(shape), batch, order, levels)
     if levels < 2:
         assert tr == fwd == 0
+        return
+    if len(shape) < 3:
+        assert tr == fwd + 4 * _shell_scratch_floats(shape, batch, order, levels)
         return
     ext = [2 * symdwt.sym_length(v, 2 * order) + 2 * order - 2 for v in shape]
     stored = int(np.prod(ext[:-1])) * ((ext[-1] + 3) // 4 * 4)
