@@ -148,27 +148,23 @@ __global__ void __launch_bounds__(kCgThreads) k_cg_apply(int64_t n, int per, flo
   if (threadIdx.x == 0) gst(part + blockIdx.x, t);
 }
 
-// x += a d, r -= a ad; partial r . r
+// r -= a ad; partial r . r  (x += a d waits for the direction pass, which reads d anyway)
 __global__ void __launch_bounds__(kCgThreads) k_cg_step(int64_t n, int per, const CgScal* __restrict__ sc,
-                                                        float* __restrict__ x, float* __restrict__ r,
-                                                        const float* __restrict__ d, const float* __restrict__ ad,
+                                                        float* __restrict__ r, const float* __restrict__ ad,
                                                         float* __restrict__ part) {
   const Span sp = span_of(n, per);
   const float a = sc[sp.inst].a;
   KSum acc;
   for_chunk(sp, n, [&](int64_t i, int w) {
     if (w == 4) {
-      const float4 xv = gld4(x + i), rv = gld4(r + i), dv = gld4(d + i), g = gld4(ad + i);
-      const float4 xn = make_float4(fmaf(a, dv.x, xv.x), fmaf(a, dv.y, xv.y), fmaf(a, dv.z, xv.z), fmaf(a, dv.w, xv.w));
+      const float4 rv = gld4(r + i), g = gld4(ad + i);
       const float4 rn = make_float4(fmaf(-a, g.x, rv.x), fmaf(-a, g.y, rv.y), fmaf(-a, g.z, rv.z), fmaf(-a, g.w, rv.w));
-      gst4(x + i, xn);
       gst4(r + i, rn);
       acc.add(rn.x * rn.x);
       acc.add(rn.y * rn.y);
       acc.add(rn.z * rn.z);
       acc.add(rn.w * rn.w);
     } else {
-      gst(x + i, fmaf(a, gld(d + i), gld(x + i)));
       const float rn = fmaf(-a, gld(ad + i), gld(r + i));
       gst(r + i, rn);
       acc.add(rn * rn);
@@ -178,18 +174,22 @@ __global__ void __launch_bounds__(kCgThreads) k_cg_step(int64_t n, int per, cons
   if (threadIdx.x == 0) gst(part + blockIdx.x, t);
 }
 
-// d = beta d + z
+// x += a d (this iteration's step), then d = beta d + z
 __global__ void __launch_bounds__(kCgThreads) k_cg_dir(int64_t n, int per, const CgScal* __restrict__ sc,
-                                                       float* __restrict__ d, const float* __restrict__ z) {
+                                                       float* __restrict__ x, float* __restrict__ d,
+                                                       const float* __restrict__ z) {
   const Span sp = span_of(n, per);
-  const float beta = sc[sp.inst].beta;
+  const float a = sc[sp.inst].a, beta = sc[sp.inst].beta;
   for_chunk(sp, n, [&](int64_t i, int w) {
     if (w == 4) {
-      const float4 dv = gld4(d + i), zv = gld4(z + i);
+      const float4 xv = gld4(x + i), dv = gld4(d + i), zv = gld4(z + i);
+      gst4(x + i, make_float4(fmaf(a, dv.x, xv.x), fmaf(a, dv.y, xv.y), fmaf(a, dv.z, xv.z), fmaf(a, dv.w, xv.w)));
       gst4(d + i, make_float4(fmaf(beta, dv.x, zv.x), fmaf(beta, dv.y, zv.y), fmaf(beta, dv.z, zv.z),
                               fmaf(beta, dv.w, zv.w)));
     } else {
-      gst(d + i, fmaf(beta, gld(d + i), gld(z + i)));
+      const float dv = gld(d + i);
+      gst(x + i, fmaf(a, dv, gld(x + i)));
+      gst(d + i, fmaf(beta, dv, gld(z + i)));
     }
   });
 }
@@ -364,8 +364,8 @@ es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int ord
       st = ok("CG operator update launch");
     }
     if (st != ES_OK || (st = final_(F_A, np)) != ES_OK) return st;
-    // x += a d, r -= a ad, rel = ||r|| / ||b||
-    hipLaunchKernelGGL(k_cg_step, grid, blk, 0, hs, n, (int)per, sc, x, r, d, ad, part);
+    // r -= a ad, rel = ||r|| / ||b||
+    hipLaunchKernelGGL(k_cg_step, grid, blk, 0, hs, n, (int)per, sc, r, ad, part);
     if ((st = ok("CG step launch")) != ES_OK || (st = final_(F_RR, per)) != ES_OK) return st;
     // z = P r, beta = (r . z) / rz, d = z + beta d
     np = per;
@@ -377,7 +377,8 @@ es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int ord
       st = ok("CG dot launch");
     }
     if (st != ES_OK || (st = final_(F_BETA, np)) != ES_OK) return st;
-    hipLaunchKernelGGL(k_cg_dir, grid, blk, 0, hs, n, (int)per, sc, d, z);
+    // x += a d, d = z + beta d
+    hipLaunchKernelGGL(k_cg_dir, grid, blk, 0, hs, n, (int)per, sc, x, d, z);
     if ((st = ok("CG direction launch")) != ES_OK) return st;
     ++it;
     if (it % check_every == 0 || it == max_iter) {
