@@ -44,8 +44,10 @@ def template_name(launch_name):
     kname = {"lp_down": "k_lp_down", "lp_up": "k_lp_up", "fb_down": "k_fb_down", "fb_up": "k_fb_up"}.get(kind)
     if kind.startswith("lp_up2") or launch_name.startswith("lp_up2"):
         return f"void es::k_lp_up2<{taps}, {tile[1]}, {tile[2]}, 256, {vec}>(es::TaskArgs, es::Filter)"
-    if len(parts) > 2 and parts[2] == "s" and kind == "lp_down":  # 2-D, streamed along axis 1
+    if len(parts) > 2 and parts[2] == "s" and kind == "lp_down" and d == 2:  # 2-D, streamed along axis 1
         return f"void es::k_lp_down_s<{taps}, {tile[1]}, {tile[2]}, 256, {vec}>(es::TaskArgs, es::Filter)"
+    if len(parts) > 2 and parts[2] == "s" and kind in ("lp_down", "lp_up"):  # 3-D low-pass, streamed along axis 0
+        return f"void es::{kname}_s3<{taps}, {tile[0]}, {tile[1]}, {tile[2]}, 256, {vec}>(es::TaskArgs, es::Filter)"
     if len(parts) > 2 and parts[2] == "s":  # 3-D levels streamed along axis 0 (no dims argument)
         return f"void es::{kname}_s<{taps}, {tile[0]}, {tile[1]}, {tile[2]}, 256, {vec}>(es::TaskArgs, es::Filter)"
     return f"void es::{kname}<{d}, {taps}, {tile[0]}, {tile[1]}, {tile[2]}, 256, {vec}>(es::TaskArgs, es::Filter)"

@@ -312,7 +312,7 @@ int pick_variant(int kind, const Geo& g, int level, int64_t batch) {
   const int64_t wg0 = (int64_t)t.tiles_per_inst * batch;
   // large levels: wide tiles for analysis, medium tiles for the synthesis kernels (measured
   // fastest on 64 x 1024^2 db8); small levels: narrow tiles (more work-groups)
-  const int big = (kind == K_LP_UP || kind == K_FB_UP) ? 2 : 0;
+  const int big = (kind == K_LP_UP || kind == K_FB_UP || kind == K_LP_UP_S) ? 2 : 0;
   if (w0 <= 1.25 && wg0 >= 1024) return big;
   if (w0 <= w1 && wg0 >= 2048) return big;
   return 1;
@@ -337,20 +337,24 @@ void strides_of(const int dims[3], int32_t st[2]) {
   st[1] = dims[2];
 }
 
-// 3-D full-bank levels and 2-D low-pass analysis levels have two kernel families: plain tiles,
-// and tiles streamed along the slowest axis (no halo re-reads along it, but one work-group walks
-// its run in sequence).  Streaming wins when the level has enough tiles to fill the chip.
+// 3-D levels (full-bank and low-pass) and 2-D low-pass analysis levels have two kernel families:
+// plain tiles, and tiles streamed along the slowest axis (no halo re-reads along it, but one
+// work-group walks its run in sequence).  Streaming wins when the level has enough tiles to fill
+// the chip.
 bool has_family(int kind, int D) {
-  return (D == 3 && (kind == K_FB_DOWN || kind == K_FB_UP || kind == K_FB_DOWN_S || kind == K_FB_UP_S)) ||
+  return (D == 3 && (kind == K_FB_DOWN || kind == K_FB_UP || kind == K_FB_DOWN_S || kind == K_FB_UP_S ||
+                     kind == K_LP_DOWN || kind == K_LP_DOWN_S || kind == K_LP_UP || kind == K_LP_UP_S)) ||
          (D == 2 && (kind == K_LP_DOWN || kind == K_LP_DOWN_S));
 }
 bool is_family(const Launch& l) { return !l.is_tail && has_family(l.kind, l.D); }
 int streamed_kind(int kind) {
   if (kind == K_LP_DOWN || kind == K_LP_DOWN_S) return K_LP_DOWN_S;
+  if (kind == K_LP_UP || kind == K_LP_UP_S) return K_LP_UP_S;
   return kind_is_analysis(kind) ? K_FB_DOWN_S : K_FB_UP_S;
 }
 int tiled_kind(int kind) {
   if (kind == K_LP_DOWN || kind == K_LP_DOWN_S) return K_LP_DOWN;
+  if (kind == K_LP_UP || kind == K_LP_UP_S) return K_LP_UP;
   return kind_is_analysis(kind) ? K_FB_DOWN : K_FB_UP;
 }
 
@@ -805,6 +809,7 @@ void launch_accesses(const Launch& l, std::vector<Access>* acc) {
       add(t.out0, t.bs_out0, dense_span(h), true);
       break;
     case K_LP_UP:
+    case K_LP_UP_S:
       add(t.in0, t.bs_in0, dense_span(h), false);
       add(t.in1, t.bs_in1, dense_span(t.b), false);
       add(t.out0, t.bs_out0, dense_span(t.b), true);
@@ -2551,7 +2556,8 @@ es_status es_schedule_describe(int op, int ndim, const int64_t* shape, int64_t b
   if (st != ES_OK) return st;
   if (index < 0 || index >= (int32_t)sc.launches.size()) return fail(ES_EINVAL, "step index out of range");
   const Launch& l = sc.launches[index];
-  static const char* kinds[8] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2", "fb_down_s", "fb_up_s", "lp_down_s"};
+  static const char* kinds[9] = {"lp_down", "lp_up", "fb_down", "fb_up", "lp_up2", "fb_down_s", "fb_up_s", "lp_down_s",
+                                 "lp_up_s"};
   static const char* tails[4] = {"tail_lp_off", "tail_fb_analysis", "tail_fb_synthesis", "lp_coarse"};
   char buf[128];
   int lev = 0;

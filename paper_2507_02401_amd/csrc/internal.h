@@ -102,7 +102,8 @@ enum KernelKind {
   K_LP_UP2 = 4,
   K_FB_DOWN_S = 5,  // 3-D full analysis level, streamed along axis 0 (same Task fields as FB_DOWN)
   K_FB_UP_S = 6,    // 3-D full synthesis level, streamed along axis 0 (same Task fields as FB_UP)
-  K_LP_DOWN_S = 7   // 2-D low-pass analysis level, streamed along axis 1 (same Task fields as LP_DOWN)
+  K_LP_DOWN_S = 7,  // low-pass analysis level, streamed along axis 1 (2-D) or axis 0 (3-D) (same Task fields as LP_DOWN)
+  K_LP_UP_S = 8     // 3-D low-pass synthesis level, streamed along axis 0 (same Task fields as LP_UP)
 };
 inline bool kind_is_analysis(int k) {
   return k == K_LP_DOWN || k == K_FB_DOWN || k == K_FB_DOWN_S || k == K_LP_DOWN_S;

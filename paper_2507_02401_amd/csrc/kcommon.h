@@ -283,10 +283,10 @@ DEVI void row_pass_inplace(float* s_in, const Filter& f) {
 }
 
 // Contiguous-dim analysis of NROW staged rows of `src` into `dst`, as rows of 2 T2 floats
-// [lo T2 | hi T2].  Each task is P consecutive outputs of one row, the taps summed in the order
-// of row_pass_inplace.  No barrier: the caller orders the reads of `src` and the writes of `dst`
-// against the other threads.
-template <int L, int P, int NROW, int T2, int I2P, int NT>
+// [lo T2 | hi T2] (FB) or of T2 low-pass floats.  Each task is P consecutive outputs of one row,
+// the taps summed in the order of row_pass_inplace.  No barrier: the caller orders the reads of
+// `src` and the writes of `dst` against the other threads.
+template <int L, int P, int NROW, int T2, int I2P, int NT, bool FB = true>
 DEVI void row_pass_to(const float* src, float* dst, const Filter& f) {
   constexpr int NCH = T2 / P;
   constexpr int NTASK = NROW * NCH;
@@ -309,14 +309,14 @@ DEVI void row_pass_to(const float* src, float* dst, const Filter& f) {
 #pragma unroll
       for (int t = 0; t < L; ++t) {
         a = fmaf(f.h[t], win[2 * q + t], a);
-        d = fmaf(f.g[t], win[2 * q + t], d);
+        if (FB) d = fmaf(f.g[t], win[2 * q + t], d);
       }
       lo[q] = a;
       hi[q] = d;
     }
-    float4* o = reinterpret_cast<float4*>(dst + l * 2 * T2 + P * ch);
+    float4* o = reinterpret_cast<float4*>(dst + l * (FB ? 2 * T2 : T2) + P * ch);
     o[0] = make_float4(lo[0], lo[1], lo[2], lo[3]);
-    o[T2 / 4] = make_float4(hi[0], hi[1], hi[2], hi[3]);
+    if (FB) o[T2 / 4] = make_float4(hi[0], hi[1], hi[2], hi[3]);
   }
 }
 

@@ -552,6 +552,295 @@ __global__ void __launch_bounds__(NT) k_fb_up_s(TaskArgs args, Filter f) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Streamed 3-D low-pass levels (projection form).  A work-group owns an in-plane tile and a run
+// of R output slices along axis 0, as the streamed full-bank kernels do, but keeps the axis order
+// of the plain 3-D low-pass tiles (axis 2, then 0, then 1): every staged slice is filtered along
+// axis 2 once; the axis-0 filter is a running sum each thread keeps in registers for its
+// positions of the axis-2-filtered plane (halo rows of axis 1 included); a completed output slice
+// goes through LDS for the axis-1 filter.  Per output the taps are summed in the plain tiles'
+// order, so both families give identical bits.
+
+// LP_DOWN_S (3-D): a_out = A a_in; in-plane half-res tile T1 x T2, R output slices.  Iteration p
+// stages input slices 2p and 2p+1 of the run; output slice k takes input slices 2k .. 2k+L-1.
+template <int L, int R, int T1, int T2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_lp_down_s3(TaskArgs args, Filter f) {
+  constexpr int H = L / 2;
+  constexpr int I1 = 2 * T1 + L - 2, I2 = 2 * T2 + L - 2;
+  constexpr int I2P = (I2 + 3) & ~3, NV = I2P / 4;
+  constexpr int NPOS = I1 * T2;             // positions of one axis-2-filtered slice
+  constexpr int QA = (NPOS + NT - 1) / NT;  // of them per thread
+  constexpr int NP = R + H - 1;             // iterations
+  constexpr int P1 = 4;
+  static_assert(T1 % P1 == 0 && T2 % 4 == 0, "tile shape");
+  __shared__ __attribute__((aligned(16))) float s_in[2 * I1 * I2P];
+  __shared__ float s_r[2 * NPOS];  // the pair's slices filtered along axis 2
+  __shared__ float s_b[NPOS];      // a completed output slice (axes 2 and 0 done)
+  __shared__ int s_row[I1];
+  __shared__ int s_col[NV];
+
+  const int wg = logical_wg(args.total_wg, args.reverse);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ src = t.in0 + tl.inst * t.bs_in0;
+  float* __restrict__ dst = t.out0 + tl.inst * t.bs_out0;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int n0o = b0 >> 1, n1o = b1 >> 1, n2o = b2 >> 1;
+  const int k0 = R * tl.c0, o1 = 2 * T1 * tl.c1, o2 = 2 * T2 * tl.c2;
+
+  for (int i = threadIdx.x; i < I1; i += NT) s_row[i] = pmod(o1 + i, b1) * t.st_in0[1];
+  for (int i = threadIdx.x; i < NV; i += NT) s_col[i] = VEC ? pmod(o2 + 4 * i, b2) : o2 + 4 * i;
+  __syncthreads();
+
+  // vector path: a pair's 16-byte loads are issued one iteration before it is staged; each
+  // thread's load offsets within a slice are computed once (LDS slot = load index)
+  constexpr int NLD = 2 * I1 * NV, ITL = (NLD + NT - 1) / NT;
+  static_assert(ITL <= 32, "one bit per load in the mask");
+  float4 pf[VEC ? ITL : 1];
+  int loff[VEC ? ITL : 1];
+  unsigned lsec = 0;  // bit it: load it reads the second slice of the pair
+  if constexpr (VEC) {
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
+      const int e = q >= I1 * NV, r = q - e * I1 * NV;
+      loff[it] = s_row[r / NV] + s_col[r % NV];
+      lsec |= unsigned(e) << it;
+    }
+  }
+  auto load_pair = [&](int p) {
+    const float* sl0 = src + pmod(2 * (k0 + p), b0) * t.st_in0[0];
+    const float* sl1 = src + pmod(2 * (k0 + p) + 1, b0) * t.st_in0[0];
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) pf[it] = gld4(((lsec >> it) & 1 ? sl1 : sl0) + loff[it]);
+  };
+  if constexpr (VEC) load_pair(0);
+
+  float acc[H][QA];
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+#pragma unroll
+    for (int u = 0; u < QA; ++u) acc[j][u] = 0.f;
+
+  for (int p = 0; p < NP; ++p) {
+    if constexpr (VEC) {
+      float4* d4 = reinterpret_cast<float4*>(s_in);
+#pragma unroll
+      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
+      __syncthreads();
+      if (p + 1 < NP) load_pair(p + 1);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        stage_rows<NT, I1, NV, false>(src + pmod(2 * (k0 + p) + e, b0) * t.st_in0[0], s_row, s_col,
+                                      s_in + e * I1 * I2P, I2P, b2);
+      __syncthreads();
+    }
+    row_pass_to<L, 4, 2 * I1, T2, I2P, NT, false>(s_in, s_r, f);  // rows (e, i1) -> T2
+    __syncthreads();
+    // axis 0: output p - j takes taps 2j (slice 2p) and 2j + 1 (slice 2p + 1)
+#pragma unroll
+    for (int u = 0; u < QA; ++u) {
+      const int q = threadIdx.x + u * NT;
+      if (NPOS % NT == 0 || q < NPOS) {
+        const float x0 = s_r[q], x1 = s_r[NPOS + q];
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+          acc[j][u] = fmaf(f.h[2 * j], x0, acc[j][u]);
+          acc[j][u] = fmaf(f.h[2 * j + 1], x1, acc[j][u]);
+        }
+      }
+    }
+    const int g0 = k0 + p - (H - 1);  // output slice completed by this iteration
+    if (p >= H - 1 && g0 < n0o) {
+#pragma unroll
+      for (int u = 0; u < QA; ++u) {
+        const int q = threadIdx.x + u * NT;
+        if (NPOS % NT == 0 || q < NPOS) s_b[q] = acc[H - 1][u];
+      }
+      __syncthreads();
+      // axis 1: (I1, T2) -> (T1, T2), lines are columns
+      analysis_pass<L, P1, false, true, NT>(
+          T2, T1 / P1, f,
+          [&](int c, int j0, float* w) {
+#pragma unroll
+            for (int j = 0; j < 2 * P1 + L - 2; ++j) w[j] = s_b[(j0 + j) * T2 + c];
+          },
+          [&](int c, int k, float lo, float) {
+            const int g1 = T1 * tl.c1 + k, g2 = T2 * tl.c2 + c;
+            if (g1 < n1o && g2 < n2o) gst(dst + (g0 * n1o + g1) * n2o + g2, lo);
+          });
+    }
+#pragma unroll
+    for (int j = H - 1; j > 0; --j)
+#pragma unroll
+      for (int u = 0; u < QA; ++u) acc[j][u] = acc[j - 1][u];
+#pragma unroll
+    for (int u = 0; u < QA; ++u) acc[0][u] = 0.f;
+  }
+}
+
+// LP_UP_S (3-D): out = alpha * same + beta * A^T z; full-res in-plane tile U1 x U2, R output
+// slices (R even).  Output pair Q (full-res slices 2Q, 2Q+1) takes half-res slices Q-(H-1) .. Q;
+// iteration p stages half-res slices 2p, 2p+1 of the run, slice r adds to pairs r .. r+H-1 and
+// pair r is complete once slice r is in.
+template <int L, int R, int U1, int U2, int NT, bool VEC>
+__global__ void __launch_bounds__(NT) k_lp_up_s3(TaskArgs args, Filter f) {
+  constexpr int H = L / 2;
+  constexpr int J1 = U1 / 2 + H - 1, J2 = U2 / 2 + H - 1;
+  constexpr int OFF = (4 - ((H - 1) & 3)) & 3;
+  constexpr int J2P = (J2 + OFF + 3) & ~3, NV = J2P / 4;
+  constexpr int NPOS = J1 * U2;             // positions of one axis-2-synthesised slice
+  constexpr int QA = (NPOS + NT - 1) / NT;  // of them per thread
+  constexpr int NS = R / 2 + H - 1;         // half-res slices the run needs
+  constexpr int NP = (NS + 1) / 2;          // iterations
+  constexpr int P2 = 4, P1 = U1 / 2 % 4 == 0 ? 4 : 2;
+  static_assert(R % 2 == 0 && U2 % 8 == 0 && (U1 / 2) % P1 == 0, "tile shape");
+  __shared__ __attribute__((aligned(16))) float s_in[2 * J1 * J2P];
+  __shared__ float s_a[2 * NPOS];     // the pair's slices synthesised along axis 2
+  __shared__ float s_b[2][2 * NPOS];  // up to two completed output pairs: planes 2Q, 2Q+1
+  __shared__ int s_row[J1];
+  __shared__ int s_col[NV];
+
+  const int wg = logical_wg(args.total_wg, args.reverse);
+  if (wg < 0) return;
+  const Task t = pick_task<Task>(args, wg);
+  const Tile tl = decode_tile(t, wg);
+  const float* __restrict__ z = t.in0 + tl.inst * t.bs_in0;
+  const float* same = t.in1 + tl.inst * t.bs_in1;  // may alias out (in-place z over a)
+  float* out = t.out0 + tl.inst * t.bs_out0;
+  const int b0 = t.b[0], b1 = t.b[1], b2 = t.b[2];
+  const int h0 = b0 >> 1, h1 = b1 >> 1, h2 = b2 >> 1;  // z dims
+  const int q0 = tl.c0 * (R / 2);                      // first output pair (half-res index)
+  const int r1 = tl.c1 * (U1 / 2) - (H - 1), r2 = tl.c2 * (U2 / 2) - (H - 1) - OFF;
+  const float alpha = t.alpha, beta = t.beta;
+
+  for (int i = threadIdx.x; i < J1; i += NT) s_row[i] = pmod(r1 + i, h1) * h2;
+  for (int i = threadIdx.x; i < NV; i += NT) s_col[i] = VEC ? pmod(r2 + 4 * i, h2) : r2 + 4 * i;
+  __syncthreads();
+
+  constexpr int NLD = 2 * J1 * NV, ITL = (NLD + NT - 1) / NT;
+  static_assert(ITL <= 32, "one bit per load in the mask");
+  float4 pf[VEC ? ITL : 1];
+  int loff[VEC ? ITL : 1];
+  unsigned lsec = 0;  // bit it: load it reads the second slice of the pair
+  if constexpr (VEC) {
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) {
+      const int q = min(int(threadIdx.x) + it * NT, NLD - 1);
+      const int e = q >= J1 * NV, r = q - e * J1 * NV;
+      loff[it] = s_row[r / NV] + s_col[r % NV];
+      lsec |= unsigned(e) << it;
+    }
+  }
+  const int slice = h1 * h2;
+  auto load_pair = [&](int p) {
+    const float* sl0 = z + pmod(q0 - (H - 1) + 2 * p, h0) * slice;
+    const float* sl1 = z + pmod(q0 - (H - 1) + 2 * p + 1, h0) * slice;
+#pragma unroll
+    for (int it = 0; it < ITL; ++it) pf[it] = gld4(((lsec >> it) & 1 ? sl1 : sl0) + loff[it]);
+  };
+  if constexpr (VEC) load_pair(0);
+
+  float ac0[H][QA], ac1[H][QA];  // pair r + j: full-res slices 2(r+j) and 2(r+j)+1
+#pragma unroll
+  for (int j = 0; j < H; ++j)
+#pragma unroll
+    for (int u = 0; u < QA; ++u) ac0[j][u] = ac1[j][u] = 0.f;
+
+  for (int p = 0; p < NP; ++p) {
+    if constexpr (VEC) {
+      float4* d4 = reinterpret_cast<float4*>(s_in);
+#pragma unroll
+      for (int it = 0; it < ITL; ++it) d4[min(int(threadIdx.x) + it * NT, NLD - 1)] = pf[it];
+      __syncthreads();
+      if (p + 1 < NP) load_pair(p + 1);
+    } else {
+#pragma unroll
+      for (int e = 0; e < 2; ++e)
+        stage_rows<NT, J1, NV, false>(z + pmod(q0 - (H - 1) + 2 * p + e, h0) * slice, s_row, s_col,
+                                      s_in + e * J1 * J2P, J2P, h2);
+      __syncthreads();
+    }
+    // axis 2: rows (e, j1) -> U2 full-res values
+    synthesis_pass<L, P2, false, false, NT>(
+        2 * J1, U2 / 2 / P2, f,
+        [&](int l, int j0, float* lo, float*) {
+          const float* ptr = s_in + l * J2P + OFF + j0;
+#pragma unroll
+          for (int j = 0; j < P2 + H - 1; ++j) lo[j] = ptr[j];
+        },
+        [&](int l, int pp, float e0, float e1) {
+          s_a[l * U2 + pp] = e0;
+          s_a[l * U2 + pp + 1] = e1;
+        });
+    __syncthreads();
+    // axis 0: slice 2p + e adds to pairs (2p + e) - (H-1) + j, oldest slice first
+    int ncomp = 0, gq0 = 0, gq1 = 0;  // completed pairs of this iteration (at most one per slice)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+#pragma unroll
+      for (int u = 0; u < QA; ++u) {
+        const int q = threadIdx.x + u * NT;
+        if (NPOS % NT == 0 || q < NPOS) {
+          const float x = s_a[e * NPOS + q];
+#pragma unroll
+          for (int j = 0; j < H; ++j) {  // same per-term order as synthesis_pass
+            ac0[j][u] = fmaf(f.h[2 * j], x, ac0[j][u]);
+            ac1[j][u] = fmaf(f.h[2 * j + 1], x, ac1[j][u]);
+          }
+        }
+      }
+      const int rel = 2 * p + e - (H - 1);  // pair completed by this slice, relative to q0
+      if (rel >= 0 && rel < R / 2 && 2 * (q0 + rel) < b0) {
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+          const int q = threadIdx.x + u * NT;
+          if (NPOS % NT == 0 || q < NPOS) {
+            s_b[ncomp][q] = ac0[0][u];
+            s_b[ncomp][NPOS + q] = ac1[0][u];
+          }
+        }
+        if (ncomp == 0) gq0 = q0 + rel;
+        else gq1 = q0 + rel;
+        ++ncomp;
+      }
+#pragma unroll
+      for (int j = 0; j < H - 1; ++j)
+#pragma unroll
+        for (int u = 0; u < QA; ++u) {
+          ac0[j][u] = ac0[j + 1][u];
+          ac1[j][u] = ac1[j + 1][u];
+        }
+#pragma unroll
+      for (int u = 0; u < QA; ++u) ac0[H - 1][u] = ac1[H - 1][u] = 0.f;
+    }
+    if (ncomp > 0) {
+      __syncthreads();
+      // axis 1 of the completed pairs: lines (pair m, plane, column) -> U1 full-res rows
+      synthesis_pass<L, P1, false, true, NT>(
+          ncomp * 2 * U2, U1 / 2 / P1, f,
+          [&](int l, int j0, float* lo, float*) {
+            const int m = l / (2 * U2), rem = l - m * 2 * U2, pl = rem / U2, c = rem - pl * U2;
+            const float* base = &s_b[m][pl * NPOS + c];
+#pragma unroll
+            for (int j = 0; j < P1 + H - 1; ++j) lo[j] = base[(j0 + j) * U2];
+          },
+          [&](int l, int pp, float v0, float v1) {
+            const int m = l / (2 * U2), rem = l - m * 2 * U2, pl = rem / U2, c = rem - pl * U2;
+            const int g0 = 2 * (m ? gq1 : gq0) + pl, g1 = tl.c1 * U1 + pp, g2 = tl.c2 * U2 + c;
+            if (g0 < b0 && g1 < b1 && g2 < b2) {
+              const int o = (g0 * b1 + g1) * b2 + g2;
+              const float s0 = gld(same + o), s1 = gld(same + o + b2);
+              gst(out + o, fmaf(alpha, s0, beta * v0));
+              gst(out + o + b2, fmaf(alpha, s1, beta * v1));
+            }
+          });
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // FB_DOWN: one full analysis level on a (T0,T1,T2) tile of every band.
 // Bands go to out0 (packed coefficient array, strides st_out0, detail bands x alpha) except
 // the all-low band, which goes to out1 (next level's approximation, strides st_out1, x beta).
@@ -1283,9 +1572,13 @@ hipError_t launch_kind(const TaskArgs& a, int grid, const Filter& f, hipStream_t
     hipLaunchKernelGGL((k_lp_up<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_DOWN)
     hipLaunchKernelGGL((k_fb_down<D, L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_LP_DOWN_S && D == 3)
+    hipLaunchKernelGGL((k_lp_down_s3<L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_LP_DOWN_S)
     hipLaunchKernelGGL((k_lp_down_s<L, shape_of(K, 2, V, L).b, shape_of(K, 2, V, L).c, kThreads, VEC>), dim3(grid),
                        dim3(kThreads), 0, s, a, f);
+  else if constexpr (K == K_LP_UP_S)
+    hipLaunchKernelGGL((k_lp_up_s3<L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_DOWN_S)
     hipLaunchKernelGGL((k_fb_down_s<L, ES_TILE(K, D, V, L), kThreads, VEC>), dim3(grid), dim3(kThreads), 0, s, a, f);
   else if constexpr (K == K_FB_UP_S)
@@ -1416,8 +1709,12 @@ hipError_t launch_level(int kind, int ndim, int taps, int variant, const TaskArg
       if (ndim != 2) return hipErrorInvalidValue;
       return launch_kd<K_LP_UP2, 2>(taps, variant, vec, args, grid, f, stream);
     case K_LP_DOWN_S:
+      if (ndim == 3) return launch_kd<K_LP_DOWN_S, 3>(taps, variant, vec, args, grid, f, stream);
       if (ndim != 2) return hipErrorInvalidValue;
       return launch_kd<K_LP_DOWN_S, 2>(taps, variant, vec, args, grid, f, stream);
+    case K_LP_UP_S:
+      if (ndim != 3) return hipErrorInvalidValue;
+      return launch_kd<K_LP_UP_S, 3>(taps, variant, vec, args, grid, f, stream);
     case K_FB_DOWN_S:
       if (ndim != 3) return hipErrorInvalidValue;
       return launch_kd<K_FB_DOWN_S, 3>(taps, variant, vec, args, grid, f, stream);

@@ -12,7 +12,9 @@ struct Shape3 {
 constexpr Shape3 shape_of(int K, int D, int V, int L) {
   // V: 0 wide, 1 narrow, 2 medium
   if (K == K_LP_UP2) return V == 0 ? Shape3{1, 64, 128} : (V == 1 ? Shape3{1, 32, 64} : Shape3{1, 32, 128});
+  if (K == K_LP_DOWN_S && D == 3) return V == 0 ? Shape3{16, 8, 32} : (V == 1 ? Shape3{8, 8, 16} : Shape3{8, 8, 32});
   if (K == K_LP_DOWN_S) return V == 0 ? Shape3{1, 64, 64} : (V == 1 ? Shape3{1, 16, 64} : Shape3{1, 32, 64});
+  if (K == K_LP_UP_S) return V == 0 ? Shape3{16, 16, 32} : (V == 1 ? Shape3{8, 8, 32} : Shape3{8, 16, 32});
   if (K == K_FB_DOWN_S) return V == 0 ? Shape3{16, 8, 32} : (V == 1 ? Shape3{8, 8, 16} : Shape3{8, 8, 32});
   if (K == K_FB_UP_S) return V == 0 ? Shape3{16, 16, 32} : (V == 1 ? Shape3{8, 8, 32} : Shape3{8, 16, 32});
   if (D == 1) {

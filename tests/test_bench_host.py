@@ -26,6 +26,10 @@ def test_template_names():
         "void es::k_lp_down_s<16, 64, 256, 256, true>(es::TaskArgs, es::Filter)"
     assert bench.template_name("fb_down_s_3d_L8_v1_t8x8x16") == \
         "void es::k_fb_down_s<8, 8, 8, 16, 256, true>(es::TaskArgs, es::Filter)"
+    assert bench.template_name("lp_down_s_3d_L16_v2_t8x8x32") == \
+        "void es::k_lp_down_s3<16, 8, 8, 32, 256, true>(es::TaskArgs, es::Filter)"
+    assert bench.template_name("lp_up_s_3d_L4_v0_t16x16x32_scalar") == \
+        "void es::k_lp_up_s3<4, 16, 16, 32, 256, false>(es::TaskArgs, es::Filter)"
 
 
 def test_more_than_one_gpu_is_refused():

@@ -66,7 +66,7 @@ CASES_3D = [c for c in CASES if len(c[0]) == 3] + [((16, 24, 20), 3, 2, 1.0), ((
 # rows not a multiple of 4 (scalar staging), filters longer than the coarse levels
 CASES_2D = [c for c in CASES if len(c[0]) == 2] + [((200, 776), 8, 3, 1.5), ((40, 36), 2, 2, 1.0),
                                                     ((1024, 96), 7, 5, 0.5)]
-FAMILY_CASES = [(c, op) for c in CASES_3D for op in (0, 1)] + [(c, op) for c in CASES_2D for op in (2, 3)]
+FAMILY_CASES = [(c, op) for c in CASES_3D for op in (0, 1, 2, 3)] + [(c, op) for c in CASES_2D for op in (2, 3)]
 FAMILY_KNOBS = {
     "streamed": dict(ESWAVE_STREAMED=2),
     "streamed-wide": dict(ESWAVE_STREAMED=2, ESWAVE_FORCE_VARIANT=0),
@@ -80,9 +80,9 @@ FAMILY_KNOBS = {
 @pytest.mark.parametrize("case_op", FAMILY_CASES, ids=lambda c: f"{OP_NAMES[c[1]]}-{c[0][0]}-db{c[0][1]}-m{c[0][2]}")
 @pytest.mark.parametrize("family", list(FAMILY_KNOBS))
 def test_parity_families(case_op, family):
-    """Levels with two kernel families (3-D full bank: plain tiles / streamed along axis 0; 2-D
-    low-pass analysis: plain tiles / streamed along axis 1), every tile variant, with and without
-    the coarse-level kernel, batch of two."""
+    """Levels with two kernel families (3-D full bank and low-pass: plain tiles / streamed along
+    axis 0; 2-D low-pass analysis: plain tiles / streamed along axis 1), every tile variant, with
+    and without the coarse-level kernel, batch of two."""
     (shape, order, levels, s), op = case_op
     gen = np.random.default_rng(hash((shape, order, levels, op, 3)) & 0xFFFF)
     x = gen.standard_normal((2,) + shape)
@@ -113,12 +113,13 @@ def test_families_bit_identical(op, shape):
 @pytest.mark.parametrize("variant", [0, 1, 2])
 def test_families_bit_identical_3d_variants(order, variant):
     """Every streamed 3-D tile variant against the plain tiles, bit for bit: ragged in-plane
-    tiles, runs along axis 0 longer than the level, filters from 2 to 16 taps, analysis and
-    synthesis (the adjoint and the apply)."""
+    tiles, runs along axis 0 longer than the level, filters from 2 to 16 taps, full-bank analysis
+    and synthesis (the adjoint and the apply) and the low-pass levels of the projection form (the
+    covariance and the sampler)."""
     shape, levels, s = (2, 40, 24, 72), 3, 1.25
     x = torch.from_numpy(np.random.default_rng(order * 10 + variant).standard_normal(shape).astype(np.float32)).to(DEV)
     say("families-bits-3d", order, variant, shape)
-    for op in (0, 1):
+    for op in (0, 1, 2, 3):
         outs = []
         for knobs in (dict(ESWAVE_STREAMED=0, ESWAVE_TAIL_MAX=0),
                       dict(ESWAVE_STREAMED=2, ESWAVE_TAIL_MAX=0, ESWAVE_FORCE_VARIANT=variant)):
