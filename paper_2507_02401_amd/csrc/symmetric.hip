@@ -414,7 +414,7 @@ constexpr int kSymThreads = 256;
 
 SymTiles sym_tiles(int D, int L) {
   if (D == 1) return {{1, 1, 256}, {1, 1, 512}};
-  if (D == 2) return {{1, 16, 64}, {1, 32, 64}};
+  if (D == 2) return {{1, 16, 48}, {1, 32, 64}};  // 48 columns: 11 tiles cover 519 (the 1024^2 db8 level 1)
   if (L <= 4) return {{4, 8, 16}, {8, 8, 32}};
   if (L <= 8) return {{4, 4, 16}, {8, 8, 32}};
   return {{2, 4, 16}, {8, 8, 32}};
@@ -657,7 +657,7 @@ hipError_t launch_sym_level(bool up, const SymTask& t, int64_t grid, const Filte
     else hipLaunchKernelGGL((k_sym_down<1, L, 1, 1, 256, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
   } else if constexpr (D == 2) {
     if (up) hipLaunchKernelGGL((k_sym_up<2, L, 1, 32, 64, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
-    else hipLaunchKernelGGL((k_sym_down<2, L, 1, 16, 64, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    else hipLaunchKernelGGL((k_sym_down<2, L, 1, 16, 48, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
   } else {
     if (up) {
       hipLaunchKernelGGL((k_sym_up<3, L, 8, 8, 32, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
