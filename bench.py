@@ -485,7 +485,8 @@ def main():
     ap.add_argument("--volume-only", action="store_true",
                     help="time only es_adjoint + es_apply of the 256^3 db4 m5 volume (for profiling) and exit")
     ap.add_argument("--ragged-seed", type=int, default=None,
-                    help="time only a 200-instance ragged plan drawn with this seed (graph vs eager) and exit; "
+                    help="time only a 200-instance ragged plan drawn with this seed (autotuned unless --no-autotune; "
+                         "graph vs eager) and exit; "
                          "seed 0 is not accepted (that case is kept off the GPU)")
     args = ap.parse_args()
     if args.trace_summary:
@@ -534,6 +535,8 @@ def main():
         ins = [torch.from_numpy(a).to(dev) for a in d["xs"]]
         outs = [torch.empty_like(a) for a in ins]
         plan = es.RaggedPlan(descs, es.OP_COV)
+        if not args.no_autotune:  # as in the main run: tile choice and coarse depth measured on these buffers
+            plan.autotune(ins, outs, reps=2)
         plan(ins, outs, graph=False)
         torch.cuda.synchronize()
         eager = [o.clone() for o in outs]
@@ -545,6 +548,7 @@ def main():
         tg = _time(lambda: plan(ins, outs, graph=True), torch, max(3, args.steps))
         te = _time(lambda: plan(ins, outs, graph=False), torch, max(3, args.steps))
         print(json.dumps({"workload": f"matern_cov_apply ragged plan: 200 instances, seed {args.ragged_seed}",
+                          "autotuned": not args.no_autotune,
                           "voxels": nvr, "launches_per_call": plan.num_launches, "graph_ms": round(1e3 * tg, 3),
                           "eager_ms": round(1e3 * te, 3), "voxels_per_s_graph": round(nvr / tg, 1),
                           "graph_equals_eager": same}), flush=True)
