@@ -423,6 +423,21 @@ SymTiles sym_tiles(int D, int L) {
 // Fold of the transposed operator's extended synthesis (A^T = fold o zero-padded synthesis onto
 // the extension): out[j] = alpha * same[j] + beta * sum of v over every extension position that
 // reflects to j, per present axis over [-(L - 2), 2 l - 1] (v's index p + (L - 2)).
+// Division of a non-negative 31-bit x by a fixed d in [1, 2^31] as a multiply-high, an add and a
+// shift (Granlund and Montgomery's method with a 33-bit multiplier whose top bit is the add):
+// with s = ceil(log2 d) and m = floor(2^32 (2^s - d) / d) + 1, floor(x / d) = (mulhi(x, m) + x) >> s.
+struct FoldDiv {
+  uint32_t m, s;
+};
+
+inline FoldDiv make_fold_div(uint32_t d) {
+  uint32_t s = 0;
+  while ((uint64_t(1) << s) < d) ++s;
+  return {(uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << s) - d)) / d + 1), s};
+}
+
+DEVI int fold_div(int x, FoldDiv q) { return (int)((__umulhi((uint32_t)x, q.m) + (uint32_t)x) >> q.s); }
+
 struct SymFold {
   const float* v;
   const float* same;  // may equal out
@@ -433,6 +448,13 @@ struct SymFold {
   int32_t nl[3];                // coefficient lengths l (padded)
   int32_t ext;                  // L - 2
   int32_t present[3];           // 1 for the axes of the grid
+  // Rows (j0, j1) with another image along axis 0 or 1 ("edge rows"): j_a outside the interior
+  // [alo[a], ahi[a]) of axis a; every row when axis 2 is shorter than L - 1.  ce1 = edge positions
+  // of axis 1, erows = edge rows per instance.
+  int32_t alo[2], ahi[2], ce1, erows;
+  FoldDiv dn1, dn2, drpi;       // dividers by no[1], no[2] and no[0] * no[1]
+  FoldDiv dce1, derows;         // dividers by ce1 and erows
+  int32_t gmain;                // work-groups of the interior rows (set at the launch)
   float alpha, beta;
 };
 
@@ -450,51 +472,140 @@ DEVI void visit_images(int j, int n, int lo, int hi, bool simple, F f) {
   }
 }
 
-// One output row (instance, j0, j1) per grid-y index; threads along the row.
-__global__ void __launch_bounds__(256) k_sym_fold(SymFold F) {
+// Outputs per work-group pass of the fold: four per thread.
+constexpr int kFoldPass = 4 * 256;
+
+// Rows of the fold per work-group pass: whole output rows (instance, j0, j1) filling up to
+// kFoldPass outputs, at least one (long rows are walked in passes).
+inline __host__ __device__ int fold_rows_per_block(int n2) { return n2 >= kFoldPass ? 1 : kFoldPass / n2; }
+
+// Fold on a 3-D grid (every axis extended), interior rows: rpb output rows per work-group blk of
+// nblk (strided over the rows), threads along the rows' outputs; the rows an edge row has in its
+// place are skipped.  Four outputs per thread and pass: every output's own position j and its
+// same[] term are loaded unconditionally first (eight loads in flight), then the at most two
+// axis-2 images of outputs near the ends of their row.
+DEVI void fold_interior(const SymFold& F, int blk, int nblk) {
+  const int n2 = F.no[2];
+  const int rows = (int)(F.total / n2);  // the host keeps the row count below 2^31
+  const int lo2 = -F.ext, hi2 = 2 * F.nl[2] - 1;
+  const int rpi = F.no[0] * F.no[1];  // rows per instance
+  const int rpb = fold_rows_per_block(n2);
+  for (int64_t rb0 = (int64_t)blk * rpb; rb0 < rows; rb0 += (int64_t)nblk * rpb) {
+    const int rb = (int)rb0;
+    const int span = min(rpb, rows - rb) * n2;  // outputs of this block's rows
+    constexpr int U = 4;
+    for (int base = threadIdx.x; base < span; base += U * 256) {
+      float acc[U], sv[U];
+      int64_t oo[U];
+      int j2s[U];
+      bool st[U];
+      const float* row[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = min(base + u * 256, span - 1);  // lanes past the end repeat the last output
+        const int dr = fold_div(e, F.dn2), j2 = e - dr * n2;
+        const int r = rb + dr;
+        const int inst = fold_div(r, F.drpi), rr = r - inst * rpi;
+        const int j0 = fold_div(rr, F.dn1), j1 = rr - j0 * F.no[1];
+        j2s[u] = j2;
+        st[u] = base + u * 256 < span && j0 >= F.alo[0] && j0 < F.ahi[0] && j1 >= F.alo[1] && j1 < F.ahi[1];
+        row[u] = F.v + inst * F.bs_v + (j0 + F.ext) * F.sv[0] + (j1 + F.ext) * F.sv[1] + F.ext;
+        oo[u] = inst * F.bs_out + (int64_t)j0 * F.so[0] + (int64_t)j1 * F.so[1] + j2;
+        acc[u] = gld(row[u] + j2);
+        sv[u] = F.same ? gld(F.same + oo[u]) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int j2 = j2s[u], pa = -1 - j2, pb = 2 * n2 - 1 - j2;
+        const bool ia = pa >= lo2, ib = pb <= hi2;
+        if (ia || ib) {
+          const float xa = gld(row[u] + (ia ? pa : j2)), xb = gld(row[u] + (ib ? pb : j2));
+          acc[u] += (ia ? xa : 0.f) + (ib ? xb : 0.f);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (st[u]) gst(F.out + oo[u], fmaf(F.alpha, sv[u], F.beta * acc[u]));
+    }
+  }
+}
+
+// Fold, edge rows (see SymFold): every image of every output, rpb rows per work-group blk of nblk.
+DEVI void fold_edges(const SymFold& F, int blk, int nblk) {
   const int n0 = F.no[0], n1 = F.no[1], n2 = F.no[2];
-  const int64_t rows = F.total / n2;
-  int lo[3], hi[3], eo[3];
+  const int rows = (int)(F.total / ((int64_t)n0 * n1 * n2)) * F.erows;
+  int lo[3], hi[3];
   bool simple[3];
   for (int a = 0; a < 3; ++a) {
     lo[a] = F.present[a] ? -F.ext : 0;
     hi[a] = F.present[a] ? 2 * F.nl[a] - 1 : 0;
-    eo[a] = F.present[a] ? F.ext : 0;
     simple[a] = !F.present[a] || F.no[a] >= F.ext + 1;
   }
-  const int rpi = n0 * n1;  // rows per instance; the host keeps the row count below 2^31
-  for (int r = blockIdx.y; r < (int)rows; r += gridDim.y) {
-    const int inst = r / rpi;
-    const int rr = r - inst * rpi;
-    const int j0 = rr / n1, j1 = rr - j0 * n1;
-    const float* v = F.v + inst * F.bs_v;
-    const int64_t orow = inst * F.bs_out + (int64_t)j0 * F.so[0] + (int64_t)j1 * F.so[1];
-    // four outputs per thread and pass, every load of the pass issued before its stores
-    constexpr int U = 4;
-    for (int base = threadIdx.x; base < n2; base += U * 256) {
-      float acc[U], sv[U];
+  const int c0rows = (F.alo[0] + n0 - F.ahi[0]) * n1;  // edge rows with j0 at an edge of axis 0
+  const int rpb = fold_rows_per_block(n2);
+  for (int64_t rb0 = (int64_t)blk * rpb; rb0 < rows; rb0 += (int64_t)nblk * rpb) {
+    const int rb = (int)rb0;
+    const int span = min(rpb, rows - rb) * n2;
+    for (int e = threadIdx.x; e < span; e += 256) {
+      const int dr = fold_div(e, F.dn2), j2 = e - dr * n2;
+      const int r = rb + dr;
+      const int inst = fold_div(r, F.derows), s = r - inst * F.erows;
+      int j0, j1;
+      if (s < c0rows) {
+        const int k = fold_div(s, F.dn1);
+        j1 = s - k * n1;
+        j0 = k < F.alo[0] ? k : F.ahi[0] + (k - F.alo[0]);
+      } else {
+        const int t = s - c0rows, k0 = fold_div(t, F.dce1), k1 = t - k0 * F.ce1;
+        j0 = F.alo[0] + k0;
+        j1 = k1 < F.alo[1] ? k1 : F.ahi[1] + (k1 - F.alo[1]);
+      }
+      const float* v = F.v + inst * F.bs_v;
+      const int64_t o = inst * F.bs_out + (int64_t)j0 * F.so[0] + (int64_t)j1 * F.so[1] + j2;
+      const int e0 = F.present[0] ? F.ext : 0, e1 = F.present[1] ? F.ext : 0, e2 = F.present[2] ? F.ext : 0;
+      float acc = 0.f;
+      if (simple[0] && simple[1] && simple[2]) {
+        // at most three images per axis (j, -1 - j, 2n - 1 - j): all 27 combinations loaded at once,
+        // a missing image replaced by j and masked
+        const int jv[3] = {j0, j1, j2};
+        int p[3][3];
+        bool ok[3][3];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j2 = base + u * 256;
-        acc[u] = 0.f;
-        sv[u] = 0.f;
-        if (j2 < n2) {
-          visit_images(j0, n0, lo[0], hi[0], simple[0], [&](int p0) {
-            visit_images(j1, n1, lo[1], hi[1], simple[1], [&](int p1) {
-              const float* row = v + (p0 + eo[0]) * F.sv[0] + (p1 + eo[1]) * F.sv[1] + eo[2];
-              visit_images(j2, n2, lo[2], hi[2], simple[2], [&](int p2) { acc[u] += gld(row + p2); });
-            });
-          });
-          if (F.same) sv[u] = gld(F.same + orow + j2);
+        for (int a = 0; a < 3; ++a) {
+          const int j = jv[a], pa = -1 - j, pb = 2 * F.no[a] - 1 - j;
+          ok[a][0] = true;
+          ok[a][1] = F.present[a] && pa >= lo[a];
+          ok[a][2] = F.present[a] && pb <= hi[a];
+          p[a][0] = j;
+          p[a][1] = ok[a][1] ? pa : j;
+          p[a][2] = ok[a][2] ? pb : j;
         }
-      }
+        float x[27];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int j2 = base + u * 256;
-        if (j2 < n2) gst(F.out + orow + j2, fmaf(F.alpha, sv[u], F.beta * acc[u]));
+        for (int i = 0; i < 27; ++i)
+          x[i] = gld(v + (p[0][i / 9] + e0) * F.sv[0] + (p[1][i / 3 % 3] + e1) * F.sv[1] + e2 + p[2][i % 3]);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) acc += (ok[0][i / 9] && ok[1][i / 3 % 3] && ok[2][i % 3]) ? x[i] : 0.f;
+      } else {  // an axis shorter than L - 1: every image family, looped
+        visit_images(j0, n0, lo[0], hi[0], simple[0], [&](int p0) {
+          visit_images(j1, n1, lo[1], hi[1], simple[1], [&](int p1) {
+            const float* rw = v + (p0 + e0) * F.sv[0] + (p1 + e1) * F.sv[1] + e2;
+            visit_images(j2, n2, lo[2], hi[2], simple[2], [&](int p2) { acc += gld(rw + p2); });
+          });
+        });
       }
+      gst(F.out + o, fmaf(F.alpha, F.same ? gld(F.same + o) : 0.f, F.beta * acc));
     }
   }
+}
+
+// One launch per level: work-groups [0, gmain) take the interior rows, the rest the edge rows.
+__global__ void __launch_bounds__(256) k_sym_fold(SymFold F) {
+  const int b = blockIdx.x;
+  if (b < F.gmain)
+    fold_interior(F, b, F.gmain);
+  else
+    fold_edges(F, b - F.gmain, gridDim.x - F.gmain);
 }
 
 // Boundary shell of the transposed operator on 1-D and 2-D grids.  On [0, n) the extended
@@ -1015,6 +1126,21 @@ es_status sym_schedule(const SymGeo& g, int64_t batch, const float* x, float* y,
       F.present[a] = a >= 3 - g.D;
     }
     F.ext = g.L - 2;
+    // interior of axes 0 and 1: no image at -1 - j (j >= L - 2) nor at 2n - 1 - j (j < 2n - 2l)
+    for (int a = 0; a < 2; ++a) {
+      const int n = F.no[a], lo = std::min(F.ext, n);
+      const bool simple = n >= F.ext + 1;
+      F.alo[a] = simple ? lo : n;
+      F.ahi[a] = simple ? std::max(std::min(2 * n - 2 * F.nl[a], n), lo) : n;
+    }
+    if (F.no[2] < F.ext + 1) F.alo[0] = F.ahi[0] = F.no[0];  // short axis 2: every row is an edge row
+    F.ce1 = F.alo[1] + F.no[1] - F.ahi[1];
+    F.erows = (F.alo[0] + F.no[0] - F.ahi[0]) * F.no[1] + (F.ahi[0] - F.alo[0]) * F.ce1;
+    F.dn1 = make_fold_div(F.no[1]);
+    F.dn2 = make_fold_div(F.no[2]);
+    F.drpi = make_fold_div(F.no[0] * F.no[1]);
+    F.dce1 = make_fold_div(std::max(F.ce1, 1));
+    F.derows = make_fold_div(std::max(F.erows, 1));
     F.alpha = (float)alpha;
     F.beta = 1.f;
     fl.grid = 0;  // 2-D grid, see the launch
@@ -1071,11 +1197,19 @@ es_status sym_run(int ndim, const int64_t* shape, int64_t batch, int order, int 
   }
   for (const SymLaunch& l : seq) {
     if (l.kind == 2) {
-      // one output row per work-group (rows over grid y, at most 65535 at a time, strided)
-      const int64_t rows = l.fold.total / l.fold.no[2];
-      const dim3 grid(1, (unsigned)std::min<int64_t>(rows, 65535));
-      hipLaunchKernelGGL(k_sym_fold, grid, dim3(256), 0, hs, l.fold);
-      he = hipGetLastError();
+      // interior rows and edge rows (disjoint outputs) in one launch: whole output rows per
+      // work-group (at most 2^20 groups per part, strided)
+      SymFold F = l.fold;
+      const int64_t rows = F.total / F.no[2], inst = rows / ((int64_t)F.no[0] * F.no[1]);
+      const int64_t rpb = fold_rows_per_block(F.no[2]);
+      const int64_t irows = inst * ((int64_t)F.no[0] * F.no[1] - F.erows), erows = inst * F.erows;
+      F.gmain = irows > 0 ? (int32_t)std::min<int64_t>((rows + rpb - 1) / rpb, 1 << 20) : 0;
+      const int64_t gedge = erows > 0 ? std::min<int64_t>((erows + rpb - 1) / rpb, 1 << 20) : 0;
+      he = hipSuccess;
+      if (F.gmain + gedge > 0) {
+        hipLaunchKernelGGL(k_sym_fold, dim3((unsigned)(F.gmain + gedge)), dim3(256), 0, hs, F);
+        he = hipGetLastError();
+      }
     } else if (l.kind == 3) {
       // preparation, then the shell, per chunk of instances with fewer than 2^31 items (32-bit
       // indices in the kernels; each item count per instance is below 2^31 by the size check)

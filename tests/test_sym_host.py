@@ -148,3 +148,26 @@ def test_transpose_validation_before_any_device_call(lib, kw, status):
                                         args["levels"], args["s"], args["x"], args["y"], args["ws"],
                                         args["ws_bytes"], None)
     assert st == status
+
+
+def _fold_div(d):
+    """Host mirror of the fold kernel's divider: s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1."""
+    s = 0
+    while (1 << s) < d:
+        s += 1
+    return ((1 << 32) * ((1 << s) - d)) // d + 1, s
+
+
+def test_fold_divider_exact_on_31_bit_numerators():
+    # the kernel takes floor(x / d) as (mulhi(x, m) + x) >> s for 0 <= x < 2^31 and 1 <= d <= 2^31;
+    # checked against integer division, with the multiples of d and their neighbours included
+    rng = np.random.default_rng(7)
+    divisors = list(range(1, 1200)) + [int(v) for v in rng.integers(1, 2 ** 31, 300)] + [2 ** 30, 2 ** 30 + 1,
+                                                                                        2 ** 31 - 1, 2 ** 31]
+    for d in divisors:
+        m, s = _fold_div(d)
+        assert 0 < m < 2 ** 32
+        xs = [int(v) for v in rng.integers(0, 2 ** 31, 200)] + list(range(0, 2100)) + [2 ** 31 - 1]
+        xs += [k * d + o for k in range(1, 40) for o in (-1, 0) if 0 <= k * d + o < 2 ** 31]
+        for x in xs:
+            assert (((x * m) >> 32) + x) >> s == x // d, (d, x)
