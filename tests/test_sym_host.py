@@ -171,3 +171,60 @@ def test_fold_divider_exact_on_31_bit_numerators():
         xs += [k * d + o for k in range(1, 40) for o in (-1, 0) if 0 <= k * d + o < 2 ** 31]
         for x in xs:
             assert (((x * m) >> 32) + x) >> s == x // d, (d, x)
+
+
+def _fold_edge_split(no, nl, ext):
+    """Host mirror of the 3-D fold's row split: interior [alo, ahi) of axes 0 and 1, edge rows."""
+    alo, ahi = [0, 0], [0, 0]
+    for a in range(2):
+        n = no[a]
+        lo, simple = min(ext, n), n >= ext + 1
+        alo[a] = lo if simple else n
+        ahi[a] = max(min(2 * n - 2 * nl[a], n), lo) if simple else n
+    if no[2] < ext + 1:
+        alo[0] = ahi[0] = no[0]
+    ce1 = alo[1] + no[1] - ahi[1]
+    erows = (alo[0] + no[0] - ahi[0]) * no[1] + (ahi[0] - alo[0]) * ce1
+    return alo, ahi, ce1, erows
+
+
+def _fold_edge_row(s, no, alo, ahi, ce1):
+    """The fold's decode of edge-row index s into (j0, j1)."""
+    c0rows = (alo[0] + no[0] - ahi[0]) * no[1]
+    if s < c0rows:
+        k, j1 = divmod(s, no[1])
+        return (k if k < alo[0] else ahi[0] + (k - alo[0])), j1
+    k0, k1 = divmod(s - c0rows, ce1)
+    return alo[0] + k0, (k1 if k1 < alo[1] else ahi[1] + (k1 - alo[1]))
+
+
+def _images(j, n, lo, hi):
+    """Every extension position in [lo, hi] that reflects to j (p = j or -1 - j mod 2n), by brute force."""
+    return sorted(p for p in range(lo, hi + 1) if p % (2 * n) in (j, (-1 - j) % (2 * n)))
+
+
+@pytest.mark.parametrize("order", [1, 2, 4, 8, 10])
+def test_fold_row_split_covers_every_row_once(lib, order):
+    # edge rows decode onto exactly the rows with another image along axis 0 or 1 (or every row
+    # when axis 2 is shorter than L - 1); interior rows have one image along axes 0 and 1 and at
+    # most the two axis-2 images the interior part loads
+    L = 2 * order
+    ext = L - 2
+    for no in [(1, 1, 1), (3, 2, 6), (5, 9, 3), (13, 17, 19), (20, 30, 40), (33, 4, 7), (8, 2, 1)]:
+        nl = [int(symdwt.sym_length(n, L)) for n in no]
+        alo, ahi, ce1, erows = _fold_edge_split(no, nl, ext)
+        edge = [_fold_edge_row(s, no, alo, ahi, ce1) for s in range(erows)]
+        assert all(0 <= a < no[0] and 0 <= b < no[1] for a, b in edge)
+        assert len(set(edge)) == erows
+        for j0 in range(no[0]):
+            for j1 in range(no[1]):
+                interior = alo[0] <= j0 < ahi[0] and alo[1] <= j1 < ahi[1]
+                assert interior != ((j0, j1) in set(edge))
+                if not interior:
+                    continue
+                assert _images(j0, no[0], -ext, 2 * nl[0] - 1) == [j0]
+                assert _images(j1, no[1], -ext, 2 * nl[1] - 1) == [j1]
+                for j2 in range(no[2]):
+                    pa, pb = -1 - j2, 2 * no[2] - 1 - j2
+                    want = sorted([j2] + [pa] * (pa >= -ext) + [pb] * (pb <= 2 * nl[2] - 1))
+                    assert _images(j2, no[2], -ext, 2 * nl[2] - 1) == want
