@@ -105,8 +105,11 @@ __global__ void __launch_bounds__(NT) k_sym_down(SymTask t, Filter f) {
   constexpr int NVL = (SH + I2 + 3) / 4;  // 16-byte groups loaded per row
   constexpr int NLD = NROW * NVL, ITL = (NLD + NT - 1) / NT;
   static_assert(T2 % 4 == 0 && (D < 2 || T1 % P1 == 0) && (D < 3 || T0 % P0 == 0), "tile shape");
+  static_assert(NROW * T2 + NB <= NROW * I2P, "axis-1 results must fit past the axis-2 rows");
   __shared__ __attribute__((aligned(16))) float s_in[NROW * I2P];
-  __shared__ float s_b[NB];
+  // 3-D: the axis-1 results go past the axis-2 rows in the staging buffer (the axis-1 pass reads
+  // only those rows), which keeps the 16-tap tile within half of the CU's LDS
+  float* const s_b = s_in + NROW * T2;
   __shared__ int s_row[NROW], s_x2[I2];
 
   const int wg = blockIdx.x;
@@ -417,7 +420,10 @@ SymTiles sym_tiles(int D, int L) {
   if (D == 2) return {{1, 16, 48}, {1, 32, 64}};  // 48 columns: 11 tiles cover 519 (the 1024^2 db8 level 1)
   if (L <= 4) return {{4, 8, 16}, {8, 8, 32}};
   if (L <= 8) return {{4, 4, 16}, {8, 8, 32}};
-  return {{2, 4, 16}, {8, 8, 32}};
+  if (L <= 12) return {{2, 4, 16}, {8, 8, 32}};
+  // 14 and 16 taps: larger tiles (measured) -- the filter halo is most of a small tile
+  if (L <= 14) return {{4, 4, 16}, {8, 8, 32}};
+  return {{4, 8, 16}, {8, 8, 32}};
 }
 
 // Fold of the transposed operator's extended synthesis (A^T = fold o zero-padded synthesis onto
@@ -776,8 +782,12 @@ hipError_t launch_sym_level(bool up, const SymTask& t, int64_t grid, const Filte
       hipLaunchKernelGGL((k_sym_down<3, L, 4, 8, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     } else if constexpr (L <= 8) {
       hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
-    } else {
+    } else if constexpr (L <= 12) {
       hipLaunchKernelGGL((k_sym_down<3, L, 2, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    } else if constexpr (L <= 14) {
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+    } else {
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 8, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     }
   }
   return hipGetLastError();
