@@ -231,6 +231,34 @@ def copy_ceiling(torch, dev, nbytes):
     return round(2 * nbytes / t / 1e9, 1)
 
 
+# 3-D non-periodic volumes timed beside the 2-D batch: (shape, batch, order, levels)
+SYM_VOLUMES = (((96, 112, 160), 2, 8, 3), ((256, 256, 256), 1, 4, 5))
+
+
+def sym_volumes(es, lib, _lib, torch, dev, reps):
+    """sym_cov_apply and its transpose on SYM_VOLUMES (seeded normal inputs, outputs and
+    workspaces preallocated)."""
+    rows = []
+    gen = torch.Generator(device=dev).manual_seed(11)
+    for shape, batch, order, levels in SYM_VOLUMES:
+        x = torch.randn((batch,) + shape, generator=gen, device=dev)
+        y = torch.empty_like(x)
+        sa = _lib.shape_arg(shape)
+        ws = torch.empty(max(1, lib.es_sym_workspace_bytes(3, sa, batch, order, levels)), dtype=torch.uint8,
+                         device=dev)
+        wt = torch.empty(max(1, lib.es_sym_transpose_workspace_bytes(3, sa, batch, order, levels)),
+                         dtype=torch.uint8, device=dev)
+        tf = _time(lambda: es.sym_cov_apply(x, 3, order, levels, S, out=y, workspace=ws), torch, reps, warmup=2)
+        tt = _time(lambda: es.sym_cov_apply_transpose(x, 3, order, levels, S, out=y, workspace=wt), torch, reps,
+                   warmup=2)
+        rows.append({"workload": f"sym_cov_apply: {batch} x {'x'.join(map(str, shape))}, db{order}, {levels} levels, "
+                                 f"s={S}, half-point symmetric extension",
+                     "ms": round(1e3 * tf, 4), "transpose_ms": round(1e3 * tt, 4),
+                     "voxels_per_s": round(x.numel() / tf, 1)})
+        del x, y, ws, wt
+    return rows
+
+
 def other_workloads(args, es, inputs, torch, np):
     """The other workloads: fused path vs the plain per-instance, per-axis launches."""
     from paper_2507_02401_amd import autograd as ag
@@ -582,6 +610,9 @@ def main():
                           "ms": round(1e3 * tsym, 4), "voxels_per_s": round(voxels / tsym, 1),
                           "transpose_ms": round(1e3 * tsymT, 4),
                           "band_lengths": es.sym_band_lengths(SIDE, ORDER, LEVELS)}), flush=True)
+        del sws, tws
+        for row in sym_volumes(es, lib, _lib, torch, dev, args.steps):
+            print(json.dumps(row), flush=True)
         return
 
     if args.volume_only:
@@ -830,6 +861,7 @@ def main():
             "periodic_cov_ms": round(1e3 * elapsed / args.steps, 4),
             "rel_l2_vs_fp64_oracle_image5": None}
         del sws
+        result["sym_cov_apply"]["volumes"] = sym_volumes(es, lib, _lib, torch, dev, reps)
         result["other_workloads"] = other_workloads(args, es, inputs, torch, np)
 
     if not args.no_plain:
