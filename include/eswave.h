@@ -161,6 +161,39 @@ es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int ord
                           void* stream);
 size_t es_tikhonov_pcg_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels);
 
+/* Solves, per instance, the regularised linear system in the form the paper writes it (Sec. 3:
+ * the linear equation of the Tikhonov minimiser, E_s^* applied to its normal equations; Sec. 5:
+ * solved there by GMRES):
+ *     (E_s^* K^* K + alpha I) x = E_s^* K^* p,   K = diag(mask),  E_s^* = W^T D_{2s} W,
+ * by restarted GMRES from x = 0.  E_s^* is matern_cov_apply(s); the system is not symmetric.  For a
+ * 0/1 mask its solution is that of es_tikhonov_pcg.  Arnoldi step: one operator application, then
+ * classical Gram-Schmidt against the basis with one reorthogonalisation pass (two passes of inner
+ * products over the basis, each followed by one update pass), all on the device (FP32 vectors,
+ * compensated FP32 inner products reduced per instance in a fixed order: deterministic).  The host
+ * reads the new Hessenberg column after every step (synchronising `stream`) and keeps the
+ * Hessenberg matrix, its Givens rotations and the least-squares solution in FP64.  An instance
+ * stops contributing once its residual estimate |g_{k+1}| / ||E_s^* K^* p|| <= rtol; after every
+ * `restart` steps the iterate is formed (x += V y) and, if any instance is still above rtol and
+ * iterations remain, GMRES restarts from the true residual.  At most max_iter Arnoldi steps.
+ *   restart      basis length, 1..64.
+ *   p, mask, x   device, batch * prod(shape) floats, 16-byte aligned; x is written (must not
+ *                overlap p, mask or ws).
+ *   iterations   host, receives the Arnoldi steps run (may be NULL).
+ *   rel_residual host, batch floats: the true ||E_s^* K^* p - A x|| / ||E_s^* K^* p|| of each
+ *                instance at the end (one more operator application; 0 when the right side is 0).
+ *   ws           device, es_tikhonov_gmres_workspace_bytes(...) bytes, 256-byte aligned: the basis
+ *                (restart + 1 vectors), the right side, two work vectors, partial sums, the
+ *                per-instance coefficients and the operator's workspace.
+ * Other arguments as for matern_cov_apply.  Errors: ES_EINVAL (arguments, alpha <= 0, rtol < 0,
+ * max_iter < 0, restart outside 1..64), ES_EWORKSPACE, ES_EUNSUPPORTED, ES_EDEVICE.  Synchronous on
+ * return. */
+es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                            double alpha, const float* p, const float* mask, float* x, int32_t restart,
+                            int32_t max_iter, double rtol, int32_t* iterations, float* rel_residual, void* ws,
+                            size_t ws_bytes, void* stream);
+size_t es_tikhonov_gmres_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                                         int32_t restart);
+
 /* ---- Fourier form of E_s^* (Sec. 4, Implementation) ------------------------------------ */
 
 /* y_b = ifft(B . fft(x_b)) for each of `batch` instances: the paper's second realisation of the

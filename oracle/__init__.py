@@ -45,7 +45,7 @@ Pinning status (see tests/test_oracle_*.py):
 from .filters import daubechies_lowpass, quadrature_highpass
 from .dwt import analysis_axis, synthesis_axis, dwt, idwt, level_weights, weight_map
 from .ops import es_adjoint, es_apply, matern_cov_apply, matern_sample, hs_norm_sq
-from .solver import tikhonov_solve
+from .solver import tikhonov_gmres, tikhonov_solve
 from .fourier import fft_cov_apply, fourier_multiplier
 from .symdwt import sym_cov_apply, sym_dwt, sym_idwt, sym_lengths
 from . import dense
@@ -54,5 +54,5 @@ __all__ = [
     "daubechies_lowpass", "quadrature_highpass",
     "analysis_axis", "synthesis_axis", "dwt", "idwt", "level_weights", "weight_map",
     "es_adjoint", "es_apply", "matern_cov_apply", "matern_sample", "hs_norm_sq",
-    "tikhonov_solve", "fft_cov_apply", "fourier_multiplier", "dense",
+    "tikhonov_solve", "tikhonov_gmres", "fft_cov_apply", "fourier_multiplier", "dense",
 ]

@@ -41,6 +41,12 @@ SIGNATURES = [
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float), _fp,
                                        ctypes.c_size_t, _fp]),
     ("es_tikhonov_pcg_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int]),
+    ("es_tikhonov_gmres", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_double, ctypes.c_double, _fp, _fp, _fp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_double, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float),
+                                         _fp, ctypes.c_size_t, _fp]),
+    ("es_tikhonov_gmres_workspace_bytes", ctypes.c_size_t, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_int,
+                                                             ctypes.c_int, ctypes.c_int32]),
     ("es_fft_cov_apply", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
                                         _fp, _fp, _fp, ctypes.c_size_t, _fp]),
     ("es_fft_workspace_bytes", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),

@@ -225,8 +225,161 @@ __global__ void __launch_bounds__(kCgThreads) k_cg_final(int kind, int per, cons
   sc[inst] = c;
 }
 
+// ---- GMRES on (E_s^* K^* K + alpha I) x = E_s^* K^* p (K = diag(mask)) ----------------------
+constexpr int kGmMaxBasis = 64;  // largest restart length
+// Vectors of the basis are batch * n floats, `vs` floats apart.  Per-instance coefficients
+// (inner products, norms, least-squares solutions) are device arrays indexed inst * ld + j.
+
+// out = (sq ? m * m : m) * v
+__global__ void __launch_bounds__(kCgThreads) k_gm_mask(int64_t n, int per, int sq, const float* __restrict__ mask,
+                                                        const float* __restrict__ v, float* __restrict__ out) {
+  const Span sp = span_of(n, per);
+  for_chunk(sp, n, [&](int64_t i, int w) {
+    for (int k = 0; k < w; ++k) {
+      const float m = gld(mask + i + k);
+      gst(out + i + k, (sq ? m * m : m) * gld(v + i + k));
+    }
+  });
+}
+
+// out = a x + b y + c z (a null vector contributes nothing); partial ||out||^2 when part is given.
+// out may be one of x, y, z (each element is read, then written, by the same thread).
+__global__ void __launch_bounds__(kCgThreads) k_gm_lin3(int64_t n, int per, float a, const float* x, float b,
+                                                        const float* y, float c, const float* z, float* out,
+                                                        float* __restrict__ part) {
+  const Span sp = span_of(n, per);
+  KSum acc;
+  for_chunk(sp, n, [&](int64_t i, int w) {
+    for (int k = 0; k < w; ++k) {
+      float o = 0.f;
+      if (x) o = a * gld(x + i + k);
+      if (y) o = fmaf(b, gld(y + i + k), o);
+      if (z) o = fmaf(c, gld(z + i + k), o);
+      gst(out + i + k, o);
+      acc.add(o * o);
+    }
+  });
+  if (part) {
+    const float t = wg_sum(acc.value());
+    if (threadIdx.x == 0) gst(part + blockIdx.x, t);
+  } else {
+    (void)acc;
+  }
+}
+
+// part[j * nblk + blk] = <v_j, w> over this work-group's chunk, j < nv (w's chunk read once)
+constexpr int kGmPer = kCgChunk / kCgThreads;  // elements of a chunk per thread
+__global__ void __launch_bounds__(kCgThreads) k_gm_dots(int64_t n, int per, int nv, const float* __restrict__ V,
+                                                        int64_t vs, const float* __restrict__ w,
+                                                        float* __restrict__ part) {
+  const Span sp = span_of(n, per);
+  const int64_t base = sp.inst * n;
+  float wv[kGmPer];
+#pragma unroll
+  for (int k = 0; k < kGmPer; ++k) {
+    const int64_t i = sp.lo + threadIdx.x + (int64_t)k * kCgThreads;
+    wv[k] = i < sp.hi ? gld(w + base + i) : 0.f;
+  }
+  const int nblk = gridDim.x;
+  for (int j = 0; j < nv; ++j) {
+    const float* v = V + j * vs + base;
+    KSum acc;
+#pragma unroll
+    for (int k = 0; k < kGmPer; ++k) {
+      const int64_t i = sp.lo + threadIdx.x + (int64_t)k * kCgThreads;
+      if (i < sp.hi) acc.add(gld(v + i) * wv[k]);
+    }
+    const float t = wg_sum(acc.value());
+    if (threadIdx.x == 0) gst(part + (int64_t)j * nblk + blockIdx.x, t);
+  }
+}
+
+// dst[inst * ld + j] = sum of instance inst's `per` partials of vector j, in a fixed order;
+// grid (batch, nv)
+__global__ void __launch_bounds__(kCgThreads) k_gm_final(int per, int nblk, const float* __restrict__ part,
+                                                         float* __restrict__ dst, int ld) {
+  const int inst = blockIdx.x, j = blockIdx.y;
+  KSum acc;
+  for (int k = threadIdx.x; k < per; k += kCgThreads) acc.add(part[(int64_t)j * nblk + (int64_t)inst * per + k]);
+  const float sum = wg_sum(acc.value());
+  if (threadIdx.x == 0) dst[inst * ld + j] = sum;
+}
+
+// w -= sum_j h[inst * ld + j] v_j (j < nv); partial ||w||^2 when part is given
+__global__ void __launch_bounds__(kCgThreads) k_gm_sub(int64_t n, int per, int nv, const float* __restrict__ V,
+                                                       int64_t vs, const float* __restrict__ h, int ld,
+                                                       float* __restrict__ w, float* __restrict__ part) {
+  const Span sp = span_of(n, per);
+  const int64_t base = sp.inst * n;
+  __shared__ float hs[kGmMaxBasis + 1];
+  for (int j = threadIdx.x; j < nv; j += kCgThreads) hs[j] = h[sp.inst * ld + j];
+  __syncthreads();
+  KSum acc;
+  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += kCgThreads) {
+    float o = gld(w + base + i);
+    for (int j = 0; j < nv; ++j) o = fmaf(-hs[j], gld(V + j * vs + base + i), o);
+    gst(w + base + i, o);
+    acc.add(o * o);
+  }
+  if (part) {
+    const float t = wg_sum(acc.value());
+    if (threadIdx.x == 0) gst(part + blockIdx.x, t);
+  }
+}
+
+// v = w / sqrt(nrm2[inst]), or 0 when the norm is 0 (an exhausted or zero instance)
+__global__ void __launch_bounds__(kCgThreads) k_gm_scale(int64_t n, int per, const float* __restrict__ nrm2,
+                                                         const float* __restrict__ w, float* __restrict__ v) {
+  const Span sp = span_of(n, per);
+  const float q = nrm2[sp.inst];
+  const float sc = q > 0.f ? 1.f / sqrtf(q) : 0.f;
+  for_chunk(sp, n, [&](int64_t i, int wdt) {
+    for (int k = 0; k < wdt; ++k) gst(v + i + k, sc * gld(w + i + k));
+  });
+}
+
+// x += sum_j y[inst * ld + j] v_j (j < nv)
+__global__ void __launch_bounds__(kCgThreads) k_gm_combine(int64_t n, int per, int nv, const float* __restrict__ V,
+                                                           int64_t vs, const float* __restrict__ y, int ld,
+                                                           float* __restrict__ x) {
+  const Span sp = span_of(n, per);
+  const int64_t base = sp.inst * n;
+  __shared__ float ys[kGmMaxBasis + 1];
+  for (int j = threadIdx.x; j < nv; j += kCgThreads) ys[j] = y[sp.inst * ld + j];
+  __syncthreads();
+  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += kCgThreads) {
+    float o = gld(x + base + i);
+    for (int j = 0; j < nv; ++j) o = fmaf(ys[j], gld(V + j * vs + base + i), o);
+    gst(x + base + i, o);
+  }
+}
+
 int64_t cg_parts(int64_t n) { return (n + kCgChunk - 1) / kCgChunk; }
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct GmLayout {
+  size_t V, b, w, t, part, h1, h2, nrm, y, cov, total;
+  int64_t vs;  // floats between basis vectors
+};
+
+GmLayout gm_layout(int64_t n, int64_t batch, int m, size_t cov_bytes, int64_t per) {
+  GmLayout L;
+  const size_t vec = a256((size_t)(n * batch) * sizeof(float));
+  L.vs = (int64_t)(vec / sizeof(float));
+  L.V = 0;
+  L.b = L.V + vec * (size_t)(m + 1);
+  L.w = L.b + vec;
+  L.t = L.w + vec;
+  L.part = L.t + vec;
+  L.h1 = L.part + a256((size_t)((m + 1) * per * batch) * sizeof(float));
+  L.h2 = L.h1 + a256((size_t)(batch * (m + 1)) * sizeof(float));
+  L.nrm = L.h2 + a256((size_t)(batch * (m + 1)) * sizeof(float));
+  L.y = L.nrm + a256((size_t)batch * sizeof(float));
+  L.cov = L.y + a256((size_t)(batch * (m + 1)) * sizeof(float));
+  L.total = L.cov + cov_bytes;
+  return L;
+}
+
 
 struct CgLayout {
   size_t r, z, d, ad, part, scal, cov, total;
@@ -399,6 +552,233 @@ es_status es_tikhonov_pcg(int ndim, const int64_t* shape, int64_t batch, int ord
     return report_error(ES_EDEVICE, msg);
   }
   for (int64_t b = 0; b < batch; ++b) rel_residual[b] = host[(size_t)b].rel;
+  if (iterations) *iterations = it;
+  return ES_OK;
+}
+
+
+size_t es_tikhonov_gmres_workspace_bytes(int ndim, const int64_t* shape, int64_t batch, int order, int levels,
+                                         int32_t restart) {
+  if (batch < 1 || ndim < 1 || ndim > 3 || !shape || restart < 1 || restart > kGmMaxBasis) return 0;
+  int64_t n = 1;
+  for (int k = 0; k < ndim; ++k) n *= shape[k];
+  const size_t cov = es_workspace_bytes(ndim, shape, batch, order, levels, ES_OP_COV);
+  return gm_layout(n, batch, restart, cov, cg_parts(n)).total;
+}
+
+es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
+                            double alpha, const float* p, const float* mask, float* x, int32_t restart,
+                            int32_t max_iter, double rtol, int32_t* iterations, float* rel_residual, void* ws,
+                            size_t ws_bytes, void* stream) {
+  char msg[256];
+  if (ndim < 1 || ndim > 3 || !shape) return report_error(ES_EINVAL, "ndim must be 1..3 and shape non-NULL");
+  if (batch < 0) return report_error(ES_EINVAL, "batch must be >= 0");
+  if (!(alpha > 0) || !std::isfinite(alpha)) return report_error(ES_EINVAL, "alpha must be positive and finite");
+  if (!(rtol >= 0) || !std::isfinite(rtol)) return report_error(ES_EINVAL, "rtol must be finite and >= 0");
+  if (max_iter < 0) return report_error(ES_EINVAL, "max_iter must be >= 0");
+  if (restart < 1 || restart > kGmMaxBasis) return report_error(ES_EINVAL, "restart must be 1..64");
+  if (iterations) *iterations = 0;
+  if (batch == 0) return ES_OK;
+  if (batch > 0x7fffffffll) return report_error(ES_EINVAL, "batch too large");
+  int64_t n = 1;
+  for (int k = 0; k < ndim; ++k) {
+    if (shape[k] < 1) return report_error(ES_EINVAL, "shape entries must be positive");
+    n *= shape[k];
+  }
+  const int64_t per = cg_parts(n);
+  if (per * batch > 0x7fffffffll) return report_error(ES_EINVAL, "problem too large");
+  const size_t cov = es_workspace_bytes(ndim, shape, batch, order, levels, ES_OP_COV);
+  if (cov == 0 && levels > 1) return report_error(ES_EINVAL, "invalid operator arguments (order, levels, shape)");
+  const int m = restart;
+  const GmLayout L = gm_layout(n, batch, m, cov, per);
+  if (!p || !mask || !x || !rel_residual) return report_error(ES_EINVAL, "p, mask, x and rel_residual must be non-NULL");
+  if (((uintptr_t)p | (uintptr_t)mask | (uintptr_t)x) & 15) return report_error(ES_EINVAL, "p, mask and x must be 16-byte aligned");
+  if (!ws || ws_bytes < L.total) {
+    snprintf(msg, sizeof msg, "workspace of %zu bytes required", L.total);
+    return report_error(ES_EWORKSPACE, msg);
+  }
+  if ((uintptr_t)ws & 255) return report_error(ES_EINVAL, "workspace must be 256-byte aligned");
+  const size_t vb = (size_t)(n * batch) * sizeof(float);
+  auto ov = [](const void* a, size_t na, const void* b, size_t nb) {
+    return (const char*)a < (const char*)b + nb && (const char*)b < (const char*)a + na;
+  };
+  if (ov(x, vb, p, vb) || ov(x, vb, mask, vb) || ov(ws, L.total, x, vb) || ov(ws, L.total, p, vb) ||
+      ov(ws, L.total, mask, vb))
+    return report_error(ES_EINVAL, "x must not overlap p, mask or the workspace; the workspace must not overlap p or mask");
+  es_status st = device_check();
+  if (st != ES_OK) return st;
+
+  char* wsc = (char*)ws;
+  float* V = (float*)(wsc + L.V);
+  float* bv = (float*)(wsc + L.b);
+  float* w = (float*)(wsc + L.w);
+  float* t = (float*)(wsc + L.t);
+  float* part = (float*)(wsc + L.part);
+  float* h1 = (float*)(wsc + L.h1);
+  float* h2 = (float*)(wsc + L.h2);
+  float* nrm = (float*)(wsc + L.nrm);
+  float* yd = (float*)(wsc + L.y);
+  void* cws = cov ? (void*)(wsc + L.cov) : nullptr;
+  const int64_t vs = L.vs;
+  const int ld = m + 1;
+  const hipStream_t hs = (hipStream_t)stream;
+  const dim3 grid((unsigned)(per * batch)), blk(kCgThreads);
+  const int nblk = (int)(per * batch);
+  auto ok = [&](const char* what) -> es_status {
+    const hipError_t e = hipGetLastError();
+    if (e == hipSuccess) return ES_OK;
+    snprintf(msg, sizeof msg, "%s: %s", what, hipGetErrorString(e));
+    return report_error(ES_EDEVICE, msg);
+  };
+  auto to_host = [&](void* dst, const void* src, size_t bytes) -> es_status {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e == hipSuccess) return ES_OK;
+    snprintf(msg, sizeof msg, "GMRES coefficient read: %s", hipGetErrorString(e));
+    return report_error(ES_EDEVICE, msg);
+  };
+  // per-instance sums of `nv` partial arrays into dst[inst * ldd + j]
+  auto final_ = [&](int nv, float* dst, int ldd) -> es_status {
+    hipLaunchKernelGGL(k_gm_final, dim3((unsigned)batch, (unsigned)nv), blk, 0, hs, (int)per, nblk, part, dst, ldd);
+    return ok("GMRES reduction launch");
+  };
+  // out = A v = E_s^*(mask^2 v) + alpha v, or out = b - A v (residual)
+  auto apply_a = [&](const float* v, float* out, bool residual, float* nparts) -> es_status {
+    hipLaunchKernelGGL(k_gm_mask, grid, blk, 0, hs, n, (int)per, 1, mask, v, t);
+    es_status r = ok("GMRES mask launch");
+    if (r == ES_OK) r = matern_cov_apply(ndim, shape, batch, order, levels, s, t, out, cws, cov, stream);
+    if (r != ES_OK) return r;
+    if (residual)
+      hipLaunchKernelGGL(k_gm_lin3, grid, blk, 0, hs, n, (int)per, 1.f, (const float*)bv, -1.f, (const float*)out,
+                         (float)-alpha, v, out, nparts);
+    else
+      hipLaunchKernelGGL(k_gm_lin3, grid, blk, 0, hs, n, (int)per, 1.f, (const float*)out, (float)alpha, v,
+                         0.f, (const float*)nullptr, out, nparts);
+    return ok("GMRES update launch");
+  };
+  std::vector<float> hb((size_t)batch * ld), hb2((size_t)batch * ld), hn((size_t)batch);
+  std::vector<float> yh((size_t)batch * ld, 0.f);
+
+  // b = E_s^*(mask p), x = 0, v_0 = b / ||b||
+  hipLaunchKernelGGL(k_gm_mask, grid, blk, 0, hs, n, (int)per, 0, mask, p, t);
+  if ((st = ok("GMRES mask launch")) != ES_OK) return st;
+  if ((st = matern_cov_apply(ndim, shape, batch, order, levels, s, t, bv, cws, cov, stream)) != ES_OK) return st;
+  hipLaunchKernelGGL(k_gm_lin3, grid, blk, 0, hs, n, (int)per, 0.f, (const float*)nullptr, 0.f,
+                     (const float*)nullptr, 0.f, (const float*)nullptr, x, (float*)nullptr);
+  hipLaunchKernelGGL(k_gm_lin3, grid, blk, 0, hs, n, (int)per, 1.f, (const float*)bv, 0.f, (const float*)nullptr,
+                     0.f, (const float*)nullptr, w, part);
+  if ((st = ok("GMRES init launch")) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
+  hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, nrm, w, V);
+  if ((st = ok("GMRES scale launch")) != ES_OK || (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
+    return st;
+
+  // host state per instance (FP64): R (upper triangle of the rotated Hessenberg, column-major
+  // m x m), rotations, right side g, ||b||, whether it still needs steps
+  std::vector<double> R((size_t)batch * m * m), cs((size_t)batch * m), sn((size_t)batch * m), g((size_t)batch * ld);
+  std::vector<double> bn((size_t)batch), beta((size_t)batch);
+  std::vector<char> active((size_t)batch);
+  std::vector<int> kk((size_t)batch);
+  for (int64_t b = 0; b < batch; ++b) {
+    bn[b] = beta[b] = std::sqrt((double)hn[b]);
+    active[b] = bn[b] > 0 && 1.0 > rtol;
+  }
+  int it = 0;
+  auto any_active = [&]() {
+    for (char a : active)
+      if (a) return true;
+    return false;
+  };
+  while (any_active() && it < max_iter) {
+    for (int64_t b = 0; b < batch; ++b) {
+      std::fill(g.begin() + b * ld, g.begin() + (b + 1) * ld, 0.0);
+      g[b * ld] = beta[b];
+      kk[b] = 0;
+    }
+    int K = 0;  // Arnoldi steps of this cycle
+    while (K < m && it < max_iter && any_active()) {
+      const int k = K;
+      const float* vk = V + k * vs;
+      if ((st = apply_a(vk, w, false, nullptr)) != ES_OK) return st;
+      // classical Gram-Schmidt against v_0 .. v_k, twice
+      hipLaunchKernelGGL(k_gm_dots, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)w, part);
+      if ((st = ok("GMRES inner-product launch")) != ES_OK || (st = final_(k + 1, h1, ld)) != ES_OK) return st;
+      hipLaunchKernelGGL(k_gm_sub, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)h1, ld, w,
+                         (float*)nullptr);
+      if ((st = ok("GMRES update launch")) != ES_OK) return st;
+      hipLaunchKernelGGL(k_gm_dots, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)w, part);
+      if ((st = ok("GMRES inner-product launch")) != ES_OK || (st = final_(k + 1, h2, ld)) != ES_OK) return st;
+      hipLaunchKernelGGL(k_gm_sub, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)h2, ld, w,
+                         part);
+      if ((st = ok("GMRES update launch")) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
+      hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, (const float*)nrm, (const float*)w,
+                         V + (k + 1) * vs);
+      if ((st = ok("GMRES scale launch")) != ES_OK) return st;
+      if ((st = to_host(hb.data(), h1, hb.size() * sizeof(float))) != ES_OK ||
+          (st = to_host(hb2.data(), h2, hb2.size() * sizeof(float))) != ES_OK ||
+          (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
+        return st;
+      ++it;
+      ++K;
+      for (int64_t b = 0; b < batch; ++b) {
+        if (!active[b]) continue;
+        double col[kGmMaxBasis + 1];
+        for (int j = 0; j <= k; ++j) col[j] = (double)hb[b * ld + j] + (double)hb2[b * ld + j];
+        col[k + 1] = std::sqrt((double)hn[b]);
+        double* c = cs.data() + b * m;
+        double* sv = sn.data() + b * m;
+        for (int i = 0; i < k; ++i) {  // earlier rotations
+          const double u = col[i], v = col[i + 1];
+          col[i] = c[i] * u + sv[i] * v;
+          col[i + 1] = -sv[i] * u + c[i] * v;
+        }
+        const double r = std::hypot(col[k], col[k + 1]);
+        c[k] = r > 0 ? col[k] / r : 1.0;
+        sv[k] = r > 0 ? col[k + 1] / r : 0.0;
+        col[k] = r;
+        double* gb = g.data() + b * ld;
+        gb[k + 1] = -sv[k] * gb[k];
+        gb[k] = c[k] * gb[k];
+        for (int j = 0; j <= k; ++j) R[(size_t)b * m * m + (size_t)k * m + j] = col[j];
+        kk[b] = k + 1;
+        if (!(std::fabs(gb[k + 1]) / bn[b] > rtol) || r == 0) active[b] = 0;
+      }
+    }
+    // x += V y, y = R^{-1} g over each instance's steps of this cycle
+    for (int64_t b = 0; b < batch; ++b) {
+      const int nk = kk[b];
+      const double* Rb = R.data() + (size_t)b * m * m;
+      double yv[kGmMaxBasis];
+      for (int i = nk - 1; i >= 0; --i) {
+        double v = g[b * ld + i];
+        for (int j = i + 1; j < nk; ++j) v -= Rb[(size_t)j * m + i] * yv[j];
+        yv[i] = Rb[(size_t)i * m + i] != 0 ? v / Rb[(size_t)i * m + i] : 0.0;
+      }
+      for (int j = 0; j < ld; ++j) yh[b * ld + j] = j < nk ? (float)yv[j] : 0.f;
+    }
+    hipError_t e = hipMemcpyAsync(yd, yh.data(), yh.size() * sizeof(float), hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess) e = hipStreamSynchronize(hs);
+    if (e != hipSuccess) {
+      snprintf(msg, sizeof msg, "GMRES coefficient write: %s", hipGetErrorString(e));
+      return report_error(ES_EDEVICE, msg);
+    }
+    hipLaunchKernelGGL(k_gm_combine, grid, blk, 0, hs, n, (int)per, K, (const float*)V, vs, (const float*)yd, ld, x);
+    if ((st = ok("GMRES combine launch")) != ES_OK) return st;
+    if (!any_active() || it >= max_iter) break;
+    // restart from the true residual r = b - A x: v_0 = r / ||r||
+    if ((st = apply_a(x, w, true, part)) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
+    hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, (const float*)nrm, (const float*)w, V);
+    if ((st = ok("GMRES scale launch")) != ES_OK || (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
+      return st;
+    for (int64_t b = 0; b < batch; ++b) {
+      beta[b] = std::sqrt((double)hn[b]);
+      if (active[b] && !(beta[b] / bn[b] > rtol)) active[b] = 0;
+    }
+  }
+  // true relative residual of the final iterate
+  if ((st = apply_a(x, w, true, part)) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
+  if ((st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK) return st;
+  for (int64_t b = 0; b < batch; ++b)
+    rel_residual[b] = bn[b] > 0 ? (float)(std::sqrt((double)hn[b]) / bn[b]) : 0.f;
   if (iterations) *iterations = it;
   return ES_OK;
 }

@@ -78,3 +78,58 @@ def test_tikhonov_pcg_fused_steps_match_separate_kernels():
         assert rel_l2(xf[b], ref) <= SOLVE_TOL
         assert rel_l2(xs[b], ref) <= SOLVE_TOL
         assert rel_l2(xf[b], xs[b]) <= SOLVE_TOL
+
+
+# GMRES iterates: FP32 operator applications (~1e-6 relative) through 15 Arnoldi steps on systems
+# with eigenvalues in about [alpha, 1 + alpha] (condition <= 11 here); 1e-4 covers both.
+GMRES_TOL = 1e-4
+
+
+@pytest.mark.parametrize("shape,ndim,order,levels,s,alpha", [((2, 64, 96), 2, 4, 4, 1.5, 0.1),
+                                                             ((2, 16, 24, 32), 3, 2, 3, 1.0, 0.2),
+                                                             ((1, 128, 128), 2, 8, 5, 1.5, 0.1)])
+def test_tikhonov_gmres_iterates_match_oracle(shape, ndim, order, levels, s, alpha):
+    """15 GMRES steps (the paper's count, Sec. 5) on (E_s^* K^* K + alpha I) x = E_s^* K^* p with a
+    non-binary mask: the GPU's 15th iterate against the FP64 oracle's."""
+    from paper_2507_02401_amd.solver import tikhonov_gmres
+    gen = np.random.default_rng(17)
+    truth = np.cumsum(gen.standard_normal(shape), axis=-1) / 4.0
+    mask = gen.random(shape).astype(np.float32)
+    p = (truth + 0.05 * gen.standard_normal(shape)).astype(np.float32)
+    say("tikhonov_gmres 15 steps", shape, order, levels, s, alpha)
+    x, info = tikhonov_gmres(torch.from_numpy(p).cuda(), torch.from_numpy(mask).cuda(), ndim, order, levels, s, alpha,
+                             iters=15, restart=15, rtol=0.0)
+    assert info["iterations"] == 15
+    xs = x.cpu().numpy().reshape((-1,) + shape[len(shape) - ndim:])
+    ps, ms = p.reshape(xs.shape), mask.reshape(xs.shape)
+    for b in range(xs.shape[0]):
+        ref = oracle.tikhonov_gmres(ps[b].astype(np.float64), ms[b].astype(np.float64), order, levels, s, alpha, 15)
+        err = rel_l2(xs[b], ref)
+        assert err <= GMRES_TOL, (b, err)
+
+
+@pytest.mark.parametrize("restart", [30, 6])
+def test_tikhonov_gmres_converges_to_the_solution(restart):
+    """Restarted GMRES to a residual of 1e-6 reaches the FP64 solution (for a 0/1 mask the CG
+    oracle's); the reported residual is the true one of the returned iterate; an instance with an
+    empty mask stays at x = 0 with residual 0; two runs give the same bits."""
+    from paper_2507_02401_amd.solver import tikhonov_gmres
+    gen = np.random.default_rng(23)
+    shape = (3, 96, 80)
+    truth = np.cumsum(np.cumsum(gen.standard_normal(shape), axis=-1), axis=-2) / 8.0
+    mask = (gen.random(shape) < 0.3).astype(np.float32)
+    mask[1] = 0.0
+    p = (truth + 0.05 * gen.standard_normal(shape)).astype(np.float32)
+    pt, mt = torch.from_numpy(p).cuda(), torch.from_numpy(mask).cuda()
+    say("tikhonov_gmres converge, restart", restart)
+    x, info = tikhonov_gmres(pt, mt, 2, 4, 4, 1.5, 0.1, iters=600, restart=restart, rtol=1e-6)
+    x2, info2 = tikhonov_gmres(pt, mt, 2, 4, 4, 1.5, 0.1, iters=600, restart=restart, rtol=1e-6)
+    assert torch.equal(x, x2) and info["iterations"] == info2["iterations"]
+    assert info["iterations"] < 600
+    rel = info["rel_residual"]
+    assert float(rel[1]) == 0.0 and float(x[1].abs().max()) == 0.0
+    assert float(rel[0]) <= 1e-5 and float(rel[2]) <= 1e-5
+    xs = x.cpu().numpy()
+    for b in (0, 2):
+        ref = oracle.tikhonov_solve(p[b].astype(np.float64), mask[b].astype(np.float64), 4, 4, 1.5, 0.1)
+        assert rel_l2(xs[b], ref) <= SOLVE_TOL, b

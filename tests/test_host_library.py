@@ -193,6 +193,32 @@ def test_tikhonov_pcg_validates_on_host(lib):
     assert call(x=P + 64) == _lib.ES_EINVAL            # x overlaps p
 
 
+def test_tikhonov_gmres_validates_on_host(lib):
+    """The GMRES entry point refuses bad arguments before any device call; its workspace holds the
+    basis (restart + 1 vectors) and three more vectors."""
+    shp = _lib.shape_arg((64, 64))
+    need = lib.es_tikhonov_gmres_workspace_bytes(2, shp, 2, 4, 3, 15)
+    assert need >= (15 + 4) * 2 * 64 * 64 * 4
+    assert lib.es_tikhonov_gmres_workspace_bytes(2, shp, 2, 4, 3, 30) > need
+    assert lib.es_tikhonov_gmres_workspace_bytes(2, shp, 2, 4, 3, 0) == 0
+    assert lib.es_tikhonov_gmres_workspace_bytes(2, shp, 2, 4, 3, 65) == 0
+    rel = (ctypes.c_float * 2)()
+    its = ctypes.c_int32()
+    P, M, X, WS = 1 << 20, 1 << 24, 1 << 28, 1 << 32
+    def call(alpha=0.1, rtol=1e-6, max_iter=10, restart=15, ws=WS, ws_bytes=need, x=X):
+        return lib.es_tikhonov_gmres(2, shp, 2, 4, 3, 1.0, alpha, P, M, x, restart, max_iter, rtol, ctypes.byref(its),
+                                     rel, ws, ws_bytes, None)
+    assert call(alpha=0.0) == _lib.ES_EINVAL
+    assert call(alpha=float("inf")) == _lib.ES_EINVAL
+    assert call(rtol=-1.0) == _lib.ES_EINVAL
+    assert call(max_iter=-1) == _lib.ES_EINVAL
+    assert call(restart=0) == _lib.ES_EINVAL and b"restart" in lib.es_last_error()
+    assert call(restart=65) == _lib.ES_EINVAL
+    assert call(ws_bytes=need - 1) == _lib.ES_EWORKSPACE
+    assert call(ws=WS + 16) == _lib.ES_EINVAL          # workspace alignment
+    assert call(x=P + 64) == _lib.ES_EINVAL            # x overlaps p
+
+
 def test_every_library_knob_is_created_before_device_use():
     """The test session creates every environment knob the library reads before the first device
     call (tests switch them by replacing values only)."""

@@ -191,3 +191,57 @@ def test_tikhonov_solve_matches_dense_direct_solve(shape, order, levels, s, alph
         return 0.5 * np.sum((mask * v - p) ** 2) + 0.5 * alpha * oracle.hs_norm_sq(v, order, levels, s)
     for k in range(3):
         assert J(x) < J(x + 1e-3 * gen.standard_normal(shape))
+
+
+def _gmres_system(shape, order, levels, s, alpha, seed, binary):
+    gen = np.random.default_rng(seed)
+    p = gen.standard_normal(shape)
+    mask = (gen.random(shape) < 0.4).astype(np.float64) if binary else gen.random(shape)
+    E = operator_matrices(shape, order, levels, s)[2]  # W^T D_{2s} W, dense
+    A = E @ np.diag((mask * mask).ravel()) + alpha * np.eye(E.shape[0])
+    b = E @ (mask * p).ravel()
+    return p, mask, A, b
+
+
+@pytest.mark.parametrize("shape,order,levels,s,alpha", [((16, 16), 4, 3, 1.5, 0.05), ((8, 8, 4), 2, 2, 1.0, 0.2)])
+def test_tikhonov_gmres_iterates_are_least_residual_in_the_krylov_space(shape, order, levels, s, alpha):
+    """Each GMRES iterate x_k is the point of least residual in the Krylov space
+    K_k(E_s^* K^* K + alpha I, E_s^* K^* p) (Sec. 5 and its convergence figure), found here by brute
+    force: an orthonormal basis of the explicitly built space [b, Ab, ..., A^{k-1} b] and a dense
+    least-squares solve.  A non-binary mask makes K^* K = diag(mask^2) differ from diag(mask)."""
+    p, mask, A, b = _gmres_system(shape, order, levels, s, alpha, 3, False)
+    prev = np.inf
+    for k in range(1, 7):
+        x = oracle.tikhonov_gmres(p, mask, order, levels, s, alpha, iters=k).ravel()
+        cols = [b]
+        for _ in range(k - 1):
+            cols.append(A @ cols[-1])
+        Q = np.linalg.qr(np.stack(cols, axis=1))[0]
+        c = np.linalg.lstsq(A @ Q, b, rcond=None)[0]
+        xb = Q @ c
+        assert np.linalg.norm(x - xb) <= 1e-7 * np.linalg.norm(xb), k
+        res = np.linalg.norm(b - A @ x)
+        assert res <= prev * (1 + 1e-12)  # minimal residuals never grow with the space
+        prev = res
+
+
+def test_tikhonov_gmres_full_space_is_the_direct_solve():
+    """After as many steps as unknowns the Krylov space is the whole space: GMRES returns the dense
+    direct solution of (E_s^* K^* K + alpha I) x = E_s^* K^* p; restarted GMRES converges to it too."""
+    shape, order, levels, s, alpha = (8, 8), 2, 2, 1.0, 0.1
+    p, mask, A, b = _gmres_system(shape, order, levels, s, alpha, 4, False)
+    xd = np.linalg.solve(A, b)
+    x = oracle.tikhonov_gmres(p, mask, order, levels, s, alpha, iters=64).ravel()
+    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
+    xr = oracle.tikhonov_gmres(p, mask, order, levels, s, alpha, iters=400, restart=8).ravel()
+    assert np.linalg.norm(xr - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_tikhonov_gmres_solution_is_the_cg_solution_for_binary_masks():
+    """With a 0/1 mask (K^* K = diag(mask)) the paper's equation and the normal equations solved by
+    the CG oracle have the same solution (multiply by Gamma^2 = (E_s^*)^{-1})."""
+    shape, order, levels, s, alpha = (16, 16), 4, 3, 1.5, 0.05
+    p, mask, A, b = _gmres_system(shape, order, levels, s, alpha, 5, True)
+    xg = oracle.tikhonov_gmres(p, mask, order, levels, s, alpha, iters=600, restart=30)
+    xc = oracle.tikhonov_solve(p, mask, order, levels, s, alpha)
+    assert np.linalg.norm(xg - xc) <= 1e-8 * np.linalg.norm(xc)
