@@ -813,7 +813,21 @@ def main():
                                   "ms_per_iteration": round(1e3 * tt / its, 4),
                                   "max_rel_residual": float(info["rel_residual"].max()),
                                   "operator_applications_per_iteration": 2, "alpha": 0.05, "mask_density": 0.3}
-        del xr, msk, pdat
+        del xr
+        # the paper's own solve: GMRES, 15 iterations, on (E_s^* K^* K + alpha I) x = E_s^* K^* p
+        from paper_2507_02401_amd.solver import tikhonov_gmres
+        tikhonov_gmres(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=2, restart=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xg, ginfo = tikhonov_gmres(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=15, restart=15, rtol=0.0)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t0
+        result["tikhonov_gmres"] = {"iterations": ginfo["iterations"], "restart": 15, "ms_total": round(1e3 * tg, 3),
+                                    "ms_per_iteration": round(1e3 * tg / max(1, ginfo["iterations"]), 4),
+                                    "max_rel_residual": float(ginfo["rel_residual"].max()),
+                                    "operator_applications": ginfo["iterations"] + 2, "alpha": 0.05,
+                                    "mask_density": 0.3}
+        del xg, msk, pdat
         # Fourier form of E_s^* on the same batch (hipFFT transforms + the library's spectral pass)
         print("[bench] Fourier form", file=sys.stderr, flush=True)
         from paper_2507_02401_amd.ops import fft_workspace_bytes
