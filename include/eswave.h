@@ -67,7 +67,7 @@ typedef enum {
   ES_EWORKSPACE = 2,   /* workspace missing or smaller than es_workspace_bytes()                     */
   ES_EUNSUPPORTED = 3, /* valid request this build cannot run (e.g. no gfx950 device)               */
   ES_EDEVICE = 4,      /* HIP runtime error; message from hipGetErrorString in es_last_error()      */
-  ES_ENOMEM = 5        /* host or device allocation failed (plan API only)                          */
+  ES_ENOMEM = 5        /* host or device allocation failed (plans, FFT plans, GMRES host state)     */
 } es_status;
 
 typedef enum { ES_OP_ADJOINT = 0, ES_OP_APPLY = 1, ES_OP_COV = 2, ES_OP_SAMPLE = 3 } es_op;
@@ -185,7 +185,8 @@ size_t es_tikhonov_pcg_workspace_bytes(int ndim, const int64_t* shape, int64_t b
  *                (restart + 1 vectors), the right side, two work vectors, partial sums, the
  *                per-instance coefficients and the operator's workspace.
  * Other arguments as for matern_cov_apply.  Errors: ES_EINVAL (arguments, alpha <= 0, rtol < 0,
- * max_iter < 0, restart outside 1..64), ES_EWORKSPACE, ES_EUNSUPPORTED, ES_EDEVICE.  Synchronous on
+ * max_iter < 0, restart outside 1..64), ES_EWORKSPACE, ES_ENOMEM (host memory for the per-instance
+ * least-squares state), ES_EUNSUPPORTED, ES_EDEVICE.  Synchronous on
  * return. */
 es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int order, int levels, double s,
                             double alpha, const float* p, const float* mask, float* x, int32_t restart,

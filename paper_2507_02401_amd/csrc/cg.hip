@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <new>
 #include <vector>
 
 #include "../../include/eswave.h"
@@ -656,8 +657,29 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
                          0.f, (const float*)nullptr, out, nparts);
     return ok("GMRES update launch");
   };
-  std::vector<float> hb((size_t)batch * ld), hb2((size_t)batch * ld), hn((size_t)batch);
-  std::vector<float> yh((size_t)batch * ld, 0.f);
+  // host copies of the coefficients and the FP64 least-squares state per instance: R (upper
+  // triangle of the rotated Hessenberg matrix, column-major m x m), rotations, right side g,
+  // ||b||, the current residual norm, whether the instance still takes steps, its steps this cycle
+  std::vector<float> hb, hb2, hn, yh;
+  std::vector<double> R, cs, sn, g, bn, beta;
+  std::vector<char> active;
+  std::vector<int> kk;
+  try {
+    hb.resize((size_t)batch * ld);
+    hb2.resize((size_t)batch * ld);
+    hn.resize((size_t)batch);
+    yh.assign((size_t)batch * ld, 0.f);
+    R.resize((size_t)batch * m * m);
+    cs.resize((size_t)batch * m);
+    sn.resize((size_t)batch * m);
+    g.resize((size_t)batch * ld);
+    bn.resize((size_t)batch);
+    beta.resize((size_t)batch);
+    active.resize((size_t)batch);
+    kk.resize((size_t)batch);
+  } catch (const std::bad_alloc&) {
+    return report_error(ES_ENOMEM, "host memory for the GMRES coefficients of every instance");
+  }
 
   // b = E_s^*(mask p), x = 0, v_0 = b / ||b||
   hipLaunchKernelGGL(k_gm_mask, grid, blk, 0, hs, n, (int)per, 0, mask, p, t);
@@ -672,12 +694,6 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
   if ((st = ok("GMRES scale launch")) != ES_OK || (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
     return st;
 
-  // host state per instance (FP64): R (upper triangle of the rotated Hessenberg, column-major
-  // m x m), rotations, right side g, ||b||, whether it still needs steps
-  std::vector<double> R((size_t)batch * m * m), cs((size_t)batch * m), sn((size_t)batch * m), g((size_t)batch * ld);
-  std::vector<double> bn((size_t)batch), beta((size_t)batch);
-  std::vector<char> active((size_t)batch);
-  std::vector<int> kk((size_t)batch);
   for (int64_t b = 0; b < batch; ++b) {
     bn[b] = beta[b] = std::sqrt((double)hn[b]);
     active[b] = bn[b] > 0 && 1.0 > rtol;
