@@ -167,9 +167,10 @@ size_t es_tikhonov_pcg_workspace_bytes(int ndim, const int64_t* shape, int64_t b
  *     (E_s^* K^* K + alpha I) x = E_s^* K^* p,   K = diag(mask),  E_s^* = W^T D_{2s} W,
  * by restarted GMRES from x = 0.  E_s^* is matern_cov_apply(s); the system is not symmetric.  For a
  * 0/1 mask its solution is that of es_tikhonov_pcg.  Arnoldi step: one operator application, then
- * classical Gram-Schmidt against the basis with one reorthogonalisation pass (two passes of inner
- * products over the basis, each followed by one update pass), all on the device (FP32 vectors,
- * compensated FP32 inner products reduced per instance in a fixed order: deterministic).  The host
+ * classical Gram-Schmidt with one reorthogonalisation pass, the second pass written through the
+ * basis's Gram matrix: one pass of inner products over the basis (with the new vector and with the
+ * newest basis vector), coefficients c = 2h - G h, one update pass; all on the device (FP32
+ * vectors, compensated FP32 inner products reduced per instance in a fixed order: deterministic).  The host
  * reads the new Hessenberg column after every step (synchronising `stream`) and keeps the
  * Hessenberg matrix, its Givens rotations and the least-squares solution in FP64.  An instance
  * stops contributing once its residual estimate |g_{k+1}| / ||E_s^* K^* p|| <= rtol; after every

@@ -268,30 +268,64 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_lin3(int64_t n, int per, floa
   }
 }
 
-// part[j * nblk + blk] = <v_j, w> over this work-group's chunk, j < nv (w's chunk read once)
+// Over this work-group's chunk, for j < nv: part[j * nblk + blk] = <v_j, w> and
+// part[(nv + j) * nblk + blk] = <v_j, u> (u = v_{nv-1}, the newest basis vector: the new column of
+// the basis's Gram matrix).  The chunks of w and u are read once, into registers.
 constexpr int kGmPer = kCgChunk / kCgThreads;  // elements of a chunk per thread
 __global__ void __launch_bounds__(kCgThreads) k_gm_dots(int64_t n, int per, int nv, const float* __restrict__ V,
                                                         int64_t vs, const float* __restrict__ w,
                                                         float* __restrict__ part) {
   const Span sp = span_of(n, per);
   const int64_t base = sp.inst * n;
-  float wv[kGmPer];
+  const float* u = V + (int64_t)(nv - 1) * vs + base;
+  float wv[kGmPer], uv[kGmPer];
 #pragma unroll
   for (int k = 0; k < kGmPer; ++k) {
     const int64_t i = sp.lo + threadIdx.x + (int64_t)k * kCgThreads;
     wv[k] = i < sp.hi ? gld(w + base + i) : 0.f;
+    uv[k] = i < sp.hi ? gld(u + i) : 0.f;
   }
   const int nblk = gridDim.x;
   for (int j = 0; j < nv; ++j) {
     const float* v = V + j * vs + base;
-    KSum acc;
+    KSum aw, au;
 #pragma unroll
     for (int k = 0; k < kGmPer; ++k) {
       const int64_t i = sp.lo + threadIdx.x + (int64_t)k * kCgThreads;
-      if (i < sp.hi) acc.add(gld(v + i) * wv[k]);
+      if (i < sp.hi) {
+        const float x = gld(v + i);
+        aw.add(x * wv[k]);
+        au.add(x * uv[k]);
+      }
     }
-    const float t = wg_sum(acc.value());
-    if (threadIdx.x == 0) gst(part + (int64_t)j * nblk + blockIdx.x, t);
+    const float tw = wg_sum(aw.value());
+    const float tu = wg_sum(au.value());
+    if (threadIdx.x == 0) {
+      gst(part + (int64_t)j * nblk + blockIdx.x, tw);
+      gst(part + (int64_t)(nv + j) * nblk + blockIdx.x, tu);
+    }
+  }
+}
+
+// Coefficients of step k (one work-group of 64 threads per instance): the new Gram column
+// G[j][k] = G[k][j] = <v_j, v_k> enters the instance's (m+1) x (m+1) Gram matrix, and
+// c = 2 h - G h (j, i <= k) with h = V^T w: the two classical Gram-Schmidt passes of CGS2, the
+// second written through the Gram matrix (exact when the first subtraction is).
+__global__ void __launch_bounds__(64) k_gm_coef(int k, const float* __restrict__ hg, int ldg, float* __restrict__ G,
+                                                int ldG, float* __restrict__ c, int ldc) {
+  const int inst = blockIdx.x, j = threadIdx.x;
+  const float* h = hg + inst * ldg;        // h[0..k], then the Gram column [k+1 .. 2k+1]
+  float* Gi = G + (int64_t)inst * ldG * ldG;
+  if (j <= k) {
+    const float gj = h[k + 1 + j];
+    Gi[j * ldG + k] = gj;
+    Gi[k * ldG + j] = gj;
+  }
+  __syncthreads();
+  if (j <= k) {
+    float acc = 0.f;
+    for (int i = 0; i <= k; ++i) acc = fmaf(Gi[j * ldG + i], h[i], acc);
+    c[inst * ldc + j] = 2.f * h[j] - acc;
   }
 }
 
@@ -359,7 +393,7 @@ int64_t cg_parts(int64_t n) { return (n + kCgChunk - 1) / kCgChunk; }
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct GmLayout {
-  size_t V, b, w, t, part, h1, h2, nrm, y, cov, total;
+  size_t V, b, w, t, part, hg, c, G, nrm, y, cov, total;
   int64_t vs;  // floats between basis vectors
 };
 
@@ -372,9 +406,10 @@ GmLayout gm_layout(int64_t n, int64_t batch, int m, size_t cov_bytes, int64_t pe
   L.w = L.b + vec;
   L.t = L.w + vec;
   L.part = L.t + vec;
-  L.h1 = L.part + a256((size_t)((m + 1) * per * batch) * sizeof(float));
-  L.h2 = L.h1 + a256((size_t)(batch * (m + 1)) * sizeof(float));
-  L.nrm = L.h2 + a256((size_t)(batch * (m + 1)) * sizeof(float));
+  L.hg = L.part + a256((size_t)(2 * (m + 1) * per * batch) * sizeof(float));
+  L.c = L.hg + a256((size_t)(batch * 2 * (m + 1)) * sizeof(float));
+  L.G = L.c + a256((size_t)(batch * (m + 1)) * sizeof(float));
+  L.nrm = L.G + a256((size_t)(batch * (m + 1) * (m + 1)) * sizeof(float));
   L.y = L.nrm + a256((size_t)batch * sizeof(float));
   L.cov = L.y + a256((size_t)(batch * (m + 1)) * sizeof(float));
   L.total = L.cov + cov_bytes;
@@ -615,8 +650,9 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
   float* w = (float*)(wsc + L.w);
   float* t = (float*)(wsc + L.t);
   float* part = (float*)(wsc + L.part);
-  float* h1 = (float*)(wsc + L.h1);
-  float* h2 = (float*)(wsc + L.h2);
+  float* hg = (float*)(wsc + L.hg);
+  float* cd = (float*)(wsc + L.c);
+  float* Gd = (float*)(wsc + L.G);
   float* nrm = (float*)(wsc + L.nrm);
   float* yd = (float*)(wsc + L.y);
   void* cws = cov ? (void*)(wsc + L.cov) : nullptr;
@@ -660,13 +696,12 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
   // host copies of the coefficients and the FP64 least-squares state per instance: R (upper
   // triangle of the rotated Hessenberg matrix, column-major m x m), rotations, right side g,
   // ||b||, the current residual norm, whether the instance still takes steps, its steps this cycle
-  std::vector<float> hb, hb2, hn, yh;
+  std::vector<float> hb, hn, yh;
   std::vector<double> R, cs, sn, g, bn, beta;
   std::vector<char> active;
   std::vector<int> kk;
   try {
     hb.resize((size_t)batch * ld);
-    hb2.resize((size_t)batch * ld);
     hn.resize((size_t)batch);
     yh.assign((size_t)batch * ld, 0.f);
     R.resize((size_t)batch * m * m);
@@ -715,22 +750,20 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
       const int k = K;
       const float* vk = V + k * vs;
       if ((st = apply_a(vk, w, false, nullptr)) != ES_OK) return st;
-      // classical Gram-Schmidt against v_0 .. v_k, twice
+      // Gram-Schmidt against v_0 .. v_k: one pass of inner products (with w and with v_k), the
+      // CGS2 coefficients from the Gram matrix, one update pass
       hipLaunchKernelGGL(k_gm_dots, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)w, part);
-      if ((st = ok("GMRES inner-product launch")) != ES_OK || (st = final_(k + 1, h1, ld)) != ES_OK) return st;
-      hipLaunchKernelGGL(k_gm_sub, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)h1, ld, w,
-                         (float*)nullptr);
-      if ((st = ok("GMRES update launch")) != ES_OK) return st;
-      hipLaunchKernelGGL(k_gm_dots, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)w, part);
-      if ((st = ok("GMRES inner-product launch")) != ES_OK || (st = final_(k + 1, h2, ld)) != ES_OK) return st;
-      hipLaunchKernelGGL(k_gm_sub, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)h2, ld, w,
+      if ((st = ok("GMRES inner-product launch")) != ES_OK || (st = final_(2 * (k + 1), hg, 2 * ld)) != ES_OK) return st;
+      hipLaunchKernelGGL(k_gm_coef, dim3((unsigned)batch), dim3(64), 0, hs, k, (const float*)hg, 2 * ld, Gd, ld, cd,
+                         ld);
+      if ((st = ok("GMRES coefficient launch")) != ES_OK) return st;
+      hipLaunchKernelGGL(k_gm_sub, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)cd, ld, w,
                          part);
       if ((st = ok("GMRES update launch")) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
       hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, (const float*)nrm, (const float*)w,
                          V + (k + 1) * vs);
       if ((st = ok("GMRES scale launch")) != ES_OK) return st;
-      if ((st = to_host(hb.data(), h1, hb.size() * sizeof(float))) != ES_OK ||
-          (st = to_host(hb2.data(), h2, hb2.size() * sizeof(float))) != ES_OK ||
+      if ((st = to_host(hb.data(), cd, hb.size() * sizeof(float))) != ES_OK ||
           (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
         return st;
       ++it;
@@ -738,7 +771,7 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
       for (int64_t b = 0; b < batch; ++b) {
         if (!active[b]) continue;
         double col[kGmMaxBasis + 1];
-        for (int j = 0; j <= k; ++j) col[j] = (double)hb[b * ld + j] + (double)hb2[b * ld + j];
+        for (int j = 0; j <= k; ++j) col[j] = (double)hb[b * ld + j];
         col[k + 1] = std::sqrt((double)hn[b]);
         double* c = cs.data() + b * m;
         double* sv = sn.data() + b * m;
