@@ -57,6 +57,25 @@ DEVI float wg_sum(float v) {
   return t;
 }
 
+// Sums of two values per thread over the work-group, pairwise (fixed order); thread 0 gets them.
+DEVI float2 wg_sum2(float v, float u) {
+  __shared__ float2 part2[kCgThreads / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    v += __shfl_down(v, o, 64);
+    u += __shfl_down(u, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) part2[w] = make_float2(v, u);
+  __syncthreads();
+  float2 t = make_float2(0.f, 0.f);
+  if (threadIdx.x == 0)
+    t = make_float2((part2[0].x + part2[1].x) + (part2[2].x + part2[3].x),
+                    (part2[0].y + part2[1].y) + (part2[2].y + part2[3].y));
+  __syncthreads();
+  return t;
+}
+
 // Work-group -> (instance, chunk) of the element-wise kernels.
 struct Span {
   int64_t inst, lo, hi;  // elements [lo, hi) of instance inst
@@ -236,9 +255,14 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_mask(int64_t n, int per, int 
                                                         const float* __restrict__ v, float* __restrict__ out) {
   const Span sp = span_of(n, per);
   for_chunk(sp, n, [&](int64_t i, int w) {
-    for (int k = 0; k < w; ++k) {
-      const float m = gld(mask + i + k);
-      gst(out + i + k, (sq ? m * m : m) * gld(v + i + k));
+    if (w == 4) {
+      float4 m = gld4(mask + i);
+      const float4 x = gld4(v + i);
+      if (sq) m = make_float4(m.x * m.x, m.y * m.y, m.z * m.z, m.w * m.w);
+      gst4(out + i, make_float4(m.x * x.x, m.y * x.y, m.z * x.z, m.w * x.w));
+    } else {
+      const float m = gld(mask + i);
+      gst(out + i, (sq ? m * m : m) * gld(v + i));
     }
   });
 }
@@ -250,13 +274,20 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_lin3(int64_t n, int per, floa
                                                         float* __restrict__ part) {
   const Span sp = span_of(n, per);
   KSum acc;
+  auto l4 = [](const float* q, int64_t i) { return q ? gld4(q + i) : make_float4(0.f, 0.f, 0.f, 0.f); };
   for_chunk(sp, n, [&](int64_t i, int w) {
-    for (int k = 0; k < w; ++k) {
-      float o = 0.f;
-      if (x) o = a * gld(x + i + k);
-      if (y) o = fmaf(b, gld(y + i + k), o);
-      if (z) o = fmaf(c, gld(z + i + k), o);
-      gst(out + i + k, o);
+    if (w == 4) {  // every vector's three loads issued before the arithmetic
+      const float4 xv = l4(x, i), yv = l4(y, i), zv = l4(z, i);
+      const float4 o = make_float4(fmaf(c, zv.x, fmaf(b, yv.x, a * xv.x)), fmaf(c, zv.y, fmaf(b, yv.y, a * xv.y)),
+                                   fmaf(c, zv.z, fmaf(b, yv.z, a * xv.z)), fmaf(c, zv.w, fmaf(b, yv.w, a * xv.w)));
+      gst4(out + i, o);
+      acc.add(o.x * o.x);
+      acc.add(o.y * o.y);
+      acc.add(o.z * o.z);
+      acc.add(o.w * o.w);
+    } else {
+      const float o = fmaf(c, z ? gld(z + i) : 0.f, fmaf(b, y ? gld(y + i) : 0.f, x ? a * gld(x + i) : 0.f));
+      gst(out + i, o);
       acc.add(o * o);
     }
   });
@@ -270,40 +301,90 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_lin3(int64_t n, int per, floa
 
 // Over this work-group's chunk, for j < nv: part[j * nblk + blk] = <v_j, w> and
 // part[(nv + j) * nblk + blk] = <v_j, u> (u = v_{nv-1}, the newest basis vector: the new column of
-// the basis's Gram matrix).  The chunks of w and u are read once, into registers.
+// the basis's Gram matrix).  The chunks of w and u are read once, into registers (16-byte loads
+// when the instance size is a multiple of 4); each product is summed within the wave per basis
+// vector and across the four waves, in a fixed order, once at the end.
 constexpr int kGmPer = kCgChunk / kCgThreads;  // elements of a chunk per thread
 __global__ void __launch_bounds__(kCgThreads) k_gm_dots(int64_t n, int per, int nv, const float* __restrict__ V,
                                                         int64_t vs, const float* __restrict__ w,
                                                         float* __restrict__ part) {
+  __shared__ float2 wp[kCgThreads / 64][kGmMaxBasis + 1];
   const Span sp = span_of(n, per);
   const int64_t base = sp.inst * n;
   const float* u = V + (int64_t)(nv - 1) * vs + base;
-  float wv[kGmPer], uv[kGmPer];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto wave_store = [&](int j, KSum& aw, KSum& au) {
+    float x = aw.value(), y = au.value();
 #pragma unroll
-  for (int k = 0; k < kGmPer; ++k) {
-    const int64_t i = sp.lo + threadIdx.x + (int64_t)k * kCgThreads;
-    wv[k] = i < sp.hi ? gld(w + base + i) : 0.f;
-    uv[k] = i < sp.hi ? gld(u + i) : 0.f;
-  }
-  const int nblk = gridDim.x;
-  for (int j = 0; j < nv; ++j) {
-    const float* v = V + j * vs + base;
-    KSum aw, au;
+    for (int o = 32; o > 0; o >>= 1) {
+      x += __shfl_down(x, o, 64);
+      y += __shfl_down(y, o, 64);
+    }
+    if (lane == 0) wp[wave][j] = make_float2(x, y);
+  };
+  if ((n & 3) == 0) {
+    constexpr int G = kGmPer / 4;  // float4 groups per thread
+    float4 wv[G], uv[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int64_t i = sp.lo + 4 * threadIdx.x + (int64_t)g * 4 * kCgThreads;
+      const bool in = i < sp.hi;
+      wv[g] = in ? gld4(w + base + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+      uv[g] = in ? gld4(u + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    for (int j = 0; j < nv; ++j) {
+      const float* v = V + j * vs + base;
+      float4 xv[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        const int64_t i = sp.lo + 4 * threadIdx.x + (int64_t)g * 4 * kCgThreads;
+        xv[g] = i < sp.hi ? gld4(v + i) : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      KSum aw, au;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        aw.add(xv[g].x * wv[g].x);
+        aw.add(xv[g].y * wv[g].y);
+        aw.add(xv[g].z * wv[g].z);
+        aw.add(xv[g].w * wv[g].w);
+        au.add(xv[g].x * uv[g].x);
+        au.add(xv[g].y * uv[g].y);
+        au.add(xv[g].z * uv[g].z);
+        au.add(xv[g].w * uv[g].w);
+      }
+      wave_store(j, aw, au);
+    }
+  } else {
+    float wv[kGmPer], uv[kGmPer];
 #pragma unroll
     for (int k = 0; k < kGmPer; ++k) {
       const int64_t i = sp.lo + threadIdx.x + (int64_t)k * kCgThreads;
-      if (i < sp.hi) {
-        const float x = gld(v + i);
-        aw.add(x * wv[k]);
-        au.add(x * uv[k]);
+      wv[k] = i < sp.hi ? gld(w + base + i) : 0.f;
+      uv[k] = i < sp.hi ? gld(u + i) : 0.f;
+    }
+    for (int j = 0; j < nv; ++j) {
+      const float* v = V + j * vs + base;
+      KSum aw, au;
+#pragma unroll
+      for (int k = 0; k < kGmPer; ++k) {
+        const int64_t i = sp.lo + threadIdx.x + (int64_t)k * kCgThreads;
+        if (i < sp.hi) {
+          const float x = gld(v + i);
+          aw.add(x * wv[k]);
+          au.add(x * uv[k]);
+        }
       }
+      wave_store(j, aw, au);
     }
-    const float tw = wg_sum(aw.value());
-    const float tu = wg_sum(au.value());
-    if (threadIdx.x == 0) {
-      gst(part + (int64_t)j * nblk + blockIdx.x, tw);
-      gst(part + (int64_t)(nv + j) * nblk + blockIdx.x, tu);
-    }
+  }
+  __syncthreads();
+  const int nblk = gridDim.x;
+  for (int q = threadIdx.x; q < 2 * nv; q += kCgThreads) {
+    const int j = q >> 1;
+    const bool second = q & 1;
+    auto pick = [&](int wv_) { return second ? wp[wv_][j].y : wp[wv_][j].x; };
+    const float t = (pick(0) + pick(1)) + (pick(2) + pick(3));
+    gst(part + (int64_t)(second ? nv + j : j) * nblk + blockIdx.x, t);
   }
 }
 
@@ -350,11 +431,27 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_sub(int64_t n, int per, int n
   for (int j = threadIdx.x; j < nv; j += kCgThreads) hs[j] = h[sp.inst * ld + j];
   __syncthreads();
   KSum acc;
-  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += kCgThreads) {
-    float o = gld(w + base + i);
-    for (int j = 0; j < nv; ++j) o = fmaf(-hs[j], gld(V + j * vs + base + i), o);
-    gst(w + base + i, o);
-    acc.add(o * o);
+  if ((n & 3) == 0) {
+    for (int64_t i = sp.lo + 4 * threadIdx.x; i < sp.hi; i += 4 * kCgThreads) {
+      float4 o = gld4(w + base + i);
+      for (int j = 0; j < nv; ++j) {
+        const float4 x = gld4(V + j * vs + base + i);
+        const float hj = -hs[j];
+        o = make_float4(fmaf(hj, x.x, o.x), fmaf(hj, x.y, o.y), fmaf(hj, x.z, o.z), fmaf(hj, x.w, o.w));
+      }
+      gst4(w + base + i, o);
+      acc.add(o.x * o.x);
+      acc.add(o.y * o.y);
+      acc.add(o.z * o.z);
+      acc.add(o.w * o.w);
+    }
+  } else {
+    for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += kCgThreads) {
+      float o = gld(w + base + i);
+      for (int j = 0; j < nv; ++j) o = fmaf(-hs[j], gld(V + j * vs + base + i), o);
+      gst(w + base + i, o);
+      acc.add(o * o);
+    }
   }
   if (part) {
     const float t = wg_sum(acc.value());
@@ -369,7 +466,12 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_scale(int64_t n, int per, con
   const float q = nrm2[sp.inst];
   const float sc = q > 0.f ? 1.f / sqrtf(q) : 0.f;
   for_chunk(sp, n, [&](int64_t i, int wdt) {
-    for (int k = 0; k < wdt; ++k) gst(v + i + k, sc * gld(w + i + k));
+    if (wdt == 4) {
+      const float4 x = gld4(w + i);
+      gst4(v + i, make_float4(sc * x.x, sc * x.y, sc * x.z, sc * x.w));
+    } else {
+      gst(v + i, sc * gld(w + i));
+    }
   });
 }
 
@@ -382,10 +484,21 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_combine(int64_t n, int per, i
   __shared__ float ys[kGmMaxBasis + 1];
   for (int j = threadIdx.x; j < nv; j += kCgThreads) ys[j] = y[sp.inst * ld + j];
   __syncthreads();
-  for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += kCgThreads) {
-    float o = gld(x + base + i);
-    for (int j = 0; j < nv; ++j) o = fmaf(ys[j], gld(V + j * vs + base + i), o);
-    gst(x + base + i, o);
+  if ((n & 3) == 0) {
+    for (int64_t i = sp.lo + 4 * threadIdx.x; i < sp.hi; i += 4 * kCgThreads) {
+      float4 o = gld4(x + base + i);
+      for (int j = 0; j < nv; ++j) {
+        const float4 v = gld4(V + j * vs + base + i);
+        o = make_float4(fmaf(ys[j], v.x, o.x), fmaf(ys[j], v.y, o.y), fmaf(ys[j], v.z, o.z), fmaf(ys[j], v.w, o.w));
+      }
+      gst4(x + base + i, o);
+    }
+  } else {
+    for (int64_t i = sp.lo + threadIdx.x; i < sp.hi; i += kCgThreads) {
+      float o = gld(x + base + i);
+      for (int j = 0; j < nv; ++j) o = fmaf(ys[j], gld(V + j * vs + base + i), o);
+      gst(x + base + i, o);
+    }
   }
 }
 
