@@ -259,6 +259,41 @@ def sym_volumes(es, lib, _lib, torch, dev, reps):
     return rows
 
 
+def solvers(es, torch, x, order, levels, s, dev):
+    """The two reconstruction solvers on the batch x: PCG on the normal equations to 1e-5, and the
+    paper's solve, 15 GMRES steps on (E_s^* K^* K + alpha I) x = E_s^* K^* p (seeded 30 % mask,
+    p = mask * x, alpha = 0.05)."""
+    from paper_2507_02401_amd.solver import tikhonov_gmres, tikhonov_pcg
+    out = {}
+    gmask = torch.Generator(device=dev).manual_seed(1)
+    msk = (torch.rand(x.shape, generator=gmask, device=dev) < 0.3).float()
+    pdat = msk * x
+    tikhonov_pcg(pdat, msk, 2, order, levels, s, 0.05, iters=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xr, info = tikhonov_pcg(pdat, msk, 2, order, levels, s, 0.05, iters=200, rtol=1e-5)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t0
+    its = max(1, info["iterations"])
+    out["tikhonov_pcg"] = {"iterations": info["iterations"], "ms_total": round(1e3 * tt, 3),
+                           "ms_per_iteration": round(1e3 * tt / its, 4),
+                           "max_rel_residual": float(info["rel_residual"].max()),
+                           "operator_applications_per_iteration": 2, "alpha": 0.05, "mask_density": 0.3}
+    del xr
+    tikhonov_gmres(pdat, msk, 2, order, levels, s, 0.05, iters=2, restart=2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xg, ginfo = tikhonov_gmres(pdat, msk, 2, order, levels, s, 0.05, iters=15, restart=15, rtol=0.0)
+    torch.cuda.synchronize()
+    tg = time.perf_counter() - t0
+    out["tikhonov_gmres"] = {"iterations": ginfo["iterations"], "restart": 15, "ms_total": round(1e3 * tg, 3),
+                             "ms_per_iteration": round(1e3 * tg / max(1, ginfo["iterations"]), 4),
+                             "max_rel_residual": float(ginfo["rel_residual"].max()),
+                             "operator_applications": ginfo["iterations"] + 2, "alpha": 0.05, "mask_density": 0.3}
+    del xg, msk, pdat
+    return out
+
+
 def other_workloads(args, es, inputs, torch, np):
     """The other workloads: fused path vs the plain per-instance, per-axis launches."""
     from paper_2507_02401_amd import autograd as ag
@@ -505,6 +540,9 @@ def main():
                     help="combine two rocprofv3 --pmc runs into the committed traffic file and exit")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="also run one 1 GiB device copy (known bytes) for counter calibration")
+    ap.add_argument("--solver-only", action="store_true",
+                    help="time only the two reconstruction solvers (PCG, and the paper's 15-step GMRES) on the "
+                         "same batch (for profiling) and exit")
     ap.add_argument("--sym-only", action="store_true",
                     help="time only the non-periodic transform (sym_cov_apply) on the same batch (for profiling) "
                          "and exit")
@@ -581,6 +619,10 @@ def main():
                           "eager_ms": round(1e3 * te, 3), "voxels_per_s_graph": round(nvr / tg, 1),
                           "graph_equals_eager": same}), flush=True)
         plan.close()
+        return
+
+    if args.solver_only:
+        print(json.dumps(solvers(es, torch, x, ORDER, LEVELS, S, dev)), flush=True)
         return
 
     if args.sym_only:
@@ -796,38 +838,9 @@ def main():
                                 "effective_GBps": round(4.0 * voxels / tn / 1e9, 1),
                                 "frac_of_hbm_peak_whole_op": round(4.0 * voxels / tn / 1e9 / HBM_PEAK_GBPS, 4),
                                 "unfused_ms": round(1e3 * tu, 4), "rel_err_vs_fp64_oracle_image5": None}
-        # Tikhonov reconstruction with the H^s prior: mask Bernoulli(0.3), PCG to 1e-5
-        print("[bench] Tikhonov PCG", file=sys.stderr, flush=True)
-        from paper_2507_02401_amd.solver import tikhonov_pcg
-        gmask = torch.Generator(device=dev).manual_seed(1)
-        msk = (torch.rand(x.shape, generator=gmask, device=dev) < 0.3).float()
-        pdat = msk * x
-        tikhonov_pcg(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xr, info = tikhonov_pcg(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=200, rtol=1e-5)
-        torch.cuda.synchronize()
-        tt = time.perf_counter() - t0
-        its = max(1, info["iterations"])
-        result["tikhonov_pcg"] = {"iterations": info["iterations"], "ms_total": round(1e3 * tt, 3),
-                                  "ms_per_iteration": round(1e3 * tt / its, 4),
-                                  "max_rel_residual": float(info["rel_residual"].max()),
-                                  "operator_applications_per_iteration": 2, "alpha": 0.05, "mask_density": 0.3}
-        del xr
-        # the paper's own solve: GMRES, 15 iterations, on (E_s^* K^* K + alpha I) x = E_s^* K^* p
-        from paper_2507_02401_amd.solver import tikhonov_gmres
-        tikhonov_gmres(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=2, restart=2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        xg, ginfo = tikhonov_gmres(pdat, msk, 2, ORDER, LEVELS, S, 0.05, iters=15, restart=15, rtol=0.0)
-        torch.cuda.synchronize()
-        tg = time.perf_counter() - t0
-        result["tikhonov_gmres"] = {"iterations": ginfo["iterations"], "restart": 15, "ms_total": round(1e3 * tg, 3),
-                                    "ms_per_iteration": round(1e3 * tg / max(1, ginfo["iterations"]), 4),
-                                    "max_rel_residual": float(ginfo["rel_residual"].max()),
-                                    "operator_applications": ginfo["iterations"] + 2, "alpha": 0.05,
-                                    "mask_density": 0.3}
-        del xg, msk, pdat
+        # Tikhonov reconstruction with the H^s prior: mask Bernoulli(0.3), PCG to 1e-5 and GMRES
+        print("[bench] Tikhonov PCG and GMRES", file=sys.stderr, flush=True)
+        result.update(solvers(es, torch, x, ORDER, LEVELS, S, dev))
         # Fourier form of E_s^* on the same batch (hipFFT transforms + the library's spectral pass)
         print("[bench] Fourier form", file=sys.stderr, flush=True)
         from paper_2507_02401_amd.ops import fft_workspace_bytes
