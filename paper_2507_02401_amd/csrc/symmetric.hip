@@ -414,6 +414,9 @@ struct SymTiles {
 };
 
 constexpr int kSymThreads = 256;
+// 3-D analysis tiles of up to 12 taps: 512 threads (measured faster; the 14- and 16-tap tiles keep
+// 256, their registers would not fit the 512-thread bound)
+constexpr int kSym3Threads = 512;
 
 SymTiles sym_tiles(int D, int L) {
   if (D == 1) return {{1, 1, 256}, {1, 1, 512}};
@@ -779,11 +782,11 @@ hipError_t launch_sym_level(bool up, const SymTask& t, int64_t grid, const Filte
     if (up) {
       hipLaunchKernelGGL((k_sym_up<3, L, 8, 8, 32, kSymThreads>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     } else if constexpr (L <= 4) {
-      hipLaunchKernelGGL((k_sym_down<3, L, 4, 8, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 8, 16, kSym3Threads, ZX>), dim3((unsigned)grid), dim3(kSym3Threads), 0, s, t, f);
     } else if constexpr (L <= 8) {
-      hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+      hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSym3Threads, ZX>), dim3((unsigned)grid), dim3(kSym3Threads), 0, s, t, f);
     } else if constexpr (L <= 12) {
-      hipLaunchKernelGGL((k_sym_down<3, L, 2, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
+      hipLaunchKernelGGL((k_sym_down<3, L, 2, 4, 16, kSym3Threads, ZX>), dim3((unsigned)grid), dim3(kSym3Threads), 0, s, t, f);
     } else if constexpr (L <= 14) {
       hipLaunchKernelGGL((k_sym_down<3, L, 4, 4, 16, kSymThreads, ZX>), dim3((unsigned)grid), dim3(kSymThreads), 0, s, t, f);
     } else {
