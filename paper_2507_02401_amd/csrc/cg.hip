@@ -459,18 +459,30 @@ __global__ void __launch_bounds__(kCgThreads) k_gm_sub(int64_t n, int per, int n
   }
 }
 
-// v = w / sqrt(nrm2[inst]), or 0 when the norm is 0 (an exhausted or zero instance)
+// v = w / sqrt(nrm2[inst]), or 0 when the norm is 0 (an exhausted or zero instance); with a mask,
+// also t = mask^2 v (the next operator application's input)
 __global__ void __launch_bounds__(kCgThreads) k_gm_scale(int64_t n, int per, const float* __restrict__ nrm2,
-                                                         const float* __restrict__ w, float* __restrict__ v) {
+                                                         const float* __restrict__ w, float* __restrict__ v,
+                                                         const float* __restrict__ mask, float* __restrict__ t) {
   const Span sp = span_of(n, per);
   const float q = nrm2[sp.inst];
   const float sc = q > 0.f ? 1.f / sqrtf(q) : 0.f;
   for_chunk(sp, n, [&](int64_t i, int wdt) {
     if (wdt == 4) {
       const float4 x = gld4(w + i);
-      gst4(v + i, make_float4(sc * x.x, sc * x.y, sc * x.z, sc * x.w));
+      const float4 o = make_float4(sc * x.x, sc * x.y, sc * x.z, sc * x.w);
+      gst4(v + i, o);
+      if (mask) {
+        const float4 m = gld4(mask + i);
+        gst4(t + i, make_float4(m.x * m.x * o.x, m.y * m.y * o.y, m.z * m.z * o.z, m.w * m.w * o.w));
+      }
     } else {
-      gst(v + i, sc * gld(w + i));
+      const float o = sc * gld(w + i);
+      gst(v + i, o);
+      if (mask) {
+        const float m = gld(mask + i);
+        gst(t + i, m * m * o);
+      }
     }
   });
 }
@@ -792,9 +804,10 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
     hipLaunchKernelGGL(k_gm_final, dim3((unsigned)batch, (unsigned)nv), blk, 0, hs, (int)per, nblk, part, dst, ldd);
     return ok("GMRES reduction launch");
   };
-  // out = A v = E_s^*(mask^2 v) + alpha v, or out = b - A v (residual)
-  auto apply_a = [&](const float* v, float* out, bool residual, float* nparts) -> es_status {
-    hipLaunchKernelGGL(k_gm_mask, grid, blk, 0, hs, n, (int)per, 1, mask, v, t);
+  // out = A v = E_s^*(mask^2 v) + alpha v, or out = b - A v (residual); premasked: t already holds
+  // mask^2 v (written with the basis vector)
+  auto apply_a = [&](const float* v, float* out, bool residual, float* nparts, bool premasked) -> es_status {
+    if (!premasked) hipLaunchKernelGGL(k_gm_mask, grid, blk, 0, hs, n, (int)per, 1, mask, v, t);
     es_status r = ok("GMRES mask launch");
     if (r == ES_OK) r = matern_cov_apply(ndim, shape, batch, order, levels, s, t, out, cws, cov, stream);
     if (r != ES_OK) return r;
@@ -838,7 +851,7 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
   hipLaunchKernelGGL(k_gm_lin3, grid, blk, 0, hs, n, (int)per, 1.f, (const float*)bv, 0.f, (const float*)nullptr,
                      0.f, (const float*)nullptr, w, part);
   if ((st = ok("GMRES init launch")) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
-  hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, nrm, w, V);
+  hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, nrm, w, V, mask, t);
   if ((st = ok("GMRES scale launch")) != ES_OK || (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
     return st;
 
@@ -862,7 +875,7 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
     while (K < m && it < max_iter && any_active()) {
       const int k = K;
       const float* vk = V + k * vs;
-      if ((st = apply_a(vk, w, false, nullptr)) != ES_OK) return st;
+      if ((st = apply_a(vk, w, false, nullptr, true)) != ES_OK) return st;
       // Gram-Schmidt against v_0 .. v_k: one pass of inner products (with w and with v_k), the
       // CGS2 coefficients from the Gram matrix, one update pass
       hipLaunchKernelGGL(k_gm_dots, grid, blk, 0, hs, n, (int)per, k + 1, (const float*)V, vs, (const float*)w, part);
@@ -874,7 +887,7 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
                          part);
       if ((st = ok("GMRES update launch")) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
       hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, (const float*)nrm, (const float*)w,
-                         V + (k + 1) * vs);
+                         V + (k + 1) * vs, mask, t);
       if ((st = ok("GMRES scale launch")) != ES_OK) return st;
       if ((st = to_host(hb.data(), cd, hb.size() * sizeof(float))) != ES_OK ||
           (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
@@ -927,8 +940,8 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
     if ((st = ok("GMRES combine launch")) != ES_OK) return st;
     if (!any_active() || it >= max_iter) break;
     // restart from the true residual r = b - A x: v_0 = r / ||r||
-    if ((st = apply_a(x, w, true, part)) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
-    hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, (const float*)nrm, (const float*)w, V);
+    if ((st = apply_a(x, w, true, part, false)) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
+    hipLaunchKernelGGL(k_gm_scale, grid, blk, 0, hs, n, (int)per, (const float*)nrm, (const float*)w, V, mask, t);
     if ((st = ok("GMRES scale launch")) != ES_OK || (st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK)
       return st;
     for (int64_t b = 0; b < batch; ++b) {
@@ -937,7 +950,7 @@ es_status es_tikhonov_gmres(int ndim, const int64_t* shape, int64_t batch, int o
     }
   }
   // true relative residual of the final iterate
-  if ((st = apply_a(x, w, true, part)) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
+  if ((st = apply_a(x, w, true, part, false)) != ES_OK || (st = final_(1, nrm, 1)) != ES_OK) return st;
   if ((st = to_host(hn.data(), nrm, hn.size() * sizeof(float))) != ES_OK) return st;
   for (int64_t b = 0; b < batch; ++b)
     rel_residual[b] = bn[b] > 0 ? (float)(std::sqrt((double)hn[b]) / bn[b]) : 0.f;
