@@ -1109,7 +1109,7 @@ es_status plain_instance(int op, const Geo& g, const Filter& f, const float* in,
   };
   // synthesis of packed coefficients `src` into `dst` (src is copied to dst first)
   auto synthesis = [&](const float* src, float* dst, double tau) -> es_status {
-    ES_HIP(launch_copy(src, dst, g.N(), s), "copy kernel launch");
+    ES_HIP(launch_copy_any(src, dst, g.N(), s), "copy kernel launch");
     for (int i = m; i >= 1; --i) {
       const float w = (float)wdet(g, tau, i);
       int axes[3], na = 0;
@@ -2272,7 +2272,7 @@ es_status es_plain_apply_op(int op, int ndim, const int64_t* shape, int64_t batc
     const float* ib = in + b * g.N();
     float* ob = out + b * g.N();
     if (g.m == 0) {
-      ES_HIP(launch_copy(ib, ob, g.N(), hs), "copy kernel launch");
+      ES_HIP(launch_copy_any(ib, ob, g.N(), hs), "copy kernel launch");
       continue;
     }
     st = plain_instance(op, g, f, ib, ob, (float*)ws, hs);

@@ -206,6 +206,22 @@ hipError_t launch_block_copy(const float* src, float* dst, const int b[3], const
                              const int st_dst[2], hipStream_t stream);
 hipError_t launch_copy(const float* src, float* dst, int64_t n, hipStream_t stream);
 
+// Copies n floats whatever n and the pointers' alignment: the multiple-of-4 prefix with 16-byte
+// vectors when both pointers are 16-byte aligned, everything else element by element (launch_copy
+// alone requires n % 4 == 0 and aligned pointers).
+inline hipError_t launch_copy_any(const float* src, float* dst, int64_t n, hipStream_t stream) {
+  const bool aligned = (((uintptr_t)src | (uintptr_t)dst) & 15) == 0;
+  const int64_t head = aligned ? (n & ~(int64_t)3) : 0;
+  hipError_t e = head > 0 ? launch_copy(src, dst, head, stream) : hipSuccess;
+  for (int64_t done = head; e == hipSuccess && done < n;) {
+    const int64_t c = n - done < ((int64_t)1 << 30) ? n - done : ((int64_t)1 << 30);
+    const int b[3] = {1, 1, (int)c}, z[2] = {0, 0};
+    e = launch_block_copy(src + done, dst + done, b, z, z, stream);
+    done += c;
+  }
+  return e;
+}
+
 // Squared-norm finalisation: out[b] = sum over segments k of partials[off_k + b*per_k + t],
 // t < per_k (compensated pairs, in units of pairs), in a fixed order (deterministic), rounded to
 // FP32.  kMaxNormSegs segments at most.

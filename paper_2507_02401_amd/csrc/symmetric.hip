@@ -1205,7 +1205,7 @@ es_status sym_run(int ndim, const int64_t* shape, int64_t batch, int order, int 
   hipStream_t hs = (hipStream_t)stream;
   hipError_t he;
   if (g.m <= 1) {  // every weight is 1: the identity
-    if ((he = launch_copy(x, y, batch * N, hs)) != hipSuccess) return report_error(ES_EDEVICE, hipGetErrorString(he));
+    if ((he = launch_copy_any(x, y, batch * N, hs)) != hipSuccess) return report_error(ES_EDEVICE, hipGetErrorString(he));
     return ES_OK;
   }
   for (const SymLaunch& l : seq) {

@@ -236,3 +236,17 @@ def test_sub_batch_streams(op, streams, monkeypatch):
     y = es.apply_op(op, x, 2, order, levels, s)
     torch.cuda.synchronize()
     assert torch.equal(y, ref)
+
+
+@pytest.mark.parametrize("n,levels", [(7, 0), (6, 1), (10, 1)])
+@pytest.mark.parametrize("op", range(4), ids=OP_NAMES)
+def test_plain_path_refuses_sizes_off_multiples_of_4(op, n, levels):
+    """The plain path needs instance sizes divisible by 4 and says so (ES_EUNSUPPORTED) instead of
+    running instances that would start off 16-byte boundaries."""
+    from paper_2507_02401_amd._lib import EswaveError
+    from paper_2507_02401_amd import _lib
+    x = torch.from_numpy(np.random.default_rng(n).standard_normal((3, n)).astype(np.float32)).to(DEV)
+    say("plain refuses", OP_NAMES[op], n, levels)
+    with pytest.raises(EswaveError) as err:
+        es.plain_op(op, x, 1, 2, levels, 1.0)
+    assert err.value.status == _lib.ES_EUNSUPPORTED

@@ -163,3 +163,15 @@ def test_sym_autograd_backward_is_the_transpose():
     for b in range(2):
         ref = symdwt.sym_cov_apply(w64[b], 4, 4, 1.5)
         assert rel_l2(y.grad.cpu().numpy()[b], ref) < TOL
+
+
+@pytest.mark.parametrize("shape,batch", [((9, 21, 2), 1), ((689,), 2), ((53, 3), 3), ((5,), 3)])
+def test_sym_single_level_is_an_exact_copy_at_any_size(shape, batch):
+    """levels = 1 (every weight 1) is the identity, forward and transposed, also when the batch's
+    element count is not a multiple of 4: its last elements are copied too (regression test)."""
+    x = _input(shape, batch, 11)
+    xt = torch.from_numpy(x).to(DEV)
+    say("sym single level copy", shape, batch)
+    for fn in (es.sym_cov_apply, es.sym_cov_apply_transpose):
+        y = fn(xt, len(shape), 4, 1, 1.5).cpu().numpy()
+        assert np.array_equal(y, x), fn.__name__
